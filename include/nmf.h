@@ -1,0 +1,204 @@
+/*
+ * nmf.h -- C ABI of the MI355X (gfx950) library for the alternating
+ * anti-lopsided NNLS method of L1/L2-regularised NMF, after Nguyen & Ho,
+ * arXiv:1506.08938.
+ *
+ * Notation.  The paper factors an n x m matrix of column instances as G F.
+ * This library factors V (m x n) = W (m x r) * H (r x n) and stores H as
+ * Ht = H' (n x r), so that every NNLS solution is one contiguous row:
+ *   H-update (the paper's E-step, Algorithm 1): W fixed, one NQP per column
+ *            j of V, solution = row j of Ht;
+ *   W-update (the paper's M-step): H fixed, one NQP per row i of V, solution
+ *            = row i of W.
+ * Each NQP (Section 3.2, Eq. QP; regularised form Section 3.5, Eq. L1L2NMF)
+ * is   min_x 0.5 x' Gamma x + h' x,  x >= 0,  with Gamma = A'A + 2 l2 I and
+ * h = -A'b + l1 1, A the fixed factor and b the data column.  It is solved by
+ * Algorithm 3: anti-lopsided rescale to unit diagonal, then iterations of an
+ * exact line search on the projected gradient followed by r greedy
+ * coordinate-descent steps, stopped by ||pg_k||^2 <= eps ||pg_0||^2
+ * (Section 3.4) or max_inner.
+ *
+ * Conventions for every call:
+ *  - Matrix pointers are DEVICE pointers owned by the caller; the library
+ *    never frees or reallocates them.  Matrices are row-major, indices int32
+ *    (nnz < 2^31), values float32.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Calls are stream-ordered and asynchronous, except those that return
+ *    host-side results (trace, stats, *_host arguments), which synchronise
+ *    `stream` before returning.
+ *  - Argument errors are found on the host before any launch and return
+ *    NMF_E_INVAL; HIP runtime errors return NMF_E_DEVICE; allocation failures
+ *    NMF_E_NOMEM.  nmf_last_error() gives a message for the calling thread.
+ *    Reaching max_inner is not an error.
+ *  - r must lie in [1, NMF_MAX_RANK].
+ */
+#ifndef NMF_MI355X_H
+#define NMF_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NMF_MAX_RANK 128
+
+#if defined(NMF_BUILDING_LIBRARY)
+#define NMF_API __attribute__((visibility("default")))
+#else
+#define NMF_API
+#endif
+
+typedef enum {
+    NMF_OK = 0,
+    NMF_E_INVAL = -1,
+    NMF_E_NOMEM = -2,
+    NMF_E_DEVICE = -3,
+    NMF_E_UNSUPPORTED = -4,
+    NMF_E_BUSY = -5,
+    NMF_E_NONFINITE = -6
+} nmf_status;
+
+enum { NMF_DENSE = 0, NMF_CSR = 1 };
+enum { NMF_FP32 = 0, NMF_BF16 = 1 };
+
+/* The data matrix V (Definition 1: V >= 0).  kind = NMF_DENSE: `dense` is
+ * rows x cols with leading dimension ld >= cols.  kind = NMF_CSR: rowptr
+ * (rows+1), colidx and vals (nnz) hold CSR(V), column indices ascending in
+ * each row.  t_rowptr/t_colidx/t_vals optionally hold CSR(V') (cols+1 row
+ * pointers); when NULL the library builds it on the device. */
+typedef struct {
+    int32_t kind;
+    int64_t rows, cols;
+    const float *dense;
+    int64_t ld;
+    const int32_t *rowptr;
+    const int32_t *colidx;
+    const float *vals;
+    int64_t nnz;
+    const int32_t *t_rowptr;
+    const int32_t *t_colidx;
+    const float *t_vals;
+} nmf_matrix;
+
+/* Regularisation weights of Section 3.5: J = 0.5||V - WH||^2 + l1_h sum(H)
+ * + l2_h ||H||^2 + l1_w sum(W) + l2_w ||W||^2 (the paper's mu1, mu2 on the
+ * coefficients and beta1, beta2 on the components). */
+typedef struct {
+    float l1_w, l2_w, l1_h, l2_h;
+} nmf_reg;
+
+/* Solver options.  max_inner: iteration cap of Algorithm 3 (>= 1).  eps: the
+ * accelerated stopping condition ||pg_k||^2 <= eps ||pg_0||^2, evaluated in
+ * double precision; eps = 0 stops only when the projected gradient is exactly
+ * zero, so in practice it runs max_inner iterations.  ls_guard:
+ * 1 rejects a line-search step that would raise the objective (the literal
+ * projected step of Algorithm 3 can), 0 keeps the literal step.  precision:
+ * NMF_FP32 or NMF_BF16 for the Gram and data products (the solve is always
+ * float32).  objective_every: compute the loss every s outer iterations
+ * (0 = only when a trace or stats are requested, at the end).  check_finite:
+ * scan inputs for NaN/Inf (and V for negatives) before running. */
+typedef struct {
+    int32_t max_outer;
+    int32_t max_inner;
+    double eps;
+    int32_t ls_guard;
+    int32_t precision;
+    int32_t objective_every;
+    int32_t check_finite;
+} nmf_opts;
+
+/* Statistics of a fit.  loss = 0.5||V - W H||^2, objective = J above (both
+ * accumulated in double precision), kkt_* = max |min(x, grad)| over the last
+ * half-iteration's NQPs, kbar = inner iterations / (outer iterations x (m+n))
+ * (Section 5.3). */
+typedef struct {
+    double loss, objective, kkt_w, kkt_h, kbar;
+    int64_t inner_total;
+    int32_t outer_done;
+} nmf_stats;
+
+/* Fills *o with the defaults: max_outer 50, max_inner 100, eps 1e-3,
+ * ls_guard 1, NMF_FP32, objective_every 0, check_finite 0. */
+NMF_API void nmf_default_opts(nmf_opts *o);
+
+/* Message describing the calling thread's last non-OK status. */
+NMF_API const char *nmf_last_error(void);
+
+/* ---------------------------------------------------------------- NQP batch
+ * Algorithm 3 on ncols independent NQPs sharing one Hessian (the per-column
+ * units of Section 3.2, Algorithm 2):
+ *   gram  r x r, = A'A + 2 l2 I (symmetric positive semidefinite; a
+ *         coordinate with gram_ii <= 0 is held at 0);
+ *   h     ncols x r, row j = -A'b_j + l1;
+ *   X     ncols x r, in: x0 >= 0 (warm start), out: solution;
+ *   iters optional device int32[ncols]: iterations run per column.
+ * All device pointers; X must not alias gram or h. */
+NMF_API int nnls_solve_batch(int32_t r, int64_t ncols, const float *gram, const float *h, float *X,
+                     const nmf_opts *opt, int32_t *iters, void *stream);
+
+/* ---------------------------------------------------------------- building blocks
+ * One step of a half-iteration each (Algorithm 2; Section 4.2 costs them at
+ * O(k r^2) and O(r S(mn)) / O(mnr)).  Device pointers throughout.
+ * nmf_gram:    G (r x r) = A'A + 2 l2 I for A (k x r).
+ * nmf_product: trans = 0: P (n x r) = (W'V)' with A = W (m x r);
+ *              trans = 1: P (m x r) = V Ht   with A = Ht (n x r).
+ * precision as in nmf_opts.  Sparse V with trans = 0 needs CSR(V') (the
+ * t_* arrays). */
+NMF_API int nmf_gram(const float *A, int64_t k, int32_t r, float l2, int32_t precision, float *G,
+             void *stream);
+NMF_API int nmf_product(const nmf_matrix *V, int32_t trans, int32_t r, const float *A, int32_t precision,
+                float *P, void *stream);
+
+/* ---------------------------------------------------------------- fit
+ * Algorithm 2 with the regularised NQPs of Section 3.5: opt->max_outer outer
+ * iterations, each an H-update followed by a W-update whose Gram is built
+ * from the new H.
+ *   W  m x r (device), in: start point >= 0, out: result.
+ *   Ht n x r (device), in: start point >= 0, out: result.
+ *   trace optional HOST double[max_outer + 1]: 0.5||V - WH||^2 before the
+ *         first and after each outer iteration (NaN where not computed when
+ *         objective_every > 0 skips it).
+ *   stats optional HOST nmf_stats.
+ * A plan keeps the device workspace and any derived copy of V (CSR(V'),
+ * the BF16 copy) so that repeated runs pay set-up once; nmf_fit is
+ * nmf_plan_create + nmf_plan_run + nmf_plan_destroy. */
+typedef struct nmf_plan nmf_plan;
+
+NMF_API int nmf_plan_create(const nmf_matrix *V, int32_t r, const nmf_reg *reg, const nmf_opts *opt,
+                    nmf_plan **out, void *stream);
+/* Runs `outer` outer iterations on (W, Ht); trace (host, [outer + 1]) and
+ * stats (host) are optional. */
+NMF_API int nmf_plan_run(nmf_plan *p, float *W, float *Ht, int32_t outer, double *trace, nmf_stats *stats,
+                 void *stream);
+NMF_API void nmf_plan_destroy(nmf_plan *p);
+
+NMF_API int nmf_fit(const nmf_matrix *V, int32_t r, const nmf_reg *reg, const nmf_opts *opt, float *W,
+            float *Ht, double *trace, nmf_stats *stats, void *stream);
+
+/* Loss and objective of (V, W, Ht) in double precision (host outputs). */
+NMF_API int nmf_objective(const nmf_matrix *V, int32_t r, const nmf_reg *reg, const float *W,
+                  const float *Ht, double *loss_host, double *objective_host, void *stream);
+
+/* ---------------------------------------------------------------- fold-in
+ * The E-step alone against a resident basis (Section 3.1: the new columns'
+ * coefficients F+ in the space of the learned components): for every column
+ * v of Vnew (m x c), x = argmin_{x>=0} 0.5||v - W x||^2 + l1 1'x + l2||x||^2,
+ * started from x0 = 0.
+ * nmf_basis_create copies W (m x r, device) and computes Gamma = W'W + 2 l2 I
+ * and its rescale once.  nmf_foldin takes Vnew dense (m x c) or sparse given
+ * as CSR(Vnew') (the t_* arrays, c rows over m columns) and writes
+ * Ht_new (c x r, device); iters optional device int32[c]. */
+typedef struct nmf_basis nmf_basis;
+
+NMF_API int nmf_basis_create(const float *W, int64_t m, int32_t r, float l1, float l2, const nmf_opts *opt,
+                     nmf_basis **out, void *stream);
+NMF_API int nmf_foldin(const nmf_basis *B, const nmf_matrix *Vnew, float *Ht_new, int32_t *iters,
+               void *stream);
+NMF_API void nmf_basis_destroy(nmf_basis *B);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NMF_MI355X_H */

@@ -94,8 +94,9 @@ static double quad_form_value(int r, const double *Q, const double *q, const dou
  *   x       : in = x0 (>= 0), out = solution.
  *   max_inner, eps : stop when ||pg_k||^2 <= eps ||pg_0||^2 (the accelerated
  *             condition) or after max_inner iterations; at least one
- *             iteration always runs (repeat-until).  eps = 0 runs exactly
- *             max_inner iterations.
+ *             iteration always runs (repeat-until).  eps = 0 stops only on
+ *             an exactly zero projected gradient (further iterations would
+ *             not move), otherwise it runs max_inner iterations.
  *   ls_guard: 1 = reject a line-search step that would raise f.  The paper's
  *             projected step is not monotone; 0 keeps the literal step.
  *   flags   : ORACLE_NO_* debug switches (0 for the method itself).

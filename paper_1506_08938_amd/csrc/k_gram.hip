@@ -1,0 +1,183 @@
+// Gram matrix Gamma = A'A + 2 l2 I of the fixed factor (Algorithm 2 forms it
+// once per half-iteration; Section 4.2 costs it at O(k r^2)).
+//
+// A is k x r row-major (k up to a few 10^5, r <= 128).  Phase 1: each block
+// of four waves owns a contiguous range of rows; each wave accumulates the
+// upper-triangle 32x32 tiles of A_rows' A_rows with MFMA (FP32: 32x32x2 on
+// two rows per step; BF16: 32x32x16 on sixteen rows per step, FP32
+// accumulation), the four waves are summed in LDS, and the block writes one
+// partial.  Phase 2 sums the partials in block order (deterministic) and
+// writes the symmetric r x r result with 2 l2 on the diagonal.
+//
+// Operand layout of the 32x32 MFMAs: lane l supplies row (l % 32) of the A
+// operand / column (l % 32) of the B operand for k-slice l / 32.  For the
+// Gram both operands are A[t][c*32 + l%32] from the same rows t, so one load
+// per column block feeds every tile of that block row and column.
+#include "nmf_internal.h"
+#include "kernels_common.h"
+
+namespace nmfi {
+
+constexpr int GRAM_BLOCK = 256;
+constexpr int GRAM_MAX_BLOCKS = 240;
+
+// tile index of (ta <= tb) in row-major upper-triangle order
+template <int NT>
+__device__ __forceinline__ void tile_of(int ti, int &ta, int &tb) {
+    int t = ti;
+    ta = 0;
+    while (t >= NT - ta) { t -= NT - ta; ta++; }
+    tb = ta + t;
+}
+
+template <int NT, int PREC>
+__global__ __launch_bounds__(GRAM_BLOCK) void k_gram_partial(const float *__restrict__ A, int64_t k,
+                                                             int r, int64_t rows_per_block,
+                                                             float *__restrict__ partial) {
+    constexpr int NTILE = NT * (NT + 1) / 2;
+    constexpr int RSTEP = PREC == NMF_BF16 ? 16 : 2;  // rows per MFMA
+    __shared__ float red[NTILE * 1024];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int half = lane >> 5, col = lane & 31;
+
+    const int64_t b0 = (int64_t)blockIdx.x * rows_per_block;
+    const int64_t b1 = min(k, b0 + rows_per_block);
+    // the block's rows split over its four waves in RSTEP-aligned pieces
+    const int64_t nsteps = (b1 - b0 + RSTEP - 1) / RSTEP;
+    const int64_t s0 = b0 + (nsteps * wave / 4) * RSTEP;
+    const int64_t s1 = min(b1, b0 + (nsteps * (wave + 1) / 4) * RSTEP);
+
+    f32x16 acc[NTILE];
+#pragma unroll
+    for (int i = 0; i < NTILE; i++) acc[i] = f32x16{};
+
+    if constexpr (PREC == NMF_BF16) {
+        for (int64_t t = s0; t < s1; t += 16) {
+            bf16x8 v[NT];
+#pragma unroll
+            for (int c = 0; c < NT; c++) {
+                const int a = c * 32 + col;
+                float f[8];
+#pragma unroll
+                for (int q = 0; q < 8; q++) {
+                    const int64_t row = t + half * 8 + q;
+                    f[q] = (row < s1 && a < r) ? A[row * r + a] : 0.f;
+                }
+                v[c] = pack_bf16x8(f);
+            }
+            int ti = 0;
+#pragma unroll
+            for (int ta = 0; ta < NT; ta++)
+#pragma unroll
+                for (int tb = ta; tb < NT; tb++, ti++)
+                    acc[ti] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(v[ta], v[tb], acc[ti], 0, 0, 0);
+        }
+    } else {
+        constexpr int U = 4;  // row pairs per trip: loads in flight
+        for (int64_t t = s0; t < s1; t += 2 * U) {
+            float v[U][NT];
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const int64_t row = t + 2 * u + half;
+#pragma unroll
+                for (int c = 0; c < NT; c++) {
+                    const int a = c * 32 + col;
+                    v[u][c] = (row < s1 && a < r) ? A[row * r + a] : 0.f;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                int ti = 0;
+#pragma unroll
+                for (int ta = 0; ta < NT; ta++)
+#pragma unroll
+                    for (int tb = ta; tb < NT; tb++, ti++)
+                        acc[ti] = __builtin_amdgcn_mfma_f32_32x32x2f32(v[u][ta], v[u][tb], acc[ti],
+                                                                       0, 0, 0);
+            }
+        }
+    }
+    // sum the four waves in LDS (fixed order), then one partial per block
+    for (int w = 0; w < 4; w++) {
+        if (wave == w) {
+#pragma unroll
+            for (int ti = 0; ti < NTILE; ti++)
+#pragma unroll
+                for (int q = 0; q < 16; q++) {
+                    float *p = &red[(ti * 16 + q) * 64 + lane];
+                    *p = (w == 0) ? acc[ti][q] : *p + acc[ti][q];
+                }
+        }
+        __syncthreads();
+    }
+    float *out = partial + (size_t)blockIdx.x * NTILE * 1024;
+    for (int e = threadIdx.x; e < NTILE * 1024; e += GRAM_BLOCK) out[e] = red[e];
+}
+
+template <int NT>
+__global__ __launch_bounds__(256) void k_gram_reduce(const float *__restrict__ partial, int nblocks,
+                                                     int r, float l2, float *__restrict__ G) {
+    constexpr int NTILE = NT * (NT + 1) / 2;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= NTILE * 1024) return;
+    float s = 0.f;
+    for (int b = 0; b < nblocks; b++) s += partial[(size_t)b * NTILE * 1024 + e];
+    const int ti = e >> 10, rem = e & 1023, q = rem >> 6, lane = rem & 63;
+    int ta, tb;
+    tile_of<NT>(ti, ta, tb);
+    const int i = 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3), j = lane & 31;
+    const int a = ta * 32 + i, b = tb * 32 + j;
+    if (a >= r || b >= r) return;
+    if (ta == tb && a > b) return;  // the diagonal tile writes its upper half only
+    if (a == b) s += 2.f * l2;
+    G[(size_t)a * r + b] = s;
+    G[(size_t)b * r + a] = s;
+}
+
+template <int NT, int PREC>
+static hipError_t gram_t(const float *A, int64_t k, int r, float l2, float *G, float *scratch,
+                         hipStream_t s) {
+    constexpr int NTILE = NT * (NT + 1) / 2;
+    int64_t nb = (k + 511) / 512;
+    if (nb < 1) nb = 1;
+    if (nb > GRAM_MAX_BLOCKS) nb = GRAM_MAX_BLOCKS;
+    const int step = PREC == NMF_BF16 ? 16 : 2;
+    int64_t rpb = (k + nb - 1) / nb;
+    rpb = ((rpb + 4 * step - 1) / (4 * step)) * (4 * step);
+    if (rpb < 4 * step) rpb = 4 * step;
+    nb = (k + rpb - 1) / rpb;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL((k_gram_partial<NT, PREC>), dim3((unsigned)nb), dim3(GRAM_BLOCK), 0, s, A, k,
+                       r, rpb, scratch);
+    hipLaunchKernelGGL((k_gram_reduce<NT>), dim3((NTILE * 1024 + 255) / 256), dim3(256), 0, s,
+                       scratch, (int)nb, r, l2, G);
+    return hipGetLastError();
+}
+
+size_t gram_scratch_bytes(int r) {
+    const int NT = (r + 31) / 32;
+    return (size_t)GRAM_MAX_BLOCKS * (NT * (NT + 1) / 2) * 1024 * sizeof(float);
+}
+
+hipError_t launch_gram(const float *A, int64_t k, int r, float l2, int precision, float *G,
+                       float *scratch, hipStream_t s) {
+    const int NT = (r + 31) / 32;
+    if (precision == NMF_BF16) {
+        switch (NT) {
+        case 1: return gram_t<1, NMF_BF16>(A, k, r, l2, G, scratch, s);
+        case 2: return gram_t<2, NMF_BF16>(A, k, r, l2, G, scratch, s);
+        case 3: return gram_t<3, NMF_BF16>(A, k, r, l2, G, scratch, s);
+        case 4: return gram_t<4, NMF_BF16>(A, k, r, l2, G, scratch, s);
+        }
+    } else {
+        switch (NT) {
+        case 1: return gram_t<1, NMF_FP32>(A, k, r, l2, G, scratch, s);
+        case 2: return gram_t<2, NMF_FP32>(A, k, r, l2, G, scratch, s);
+        case 3: return gram_t<3, NMF_FP32>(A, k, r, l2, G, scratch, s);
+        case 4: return gram_t<4, NMF_FP32>(A, k, r, l2, G, scratch, s);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace nmfi

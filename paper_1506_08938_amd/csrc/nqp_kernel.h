@@ -1,0 +1,337 @@
+// Algorithm 3 (Fast Combinational Algorithm for NQP, Section 3.4) as a
+// persistent gfx950 kernel.
+//
+// Mapping.  L lanes (1, 2 or 4, always inside one DPP quad) cooperate on one
+// column; lane `sub` of the group owns the E contiguous coordinates
+// [sub*E, sub*E + E) of the padded rank R = E*L.  The rescaled Hessian Q
+// (unit diagonal) sits in LDS, row-major with stride SQ; because Q is
+// symmetric, both the matrix-vector products and the coordinate-descent
+// gradient update read one row segment per lane: Q[j][sub*E .. sub*E+E).
+// Group reductions (sums, the greedy argmax) are DPP butterflies, so every
+// lane of a group holds bitwise-identical results.
+//
+// Persistence.  Each wave keeps 64/L columns in flight.  When a column meets
+// its stopping rule the group writes the result and takes the next column
+// index from a global counter (one atomic per wave per refill), so waves do
+// not idle while a few of their columns need extra iterations.  A column's
+// arithmetic never depends on which group or wave solves it, or when.
+//
+// Pad coordinates (r <= i < R) and frozen ones (Gamma_ii <= 0) have dsq = 0,
+// an identity row/column in Q, y = 0 and q = 1: their gradient stays 1, their
+// projected gradient and best step are 0, so they never move and never touch
+// the other coordinates.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "nmf_internal.h"
+
+namespace nmfi {
+
+constexpr int NQP_BLOCK = 256;
+
+__device__ __forceinline__ int f2i(float v) { return __builtin_bit_cast(int, v); }
+__device__ __forceinline__ float i2f(int v) { return __builtin_bit_cast(float, v); }
+
+template <int CTRL>
+__device__ __forceinline__ float dppf(float v) {
+    return i2f(__builtin_amdgcn_mov_dpp(f2i(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ int dppi(int v) {
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dppd(double v) {
+    long long b = __builtin_bit_cast(long long, v);
+    int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+    int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+    long long r = ((long long)hi << 32) | (unsigned int)lo;
+    return __builtin_bit_cast(double, r);
+}
+
+// quad_perm selectors: xor 1 = [1,0,3,2], xor 2 = [2,3,0,1]
+constexpr int DPP_XOR1 = 1 | (0 << 2) | (3 << 4) | (2 << 6);
+constexpr int DPP_XOR2 = 2 | (3 << 2) | (0 << 4) | (1 << 6);
+
+// broadcast the value of group member S to every lane of its group
+template <int L, int S>
+__device__ __forceinline__ float grp_bcast(float v) {
+    if constexpr (L == 1) {
+        return v;
+    } else if constexpr (L == 2) {
+        return dppf<S | (S << 2) | ((2 + S) << 4) | ((2 + S) << 6)>(v);
+    } else {
+        return dppf<S * 0x55>(v);
+    }
+}
+
+template <int L>
+__device__ __forceinline__ float grp_sum(float v) {
+    if constexpr (L >= 2) v += dppf<DPP_XOR1>(v);
+    if constexpr (L >= 4) v += dppf<DPP_XOR2>(v);
+    return v;
+}
+template <int L>
+__device__ __forceinline__ double grp_sum_d(double v) {
+    if constexpr (L >= 2) v += dppd<DPP_XOR1>(v);
+    if constexpr (L >= 4) v += dppd<DPP_XOR2>(v);
+    return v;
+}
+
+// (best, idx, m) <- the entry with the largest best; lowest idx on ties.
+template <int CTRL>
+__device__ __forceinline__ void argmax_step(float &best, int &idx, float &m) {
+    float ob = dppf<CTRL>(best);
+    int oi = dppi<CTRL>(idx);
+    float om = dppf<CTRL>(m);
+    bool take = (ob > best) || (ob == best && oi < idx);
+    best = take ? ob : best;
+    idx = take ? oi : idx;
+    m = take ? om : m;
+}
+template <int L>
+__device__ __forceinline__ void grp_argmax(float &best, int &idx, float &m) {
+    if constexpr (L >= 2) argmax_step<DPP_XOR1>(best, idx, m);
+    if constexpr (L >= 4) argmax_step<DPP_XOR2>(best, idx, m);
+}
+
+// out[e] = sum_j Q[sub*E + e][j] v_j for this lane's E rows; v is spread over
+// the group (entry j lives in member j / E).  qseg = &Q[0][sub*E].
+template <int E, int L, int SQ, int S = 0>
+__device__ __forceinline__ void matvec_acc(const float *__restrict__ qseg, const float (&v)[E],
+                                           float (&out)[E]) {
+    if constexpr (S < L) {
+#pragma unroll
+        for (int e2 = 0; e2 < E; e2++) {
+            const float w = grp_bcast<L, S>(v[e2]);
+            const float *row = qseg + (S * E + e2) * SQ;  // Q symmetric: row j = column j
+#pragma unroll
+            for (int e = 0; e < E; e++) out[e] = fmaf(row[e], w, out[e]);
+        }
+        matvec_acc<E, L, SQ, S + 1>(qseg, v, out);
+    }
+}
+// The rescaled Hessian in LDS never changes inside the kernel, so without a
+// fence the compiler hoists its loads out of the persistent loop and tries to
+// keep R*E of them in registers.  The fence makes every use reload it.
+__device__ __forceinline__ void lds_reload_fence() { asm volatile("" ::: "memory"); }
+
+template <int E, int L, int SQ>
+__device__ __forceinline__ void matvec(const float *__restrict__ qseg, const float (&v)[E],
+                                       float (&out)[E]) {
+    lds_reload_fence();
+#pragma unroll
+    for (int e = 0; e < E; e++) out[e] = 0.f;
+    matvec_acc<E, L, SQ>(qseg, v, out);
+}
+
+__device__ __forceinline__ bool passive(float y, float g) { return y > 0.f || g < 0.f; }
+
+// Occupancy target: about 4E live registers per lane (y, g, the search
+// direction and the product), so ask for as many waves per SIMD as fit.
+template <int E>
+constexpr int nqp_waves_per_eu() {
+    return E <= 12 ? 6 : (E <= 20 ? 4 : (E <= 28 ? 3 : 2));
+}
+
+template <int E, int L>
+__global__ __launch_bounds__(NQP_BLOCK)
+__attribute__((amdgpu_waves_per_eu(nqp_waves_per_eu<E>(), 8))) void k_nqp(const NqpParams a) {
+    constexpr int R = E * L;
+    constexpr int SQ = ((R + 3) & ~3) + 4;
+    __shared__ float sQ[R * SQ];
+    __shared__ float sD[R];
+
+    for (int t = threadIdx.x; t < R * R; t += NQP_BLOCK) {
+        const int i = t / R, j = t - (t / R) * R;
+        sQ[i * SQ + j] = a.Q[t];
+    }
+    for (int t = threadIdx.x; t < R; t += NQP_BLOCK) sD[t] = a.dsq[t];
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    const int sub = lane & (L - 1);
+    const int base = sub * E;
+    const float *qseg = sQ + base;
+    const int r = a.r;
+
+    float y[E], g[E];
+#pragma unroll
+    for (int e = 0; e < E; e++) { y[e] = 0.f; g[e] = 1.f; }
+    bool active = false;
+    bool exhausted = false;  // wave-uniform
+    int64_t col = 0;
+    double n0 = 0.0;
+    int k = 0;
+    unsigned long long my_inner = 0;
+
+    for (;;) {
+        // ------------------------------------------------ refill finished groups
+        if (!exhausted) {
+            const unsigned long long needmask = __ballot(!active && sub == 0);
+            if (needmask) {
+                const int cnt = __popcll(needmask);
+                unsigned long long b0 = 0;
+                if (lane == 0) b0 = atomicAdd(a.counter, (unsigned long long)cnt);
+                const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)(b0 & 0xffffffffull));
+                const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b0 >> 32));
+                b0 = ((unsigned long long)hi << 32) | lo;
+                if (b0 + (unsigned long long)cnt >= (unsigned long long)a.ncols) exhausted = true;
+                const int leader = lane - sub;
+                const int rank = __popcll(needmask & ((1ull << leader) - 1ull));
+                bool fresh = false;
+                if (!active) {
+                    const unsigned long long c = b0 + (unsigned long long)rank;
+                    if (c < (unsigned long long)a.ncols) { col = (int64_t)c; fresh = true; }
+                }
+                if (fresh) {
+                    // y0 = x0 * sqrt(diag), q = h / sqrt(diag), g0 = Q y0 + q
+                    float q[E];
+                    const float *prow = a.P + col * (int64_t)a.ldp;
+                    const float *xrow = a.X + col * (int64_t)a.ldx;
+#pragma unroll
+                    for (int e = 0; e < E; e++) {
+                        const int i = base + e;
+                        const float ds = sD[i];
+                        float hv = 0.f, xv = 0.f;
+                        if (i < r) {
+                            hv = fmaf(a.hsign, prow[i], a.hadd);
+                            if (!a.cold) xv = xrow[i];
+                        }
+                        y[e] = ds > 0.f ? xv * ds : 0.f;
+                        q[e] = ds > 0.f ? hv / ds : 1.f;
+                    }
+                    float u[E];
+                    matvec<E, L, SQ>(qseg, y, u);
+                    double nl = 0.0;
+#pragma unroll
+                    for (int e = 0; e < E; e++) {
+                        g[e] = u[e] + q[e];
+                        const float p = passive(y[e], g[e]) ? g[e] : 0.f;
+                        nl = fma((double)p, (double)p, nl);
+                    }
+                    n0 = grp_sum_d<L>(nl);
+                    k = 0;
+                    active = true;
+                }
+            }
+        }
+        if (!__ballot(active)) break;
+
+        if (active) {
+            // ------------------------------------------------ exact line search
+            float gb[E], u[E];
+            float sl = 0.f;
+#pragma unroll
+            for (int e = 0; e < E; e++) {
+                gb[e] = passive(y[e], g[e]) ? g[e] : 0.f;
+                sl = fmaf(gb[e], gb[e], sl);
+            }
+            const float s = grp_sum<L>(sl);
+            if (s > 0.f) {
+                matvec<E, L, SQ>(qseg, gb, u);
+                float dl = 0.f;
+#pragma unroll
+                for (int e = 0; e < E; e++) dl = fmaf(gb[e], u[e], dl);
+                const float den = grp_sum<L>(dl);
+                if (den > 0.f) {
+                    const float alpha = s / den;
+#pragma unroll
+                    for (int e = 0; e < E; e++) gb[e] = fmaxf(0.f, fmaf(-alpha, gb[e], y[e])) - y[e];
+                    matvec<E, L, SQ>(qseg, gb, u);
+                    bool accept = true;
+                    if (a.ls_guard) {
+                        float gl = 0.f;
+#pragma unroll
+                        for (int e = 0; e < E; e++) gl = fmaf(gb[e], fmaf(0.5f, u[e], g[e]), gl);
+                        accept = !(grp_sum<L>(gl) > 0.f);
+                    }
+                    if (accept) {
+#pragma unroll
+                        for (int e = 0; e < E; e++) { y[e] += gb[e]; g[e] += u[e]; }
+                    }
+                }
+            }
+            // ------------------------------------------------ r greedy CD steps
+            for (int t = 0; t < r; t++) {
+                float best = -1.f, bm = 0.f;
+                int bi = 0;
+#pragma unroll
+                for (int e = 0; e < E; e++) {
+                    const float m = fminf(y[e], g[e]);        // -(best step)
+                    const float D = m * fmaf(2.f, g[e], -m);  // 2 x decrease
+                    const bool c = D > best;
+                    best = c ? D : best;
+                    bi = c ? e : bi;
+                    bm = c ? m : bm;
+                }
+                bi += base;
+                grp_argmax<L>(best, bi, bm);
+                const bool go = best > 0.f;
+                if (!__ballot(go)) break;
+                lds_reload_fence();
+                if (go) {
+                    const float *row = qseg + bi * SQ;
+#pragma unroll
+                    for (int e = 0; e < E; e++) g[e] = fmaf(-bm, row[e], g[e]);
+#pragma unroll
+                    for (int e = 0; e < E; e++) y[e] = (base + e == bi) ? y[e] - bm : y[e];
+                }
+            }
+            // ------------------------------------------------ stopping rule
+            k++;
+            double nl = 0.0;
+#pragma unroll
+            for (int e = 0; e < E; e++) {
+                const float p = passive(y[e], g[e]) ? g[e] : 0.f;
+                nl = fma((double)p, (double)p, nl);
+            }
+            const double nk = grp_sum_d<L>(nl);
+            if (nk <= a.eps * n0 || k >= a.max_inner) {
+                float *xrow = a.X + col * (int64_t)a.ldx;
+#pragma unroll
+                for (int e = 0; e < E; e++) {
+                    const int i = base + e;
+                    if (i < r) {
+                        const float ds = sD[i];
+                        xrow[i] = ds > 0.f ? y[e] / ds : 0.f;
+                    }
+                }
+                if (sub == 0) {
+                    if (a.iters) a.iters[col] = k;
+                    my_inner += (unsigned long long)k;
+                }
+                active = false;
+            }
+        }
+    }
+    if (a.inner_total) {
+        // wave total of finished columns' iterations, one atomic per wave
+        unsigned long long v = my_inner;
+        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+        if (lane == 0 && v) atomicAdd(a.inner_total, v);
+    }
+}
+
+template <int E, int L>
+hipError_t launch_nqp_t(const NqpParams &p, hipStream_t s) {
+    if (p.ncols <= 0) return hipSuccess;
+    static int per_cu = -1;
+    if (per_cu < 0) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_nqp<E, L>, NQP_BLOCK, 0) !=
+                hipSuccess || nb < 1)
+            nb = 1;
+        per_cu = nb;
+    }
+    const int64_t cols_per_block = (NQP_BLOCK / 64) * (64 / L);
+    int64_t want = (p.ncols + cols_per_block - 1) / cols_per_block;
+    int64_t cap = (int64_t)per_cu * device_cu_count();
+    int grid = (int)(want < cap ? want : cap);
+    hipLaunchKernelGGL((k_nqp<E, L>), dim3(grid), dim3(NQP_BLOCK), 0, s, p);
+    return hipGetLastError();
+}
+
+}  // namespace nmfi

@@ -1,0 +1,330 @@
+"""ctypes binding of ``libnmf_mi355x.so`` (the C ABI in ``include/nmf.h``).
+
+Argument marshalling only: torch supplies device memory and the current
+stream; every step of the method runs in the library's HIP kernels.  If the
+library has not been built this module raises; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libnmf_mi355x.so")
+
+NMF_OK, NMF_E_INVAL, NMF_E_NOMEM, NMF_E_DEVICE, NMF_E_UNSUPPORTED, NMF_E_BUSY, NMF_E_NONFINITE = (
+    0, -1, -2, -3, -4, -5, -6)
+NMF_DENSE, NMF_CSR = 0, 1
+NMF_FP32, NMF_BF16 = 0, 1
+MAX_RANK = 128
+
+# every entry point include/nmf.h declares
+EXPORTS = [
+    "nmf_default_opts", "nmf_last_error", "nnls_solve_batch", "nmf_gram", "nmf_product",
+    "nmf_plan_create", "nmf_plan_run", "nmf_plan_destroy", "nmf_fit", "nmf_objective",
+    "nmf_basis_create", "nmf_foldin", "nmf_basis_destroy",
+]
+
+
+class NmfMatrix(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("rows", ctypes.c_int64), ("cols", ctypes.c_int64),
+                ("dense", ctypes.c_void_p), ("ld", ctypes.c_int64),
+                ("rowptr", ctypes.c_void_p), ("colidx", ctypes.c_void_p),
+                ("vals", ctypes.c_void_p), ("nnz", ctypes.c_int64),
+                ("t_rowptr", ctypes.c_void_p), ("t_colidx", ctypes.c_void_p),
+                ("t_vals", ctypes.c_void_p)]
+
+
+class NmfReg(ctypes.Structure):
+    _fields_ = [("l1_w", ctypes.c_float), ("l2_w", ctypes.c_float), ("l1_h", ctypes.c_float),
+                ("l2_h", ctypes.c_float)]
+
+
+class NmfOpts(ctypes.Structure):
+    _fields_ = [("max_outer", ctypes.c_int32), ("max_inner", ctypes.c_int32),
+                ("eps", ctypes.c_double), ("ls_guard", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("objective_every", ctypes.c_int32),
+                ("check_finite", ctypes.c_int32)]
+
+
+class NmfStats(ctypes.Structure):
+    _fields_ = [("loss", ctypes.c_double), ("objective", ctypes.c_double),
+                ("kkt_w", ctypes.c_double), ("kkt_h", ctypes.c_double), ("kbar", ctypes.c_double),
+                ("inner_total", ctypes.c_int64), ("outer_done", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class NmfError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"nmf status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+_vp = ctypes.c_void_p
+
+
+def lib():
+    """Loads the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_1506_08938_amd.build` (hipcc, gfx950)")
+        L = ctypes.CDLL(LIB_PATH)
+        L.nmf_last_error.restype = ctypes.c_char_p
+        L.nmf_default_opts.argtypes = [ctypes.POINTER(NmfOpts)]
+        L.nmf_default_opts.restype = None
+        L.nnls_solve_batch.argtypes = [ctypes.c_int32, ctypes.c_int64, _vp, _vp, _vp,
+                                       ctypes.POINTER(NmfOpts), _vp, _vp]
+        L.nmf_gram.argtypes = [_vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_float, ctypes.c_int32,
+                               _vp, _vp]
+        L.nmf_product.argtypes = [ctypes.POINTER(NmfMatrix), ctypes.c_int32, ctypes.c_int32, _vp,
+                                  ctypes.c_int32, _vp, _vp]
+        L.nmf_plan_create.argtypes = [ctypes.POINTER(NmfMatrix), ctypes.c_int32,
+                                      ctypes.POINTER(NmfReg), ctypes.POINTER(NmfOpts),
+                                      ctypes.POINTER(_vp), _vp]
+        L.nmf_plan_run.argtypes = [_vp, _vp, _vp, ctypes.c_int32, _vp, ctypes.POINTER(NmfStats),
+                                   _vp]
+        L.nmf_plan_destroy.argtypes = [_vp]
+        L.nmf_plan_destroy.restype = None
+        L.nmf_fit.argtypes = [ctypes.POINTER(NmfMatrix), ctypes.c_int32, ctypes.POINTER(NmfReg),
+                              ctypes.POINTER(NmfOpts), _vp, _vp, _vp, ctypes.POINTER(NmfStats),
+                              _vp]
+        L.nmf_objective.argtypes = [ctypes.POINTER(NmfMatrix), ctypes.c_int32,
+                                    ctypes.POINTER(NmfReg), _vp, _vp, ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_double), _vp]
+        L.nmf_basis_create.argtypes = [_vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_float,
+                                       ctypes.c_float, ctypes.POINTER(NmfOpts),
+                                       ctypes.POINTER(_vp), _vp]
+        L.nmf_foldin.argtypes = [_vp, ctypes.POINTER(NmfMatrix), _vp, _vp, _vp]
+        L.nmf_basis_destroy.argtypes = [_vp]
+        L.nmf_basis_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().nmf_last_error().decode()
+
+
+def check(status: int):
+    if status != NMF_OK:
+        raise NmfError(status, last_error())
+
+
+def opts(**kw) -> NmfOpts:
+    o = NmfOpts()
+    lib().nmf_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+# --------------------------------------------------------------------------- torch plumbing
+def _torch():
+    import torch
+    return torch
+
+
+def stream_ptr():
+    return _torch().cuda.current_stream().cuda_stream
+
+
+def _dev(t, dtype, name, shape=None):
+    torch = _torch()
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def nnls_solve_batch(gram, h, X, opt: NmfOpts | None = None, iters=None):
+    """Algorithm 3 on every row of h/X (in place on X).  gram (r, r), h and X
+    (ncols, r) float32 device tensors; iters optional int32 (ncols,)."""
+    torch = _torch()
+    r = gram.shape[0]
+    ncols = h.shape[0]
+    _dev(gram, torch.float32, "gram", (r, r))
+    _dev(h, torch.float32, "h", (ncols, r))
+    _dev(X, torch.float32, "X", (ncols, r))
+    _dev(iters, torch.int32, "iters", (ncols,))
+    opt = opt or opts()
+    check(lib().nnls_solve_batch(r, ncols, _ptr(gram), _ptr(h), _ptr(X), ctypes.byref(opt),
+                                 _ptr(iters), stream_ptr()))
+    return X
+
+
+class DeviceMatrix:
+    """Keeps the device arrays of V alive and exposes its nmf_matrix struct."""
+
+    def __init__(self, V, with_transpose=True):
+        torch = _torch()
+        self.keep = []
+        m = NmfMatrix()
+        if isinstance(V, torch.Tensor):
+            _dev(V, torch.float32, "V")
+            m.kind = NMF_DENSE
+            m.rows, m.cols = V.shape
+            m.dense = V.data_ptr()
+            m.ld = V.shape[1]
+            self.keep.append(V)
+        else:  # scipy CSR on the host, or a dict of device arrays
+            import numpy as np
+            csr = V
+            m.kind = NMF_CSR
+            m.rows, m.cols = csr.shape
+
+            def up(a, dt):
+                t = torch.from_numpy(np.ascontiguousarray(a)).to(dt).cuda()
+                self.keep.append(t)
+                return t.data_ptr()
+
+            m.rowptr = up(csr.indptr.astype(np.int32), torch.int32)
+            m.colidx = up(csr.indices.astype(np.int32), torch.int32)
+            m.vals = up(csr.data.astype(np.float32), torch.float32)
+            m.nnz = csr.nnz
+            if with_transpose:
+                t = csr.T.tocsr()
+                t.sort_indices()
+                m.t_rowptr = up(t.indptr.astype(np.int32), torch.int32)
+                m.t_colidx = up(t.indices.astype(np.int32), torch.int32)
+                m.t_vals = up(t.data.astype(np.float32), torch.float32)
+        self.m = m
+
+    @property
+    def shape(self):
+        return (self.m.rows, self.m.cols)
+
+
+def gram(A, l2=0.0, precision=NMF_FP32):
+    torch = _torch()
+    _dev(A, torch.float32, "A")
+    k, r = A.shape
+    G = torch.empty((r, r), dtype=torch.float32, device=A.device)
+    check(lib().nmf_gram(_ptr(A), k, r, float(l2), precision, _ptr(G), stream_ptr()))
+    return G
+
+
+def product(V: DeviceMatrix, A, trans, precision=NMF_FP32):
+    torch = _torch()
+    _dev(A, torch.float32, "A")
+    r = A.shape[1]
+    m, n = V.shape
+    P = torch.empty(((m if trans else n), r), dtype=torch.float32, device=A.device)
+    check(lib().nmf_product(ctypes.byref(V.m), int(trans), r, _ptr(A), precision, _ptr(P),
+                            stream_ptr()))
+    return P
+
+
+def reg(l1_w=0.0, l2_w=0.0, l1_h=0.0, l2_h=0.0) -> NmfReg:
+    return NmfReg(l1_w, l2_w, l1_h, l2_h)
+
+
+class Plan:
+    """nmf_plan_create / nmf_plan_run / nmf_plan_destroy."""
+
+    def __init__(self, V: DeviceMatrix, r: int, regw: NmfReg, opt: NmfOpts):
+        self.V = V
+        self.r = r
+        self.h = _vp()
+        self.opt = opt
+        self.regw = regw
+        check(lib().nmf_plan_create(ctypes.byref(V.m), r, ctypes.byref(regw), ctypes.byref(opt),
+                                    ctypes.byref(self.h), stream_ptr()))
+
+    def run(self, W, Ht, outer, want_trace=False, want_stats=False):
+        import numpy as np
+        torch = _torch()
+        m, n = self.V.shape
+        _dev(W, torch.float32, "W", (m, self.r))
+        _dev(Ht, torch.float32, "Ht", (n, self.r))
+        trace = np.full(outer + 1, np.nan) if want_trace else None
+        st = NmfStats() if want_stats else None
+        check(lib().nmf_plan_run(self.h, _ptr(W), _ptr(Ht), int(outer),
+                                 None if trace is None else trace.ctypes.data,
+                                 None if st is None else ctypes.byref(st), stream_ptr()))
+        return trace, (st.as_dict() if st is not None else None)
+
+    def close(self):
+        if self.h:
+            lib().nmf_plan_destroy(self.h)
+            self.h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fit(V: DeviceMatrix, r, regw: NmfReg, opt: NmfOpts, W, Ht, want_trace=True):
+    """nmf_fit on device tensors W (m, r) and Ht (n, r), updated in place."""
+    import numpy as np
+    torch = _torch()
+    m, n = V.shape
+    _dev(W, torch.float32, "W", (m, r))
+    _dev(Ht, torch.float32, "Ht", (n, r))
+    trace = np.full(opt.max_outer + 1, np.nan) if want_trace else None
+    st = NmfStats()
+    check(lib().nmf_fit(ctypes.byref(V.m), r, ctypes.byref(regw), ctypes.byref(opt), _ptr(W),
+                        _ptr(Ht), None if trace is None else trace.ctypes.data, ctypes.byref(st),
+                        stream_ptr()))
+    return trace, st.as_dict()
+
+
+def objective(V: DeviceMatrix, r, regw: NmfReg, W, Ht):
+    loss = ctypes.c_double(); obj = ctypes.c_double()
+    check(lib().nmf_objective(ctypes.byref(V.m), r, ctypes.byref(regw), _ptr(W), _ptr(Ht),
+                              ctypes.byref(loss), ctypes.byref(obj), stream_ptr()))
+    return loss.value, obj.value
+
+
+class Basis:
+    """nmf_basis_create / nmf_foldin / nmf_basis_destroy."""
+
+    def __init__(self, W, l1=0.0, l2=0.0, opt: NmfOpts | None = None):
+        torch = _torch()
+        _dev(W, torch.float32, "W")
+        self.m, self.r = W.shape
+        self.h = _vp()
+        self.opt = opt or opts()
+        check(lib().nmf_basis_create(_ptr(W), self.m, self.r, float(l1), float(l2),
+                                     ctypes.byref(self.opt), ctypes.byref(self.h), stream_ptr()))
+
+    def foldin(self, Vnew: DeviceMatrix, out=None, iters=None):
+        torch = _torch()
+        c = Vnew.m.cols if Vnew.m.kind == NMF_DENSE else Vnew.m.rows
+        if out is None:
+            out = torch.empty((c, self.r), dtype=torch.float32, device="cuda")
+        _dev(out, torch.float32, "Ht_new", (c, self.r))
+        _dev(iters, torch.int32, "iters", (c,))
+        check(lib().nmf_foldin(self.h, ctypes.byref(Vnew.m), _ptr(out), _ptr(iters),
+                               stream_ptr()))
+        return out
+
+    def close(self):
+        if self.h:
+            lib().nmf_basis_destroy(self.h)
+            self.h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

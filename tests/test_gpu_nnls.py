@@ -1,0 +1,168 @@
+"""nnls_solve_batch (Algorithm 3 on a batch of NQPs) on the GPU against the
+FP64 oracle, through the C ABI.
+
+Both sides get the same float32 inputs (the oracle widens them to float64).
+Tolerances: the GPU iterates in float32, so after K iterations its x carries
+rounding of order kappa(Q) * 2^-24 relative to the oracle's; the tests use a
+converged mode (eps = 0, many iterations: a unique optimum, compared on x and
+on f) and a fixed-K mode (few iterations: compared on the objective, which is
+insensitive to the order of near-tied greedy choices, and on x for the bulk
+of the columns).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1506_08938_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def make_batch(r, ncols, seed, l1=0.0, l2=0.0, kind="random"):
+    inst = synth.nqp_instance(r, ncols, seed, l1=l1, l2=l2, kind=kind)
+    A = inst["A"].astype(np.float64); B = inst["B"].astype(np.float64)
+    G = (A.T @ A + 2 * l2 * np.eye(r)).astype(np.float32)
+    h = (-(B.T @ A) + l1).astype(np.float32)
+    return G, h, inst["x0"]
+
+
+def gpu_solve(G, h, x0, **kw):
+    import torch
+    from paper_1506_08938_amd import native
+    Gd = torch.from_numpy(G).cuda(); hd = torch.from_numpy(h).cuda()
+    Xd = torch.from_numpy(np.ascontiguousarray(x0, dtype=np.float32)).cuda()
+    it = torch.zeros(h.shape[0], dtype=torch.int32, device="cuda")
+    native.nnls_solve_batch(Gd, hd, Xd, native.opts(**kw), it)
+    torch.cuda.synchronize()
+    return Xd.cpu().numpy().astype(np.float64), it.cpu().numpy()
+
+
+def fvals(G, h, X):
+    G = G.astype(np.float64); h = h.astype(np.float64)
+    return 0.5 * np.einsum("ij,jk,ik->i", X, G, X) + np.einsum("ij,ij->i", h, X)
+
+
+def rel_err_rows(X, Y):
+    num = np.linalg.norm(X - Y, axis=1)
+    den = np.maximum(np.linalg.norm(Y, axis=1), 1e-30)
+    return num / den
+
+
+RANKS = [1, 2, 4, 8, 10, 16, 31, 32, 33, 48, 64, 65, 100, 128]
+
+
+@pytest.mark.parametrize("r", RANKS)
+def test_converged_matches_oracle(r):
+    ncols = 2 * 1024 + 37  # several waves of columns and a ragged tail
+    G, h, x0 = make_batch(r, ncols, seed=r, l1=0.01 * (r % 3), l2=0.01 * (r % 2))
+    K = 200
+    Xg, itg = gpu_solve(G, h, x0, max_inner=K, eps=0.0)
+    Xo, ito = oracle.nqp_batch(G, h, x0, max_inner=K, eps=0.0)
+    # eps = 0 stops only on an exactly zero projected gradient
+    assert ((itg >= 1) & (itg <= K)).all() and ((ito >= 1) & (ito <= K)).all()
+    assert (Xg >= 0).all()
+    e = rel_err_rows(Xg, Xo)
+    fg, fo = fvals(G, h, Xg), fvals(G, h, Xo)
+    fr = np.abs(fg - fo) / np.maximum(np.abs(fo), 1e-30)
+    print(f"r={r} x rel err: median {np.median(e):.2e} p99 {np.quantile(e, .99):.2e} "
+          f"max {e.max():.2e}; f rel: max {fr.max():.2e}")
+    # measured: f rel <= 3e-11, x rel <= 5.5e-5 (r = 128)
+    assert fr.max() < 1e-9
+    assert np.quantile(e, 0.99) < 1e-4 and e.max() < 2e-4
+
+
+@pytest.mark.parametrize("r", [2, 10, 32, 64, 100, 128])
+@pytest.mark.parametrize("K", [1, 3])
+def test_fixed_iterations_match_oracle(r, K):
+    ncols = 1024 + 5
+    G, h, x0 = make_batch(r, ncols, seed=1000 + r, l1=0.05)
+    Xg, itg = gpu_solve(G, h, x0, max_inner=K, eps=0.0)
+    Xo, ito = oracle.nqp_batch(G, h, x0, max_inner=K, eps=0.0)
+    assert (itg <= K).all() and (np.mean(itg == K) > 0.9 or r <= 2)
+    e = rel_err_rows(Xg, Xo)
+    fg, fo = fvals(G, h, Xg), fvals(G, h, Xo)
+    f0 = fvals(G, h, x0.astype(np.float64))
+    # objective gap relative to the decrease achieved
+    fr = np.abs(fg - fo) / np.maximum(np.abs(f0 - fo), 1e-30)
+    print(f"r={r} K={K} x rel err: median {np.median(e):.2e} p99 {np.quantile(e, .99):.2e} "
+          f"max {e.max():.2e}; f gap/decrease max {fr.max():.2e} p99 {np.quantile(fr, .99):.2e}")
+    # a float32 near-tie can flip one greedy choice; the objective barely moves
+    assert np.median(e) < 2e-4
+    assert np.quantile(fr, 0.99) < 2e-5 and fr.max() < 5e-4
+
+
+@pytest.mark.parametrize("r", [8, 100])
+def test_adaptive_stopping_matches_oracle_counts(r):
+    ncols = 1024
+    G, h, x0 = make_batch(r, ncols, seed=77 + r)
+    Xg, itg = gpu_solve(G, h, x0, max_inner=100, eps=1e-3)
+    Xo, ito = oracle.nqp_batch(G, h, x0, max_inner=100, eps=1e-3)
+    agree = (itg == ito).mean()
+    print(f"r={r} iteration counts agree on {agree:.4f} of columns; mean k gpu {itg.mean():.3f} "
+          f"oracle {ito.mean():.3f}")
+    assert agree > 0.97
+    assert abs(itg.mean() - ito.mean()) < 0.05 * ito.mean()
+
+
+def test_worked_example_on_gpu():
+    G = np.array([[1.0, 0.1], [0.1, 10.0]], dtype=np.float32)
+    h = np.array([[-80.0, -100.0]], dtype=np.float32)
+    x0 = np.array([[200.0, 20.0]], dtype=np.float32)
+    Xg, itg = gpu_solve(G, h, x0, max_inner=100, eps=1e-7)
+    assert itg[0] == 1
+    xs = np.array([790 / 9.99, 92 / 9.99])
+    assert np.linalg.norm(Xg[0] - xs) / np.linalg.norm(xs) < 2e-4
+
+
+@pytest.mark.parametrize("r", [1, 7, 100, 128])
+def test_closed_forms_on_gpu(r):
+    kind = "random" if r == 1 else "orthogonal"
+    G, h, x0 = make_batch(r, 300, seed=5 + r, l1=0.02, kind=kind)
+    Xg, itg = gpu_solve(G, h, x0, max_inner=5, eps=1e-10)
+    expect = np.maximum(0.0, -h.astype(np.float64)) / np.diag(G).astype(np.float64)
+    assert (itg == 1).all()
+    assert np.allclose(Xg, expect, rtol=2e-6, atol=0)
+
+
+def test_frozen_coordinate_and_singular_gram():
+    G, h, x0 = make_batch(12, 200, seed=3, kind="zerocol")
+    Xg, _ = gpu_solve(G, h, x0, max_inner=300, eps=0.0)
+    assert (Xg[:, 0] == 0).all()
+    Xo, _ = oracle.nqp_batch(G, h, x0, max_inner=300, eps=0.0)
+    fg, fo = fvals(G, h, Xg), fvals(G, h, Xo)
+    assert np.abs(fg - fo).max() <= 1e-5 * np.abs(fo).max()
+    G, h, x0 = make_batch(12, 200, seed=4, kind="dupcol")
+    Xg, _ = gpu_solve(G, h, x0, max_inner=300, eps=0.0)
+    Xo, _ = oracle.nqp_batch(G, h, x0, max_inner=300, eps=0.0)
+    fg, fo = fvals(G, h, Xg), fvals(G, h, Xo)
+    assert np.abs(fg - fo).max() <= 1e-5 * np.abs(fo).max()
+
+
+def test_edge_sizes_and_determinism():
+    import torch
+    from paper_1506_08938_amd import native
+    for ncols in [1, 63, 64, 65]:
+        G, h, x0 = make_batch(20, ncols, seed=ncols)
+        Xg, _ = gpu_solve(G, h, x0, max_inner=50, eps=1e-3)
+        Xo, _ = oracle.nqp_batch(G, h, x0, max_inner=50, eps=1e-3)
+        assert np.quantile(rel_err_rows(Xg, Xo), 0.5) < 1e-3
+    # empty batch is a no-op
+    e = torch.empty((0, 5), dtype=torch.float32, device="cuda")
+    native.nnls_solve_batch(torch.eye(5, device="cuda"), e, e.clone())
+    # bitwise determinism across runs
+    G, h, x0 = make_batch(100, 5000, seed=11)
+    a, ia = gpu_solve(G, h, x0, max_inner=100, eps=1e-3)
+    b, ib = gpu_solve(G, h, x0, max_inner=100, eps=1e-3)
+    assert np.array_equal(a, b) and np.array_equal(ia, ib)
+
+
+def test_nonfinite_input_rejected_when_checking():
+    import torch
+    from paper_1506_08938_amd import native
+    G, h, x0 = make_batch(6, 10, seed=1)
+    h[3, 2] = np.nan
+    Gd = torch.from_numpy(G).cuda(); hd = torch.from_numpy(h).cuda()
+    Xd = torch.from_numpy(x0).cuda()
+    with pytest.raises(native.NmfError) as ei:
+        native.nnls_solve_batch(Gd, hd, Xd, native.opts(check_finite=1))
+    assert ei.value.status == native.NMF_E_NONFINITE
