@@ -88,3 +88,17 @@ int check_values(const float *x, int64_t n, int nonneg, hipStream_t s) {
 }
 
 }  // namespace nmfi
+
+namespace nmfi {
+
+// graph-safe zero fill (no memset node)
+__global__ void k_zero_u64(unsigned long long *p, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0ull;
+}
+
+hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, p, n);
+    return hipGetLastError();
+}
+
+}  // namespace nmfi

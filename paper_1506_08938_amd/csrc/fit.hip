@@ -1,0 +1,644 @@
+// Host orchestration: the building-block entry points, the fit plan
+// (Algorithm 2 with the regularised NQPs of Section 3.5), the objective, and
+// fold-in against a resident basis (the E-step alone).
+#include <hipcub/hipcub.hpp>
+#include <math.h>
+
+#include <vector>
+
+#include "nmf_internal.h"
+
+using namespace nmfi;
+
+namespace nmfi {
+
+static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+int validate_matrix(const nmf_matrix *V, bool need_transpose_ok) {
+    (void)need_transpose_ok;
+    if (!V) return fail(NMF_E_INVAL, "matrix descriptor is NULL");
+    if (V->rows < 1 || V->cols < 1) return fail(NMF_E_INVAL, "V must have at least one row and column");
+    if (V->rows > INT32_MAX || V->cols > INT32_MAX) return fail(NMF_E_INVAL, "V dimensions exceed int32");
+    if (V->kind == NMF_DENSE) {
+        if (!V->dense) return fail(NMF_E_INVAL, "dense V pointer is NULL");
+        if (V->ld < V->cols) return fail(NMF_E_INVAL, "ld (%lld) < cols (%lld)", (long long)V->ld, (long long)V->cols);
+    } else if (V->kind == NMF_CSR) {
+        if (!V->rowptr || !V->colidx || !V->vals) return fail(NMF_E_INVAL, "CSR arrays must be non-NULL");
+        if (V->nnz < 0 || V->nnz > INT32_MAX) return fail(NMF_E_INVAL, "nnz must be in [0, 2^31)");
+        const bool any_t = V->t_rowptr || V->t_colidx || V->t_vals;
+        const bool all_t = V->t_rowptr && V->t_colidx && V->t_vals;
+        if (any_t && !all_t) return fail(NMF_E_INVAL, "give all three CSR(V') arrays or none");
+    } else {
+        return fail(NMF_E_INVAL, "unknown matrix kind %d", V->kind);
+    }
+    return NMF_OK;
+}
+
+// ------------------------------------------------------------------ CSR transpose
+__global__ void k_expand_rows(const int32_t *__restrict__ rowptr, int64_t m, int32_t *__restrict__ rowid) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+        for (int32_t t = rowptr[i]; t < rowptr[i + 1]; t++) rowid[t] = (int32_t)i;
+}
+__global__ void k_iota(int32_t *__restrict__ x, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        x[i] = (int32_t)i;
+}
+__global__ void k_permute(const int32_t *__restrict__ perm, const int32_t *__restrict__ rowid,
+                          const float *__restrict__ vals, int64_t n, int32_t *__restrict__ tcol,
+                          float *__restrict__ tval) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t p = perm[i];
+        tcol[i] = rowid[p];
+        tval[i] = vals[p];
+    }
+}
+// t_rowptr[j] = first position whose (sorted) column is >= j
+__global__ void k_col_bounds(const int32_t *__restrict__ keys, int64_t nnz, int64_t n,
+                             int32_t *__restrict__ trp) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j <= n; j += (int64_t)gridDim.x * blockDim.x) {
+        int64_t lo = 0, hi = nnz;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (keys[mid] < j) lo = mid + 1; else hi = mid;
+        }
+        trp[j] = (int32_t)lo;
+    }
+}
+
+// CSR(V') from CSR(V) with a stable radix sort by column (rows stay ascending
+// inside each column).  Outputs are hipMalloc'd and owned by the caller.
+int csr_transpose(const nmf_matrix *V, int32_t **trp, int32_t **tci, float **tv, hipStream_t s) {
+    const int64_t m = V->rows, n = V->cols, nnz = V->nnz;
+    *trp = nullptr; *tci = nullptr; *tv = nullptr;
+    NMF_HIP(hipMalloc((void **)trp, (n + 1) * sizeof(int32_t)));
+    NMF_HIP(hipMalloc((void **)tci, (nnz > 0 ? nnz : 1) * sizeof(int32_t)));
+    NMF_HIP(hipMalloc((void **)tv, (nnz > 0 ? nnz : 1) * sizeof(float)));
+    int32_t *rowid = nullptr, *keys = nullptr, *idx = nullptr, *perm = nullptr;
+    void *tmp = nullptr;
+    size_t tmp_bytes = 0;
+    const size_t nb = (nnz > 0 ? nnz : 1) * sizeof(int32_t);
+    NMF_HIP(hipMalloc((void **)&rowid, nb));
+    NMF_HIP(hipMalloc((void **)&keys, nb));
+    NMF_HIP(hipMalloc((void **)&idx, nb));
+    NMF_HIP(hipMalloc((void **)&perm, nb));
+    const int g = 2048;
+    hipLaunchKernelGGL(k_expand_rows, dim3(g), dim3(256), 0, s, V->rowptr, m, rowid);
+    hipLaunchKernelGGL(k_iota, dim3(g), dim3(256), 0, s, idx, nnz);
+    int bits = 1;
+    while ((int64_t(1) << bits) < n) bits++;
+    NMF_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, V->colidx, keys, idx, perm, (int)nnz, 0, bits, s));
+    NMF_HIP(hipMalloc(&tmp, tmp_bytes > 0 ? tmp_bytes : 1));
+    NMF_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, V->colidx, keys, idx, perm, (int)nnz, 0, bits, s));
+    hipLaunchKernelGGL(k_permute, dim3(g), dim3(256), 0, s, perm, rowid, V->vals, nnz, *tci, *tv);
+    hipLaunchKernelGGL(k_col_bounds, dim3((unsigned)((n + 256) / 256)), dim3(256), 0, s, keys, nnz, n, *trp);
+    NMF_HIP(hipGetLastError());
+    NMF_HIP(hipStreamSynchronize(s));
+    (void)hipFree(tmp); (void)hipFree(rowid); (void)hipFree(keys); (void)hipFree(idx); (void)hipFree(perm);
+    return NMF_OK;
+}
+
+static int host_rowptr(const int32_t *d, int64_t nrows, std::vector<int32_t> &h, hipStream_t s) {
+    h.resize(nrows + 1);
+    NMF_HIP(hipMemcpyAsync(h.data(), d, (nrows + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    NMF_HIP(hipStreamSynchronize(s));
+    if (h[0] != 0) return fail(NMF_E_INVAL, "rowptr[0] must be 0");
+    for (int64_t i = 0; i < nrows; i++)
+        if (h[i + 1] < h[i]) return fail(NMF_E_INVAL, "rowptr must be non-decreasing");
+    return NMF_OK;
+}
+
+}  // namespace nmfi
+
+// ============================================================ building blocks
+extern "C" int nmf_gram(const float *A, int64_t k, int32_t r, float l2, int32_t precision, float *G,
+                        void *stream) {
+    if (r < 1 || r > NMF_MAX_RANK) return fail(NMF_E_INVAL, "r must be in [1, %d]", NMF_MAX_RANK);
+    if (k < 1) return fail(NMF_E_INVAL, "k must be >= 1");
+    if (!A || !G) return fail(NMF_E_INVAL, "A and G must be non-NULL");
+    if (precision != NMF_FP32 && precision != NMF_BF16) return fail(NMF_E_INVAL, "bad precision");
+    hipStream_t s = (hipStream_t)stream;
+    float *scratch = nullptr;
+    NMF_HIP(hipMallocAsync((void **)&scratch, gram_scratch_bytes(r), s));
+    hipError_t e = launch_gram(A, k, r, l2, precision, G, scratch, s);
+    hipError_t e2 = hipFreeAsync(scratch, s);
+    if (e != hipSuccess) return hip_fail(e, "nmf_gram");
+    if (e2 != hipSuccess) return hip_fail(e2, "hipFreeAsync");
+    return NMF_OK;
+}
+
+extern "C" int nmf_product(const nmf_matrix *V, int32_t trans, int32_t r, const float *A,
+                           int32_t precision, float *P, void *stream) {
+    if (int st = validate_matrix(V, true)) return st;
+    if (r < 1 || r > NMF_MAX_RANK) return fail(NMF_E_INVAL, "r must be in [1, %d]", NMF_MAX_RANK);
+    if (!A || !P) return fail(NMF_E_INVAL, "A and P must be non-NULL");
+    if (trans != 0 && trans != 1) return fail(NMF_E_INVAL, "trans must be 0 or 1");
+    if (precision != NMF_FP32 && precision != NMF_BF16) return fail(NMF_E_INVAL, "bad precision");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t m = V->rows, n = V->cols;
+    if (V->kind == NMF_DENSE) {
+        const void *src = V->dense;
+        __bf16 *v16 = nullptr;
+        if (precision == NMF_BF16) {
+            NMF_HIP(hipMallocAsync((void **)&v16, (size_t)m * n * sizeof(__bf16), s));
+            NMF_HIP(launch_to_bf16(V->dense, m, n, V->ld, v16, s));
+            src = v16;
+        }
+        float *scratch = nullptr;
+        NMF_HIP(hipMallocAsync((void **)&scratch, dense_scratch_bytes(m, n, r), s));
+        hipError_t e = launch_dense_product(src, precision == NMF_BF16, m, n,
+                                            precision == NMF_BF16 ? n : V->ld, trans, A, r, P,
+                                            scratch, s);
+        (void)hipFreeAsync(scratch, s);
+        if (v16) (void)hipFreeAsync(v16, s);
+        if (e != hipSuccess) return hip_fail(e, "nmf_product");
+        return NMF_OK;
+    }
+    // CSR: trans = 1 runs over CSR(V) with A = Ht; trans = 0 over CSR(V')
+    const int32_t *rp = trans ? V->rowptr : V->t_rowptr;
+    const int32_t *ci = trans ? V->colidx : V->t_colidx;
+    const float *vv = trans ? V->vals : V->t_vals;
+    int32_t *trp = nullptr, *tci = nullptr;
+    float *tvv = nullptr;
+    if (!rp) {
+        if (int st = csr_transpose(V, &trp, &tci, &tvv, s)) return st;
+        rp = trp; ci = tci; vv = tvv;
+    }
+    const int64_t nrows = trans ? m : n;
+    std::vector<int32_t> h;
+    int st = host_rowptr(rp, nrows, h, s);
+    SpmmPlan pl{};
+    if (!st) st = build_spmm_plan(h, &pl, s);
+    float *partial = nullptr;
+    if (!st && pl.nslots > 0) {
+        hipError_t e = hipMalloc((void **)&partial, (size_t)pl.nslots * r * sizeof(float));
+        if (e != hipSuccess) st = hip_fail(e, "hipMalloc");
+    }
+    if (!st) {
+        hipError_t e = launch_spmm(pl, ci, vv, A, r, P, partial, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) st = hip_fail(e, "nmf_product");
+    }
+    free_spmm_plan(&pl);
+    if (partial) (void)hipFree(partial);
+    if (trp) { (void)hipFree(trp); (void)hipFree(tci); (void)hipFree(tvv); }
+    return st;
+}
+
+// ============================================================ plan / fit
+struct nmf_plan {
+    nmf_matrix V{};
+    int64_t m = 0, n = 0;
+    int r = 0;
+    nmf_reg reg{};
+    nmf_opts opt{};
+    NqpVariant var{};
+    int R = 0;
+    // CSR
+    int32_t *t_rowptr = nullptr, *t_colidx = nullptr;
+    float *t_vals = nullptr;
+    bool own_t = false;
+    SpmmPlan sp_h{}, sp_w{};
+    float *sp_partial = nullptr;
+    // dense
+    __bf16 *V16 = nullptr;
+    float *dense_scratch = nullptr;
+    // workspace
+    char *ws = nullptr;
+    float *G = nullptr, *gram_scratch = nullptr, *Q = nullptr, *dsq = nullptr, *P = nullptr;
+    unsigned long long *counter = nullptr, *inner_total = nullptr;
+    char *obj_scratch = nullptr;
+    double *obj_out = nullptr, *kkt_partial = nullptr, *kkt_out = nullptr;
+    // per-phase HIP-event timers
+    bool prof = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+    size_t ev_used = 0;
+    double ms[NMF_PHASES] = {0, 0, 0, 0};
+    int64_t calls[NMF_PHASES] = {0, 0, 0, 0};
+};
+
+static void plan_free(nmf_plan *p) {
+    if (!p) return;
+    for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
+    if (p->own_t) { (void)hipFree(p->t_rowptr); (void)hipFree(p->t_colidx); (void)hipFree(p->t_vals); }
+    free_spmm_plan(&p->sp_h);
+    free_spmm_plan(&p->sp_w);
+    if (p->sp_partial) (void)hipFree(p->sp_partial);
+    if (p->V16) (void)hipFree(p->V16);
+    if (p->dense_scratch) (void)hipFree(p->dense_scratch);
+    if (p->ws) (void)hipFree(p->ws);
+    delete p;
+}
+
+extern "C" int nmf_plan_create(const nmf_matrix *V, int32_t r, const nmf_reg *reg, const nmf_opts *opt,
+                               nmf_plan **out, void *stream) {
+    if (!out) return fail(NMF_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (int st = validate_matrix(V, true)) return st;
+    if (r < 1 || r > NMF_MAX_RANK) return fail(NMF_E_INVAL, "r must be in [1, %d] (got %d)", NMF_MAX_RANK, r);
+    if (!reg) return fail(NMF_E_INVAL, "reg is NULL");
+    if (int st = validate_opts(opt)) return st;
+    const float regs[4] = {reg->l1_w, reg->l2_w, reg->l1_h, reg->l2_h};
+    for (float v : regs)
+        if (!(v >= 0.f) || !isfinite(v)) return fail(NMF_E_INVAL, "regularisation weights must be finite and >= 0");
+    if (opt->max_outer < 0) return fail(NMF_E_INVAL, "max_outer must be >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    if (opt->check_finite) {
+        int st = V->kind == NMF_DENSE ? NMF_OK : check_values(V->vals, V->nnz, 1, s);
+        if (V->kind == NMF_DENSE) {
+            if (V->ld != V->cols) {
+                for (int64_t i = 0; i < V->rows && !st; i++) st = check_values(V->dense + i * V->ld, V->cols, 1, s);
+            } else {
+                st = check_values(V->dense, V->rows * V->cols, 1, s);
+            }
+        }
+        if (st) return st;
+    }
+    nmf_plan *p = new nmf_plan();
+    p->V = *V; p->m = V->rows; p->n = V->cols; p->r = r; p->reg = *reg; p->opt = *opt;
+    p->var = nqp_pick(r);
+    p->R = p->var.E * p->var.L;
+    int st = NMF_OK;
+    if (V->kind == NMF_CSR) {
+        if (!V->t_rowptr) {
+            st = csr_transpose(V, &p->t_rowptr, &p->t_colidx, &p->t_vals, s);
+            p->own_t = true;
+        } else {
+            p->t_rowptr = (int32_t *)V->t_rowptr; p->t_colidx = (int32_t *)V->t_colidx; p->t_vals = (float *)V->t_vals;
+        }
+        std::vector<int32_t> h;
+        if (!st) st = host_rowptr(p->t_rowptr, p->n, h, s);
+        if (!st) st = build_spmm_plan(h, &p->sp_h, s);
+        if (!st) st = host_rowptr(V->rowptr, p->m, h, s);
+        if (!st) st = build_spmm_plan(h, &p->sp_w, s);
+        if (!st) {
+            const int32_t slots = p->sp_h.nslots > p->sp_w.nslots ? p->sp_h.nslots : p->sp_w.nslots;
+            if (slots > 0) {
+                hipError_t e = hipMalloc((void **)&p->sp_partial, (size_t)slots * r * sizeof(float));
+                if (e != hipSuccess) st = hip_fail(e, "hipMalloc");
+            }
+        }
+    } else {
+        if (opt->precision == NMF_BF16) {
+            hipError_t e = hipMalloc((void **)&p->V16, (size_t)p->m * p->n * sizeof(__bf16));
+            if (e == hipSuccess) e = launch_to_bf16(V->dense, p->m, p->n, V->ld, p->V16, s);
+            if (e != hipSuccess) st = hip_fail(e, "BF16 copy of V");
+        }
+        if (!st) {
+            hipError_t e = hipMalloc((void **)&p->dense_scratch, dense_scratch_bytes(p->m, p->n, r));
+            if (e != hipSuccess) st = hip_fail(e, "hipMalloc");
+        }
+    }
+    if (!st) {
+        const int64_t cmax = p->m > p->n ? p->m : p->n;
+        size_t off = 0;
+        auto place = [&](size_t bytes) { size_t o = off; off += al256(bytes); return o; };
+        const size_t o_cnt = place(2 * sizeof(unsigned long long));
+        const size_t o_dsq = place(NMF_MAX_RANK * sizeof(float));
+        const size_t o_G = place((size_t)r * r * sizeof(float));
+        const size_t o_Q = place((size_t)p->R * p->R * sizeof(float));
+        const size_t o_gs = place(gram_scratch_bytes(r));
+        const size_t o_P = place((size_t)cmax * r * sizeof(float));
+        const size_t o_oo = place(4 * sizeof(double));
+        const size_t o_ko = place(4 * sizeof(double));
+        const size_t o_kp = place((size_t)cmax * sizeof(double));
+        const size_t o_os = place(objective_scratch_bytes(V, r));
+        hipError_t e = hipMalloc((void **)&p->ws, off);
+        if (e != hipSuccess) {
+            st = hip_fail(e, "plan workspace");
+        } else {
+            p->counter = (unsigned long long *)(p->ws + o_cnt);
+            p->inner_total = p->counter + 1;
+            p->dsq = (float *)(p->ws + o_dsq);
+            p->G = (float *)(p->ws + o_G);
+            p->Q = (float *)(p->ws + o_Q);
+            p->gram_scratch = (float *)(p->ws + o_gs);
+            p->P = (float *)(p->ws + o_P);
+            p->obj_out = (double *)(p->ws + o_oo);
+            p->kkt_out = (double *)(p->ws + o_ko);
+            p->kkt_partial = (double *)(p->ws + o_kp);
+            p->obj_scratch = p->ws + o_os;
+        }
+    }
+    if (!st) {
+        hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) st = hip_fail(e, "plan set-up");
+    }
+    if (st) {
+        plan_free(p);
+        return st;
+    }
+    *out = p;
+    return NMF_OK;
+}
+
+extern "C" void nmf_plan_destroy(nmf_plan *p) {
+    if (!p) return;
+    (void)hipDeviceSynchronize();
+    plan_free(p);
+}
+
+namespace nmfi {
+
+static hipEvent_t next_event(nmf_plan *p) {
+    if (p->ev_used == p->ev_pool.size()) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        p->ev_pool.push_back(e);
+    }
+    return p->ev_pool[p->ev_used++];
+}
+
+// records an event pair around a phase when profiling is on
+struct PhaseMark {
+    nmf_plan *p;
+    int phase;
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+    PhaseMark(nmf_plan *p_, int ph, hipStream_t s_) : p(p_), phase(ph), s(s_) {
+        if (p->prof && (a = next_event(p))) (void)hipEventRecord(a, s);
+    }
+    ~PhaseMark() {
+        if (!a) return;
+        hipEvent_t b = next_event(p);
+        if (!b) return;
+        (void)hipEventRecord(b, s);
+        p->pending.push_back({phase, {a, b}});
+    }
+};
+
+static int collect_timers(nmf_plan *p, hipStream_t s) {
+    if (p->pending.empty()) { p->ev_used = 0; return NMF_OK; }
+    NMF_HIP(hipStreamSynchronize(s));
+    for (auto &q : p->pending) {
+        float t = 0.f;
+        NMF_HIP(hipEventElapsedTime(&t, q.second.first, q.second.second));
+        p->ms[q.first] += t;
+        p->calls[q.first] += 1;
+    }
+    p->pending.clear();
+    p->ev_used = 0;
+    return NMF_OK;
+}
+
+// One half-iteration: X (c x r) <- NQP(A'A + 2 l2 I, -(data product) + l1, X)
+static hipError_t half_update(nmf_plan *p, bool h_update, const float *A, float *X, hipStream_t s) {
+    const int64_t k = h_update ? p->m : p->n;   // rows of the fixed factor
+    const int64_t c = h_update ? p->n : p->m;   // NQPs to solve
+    const float l1 = h_update ? p->reg.l1_h : p->reg.l1_w;
+    const float l2 = h_update ? p->reg.l2_h : p->reg.l2_w;
+    hipError_t e;
+    {
+        PhaseMark pm(p, NMF_PHASE_GRAM, s);
+        e = launch_gram(A, k, p->r, l2, p->opt.precision, p->G, p->gram_scratch, s);
+    }
+    if (e == hipSuccess) {
+        PhaseMark pm(p, NMF_PHASE_RESCALE, s);
+        e = launch_rescale(p->G, p->r, p->R, p->Q, p->dsq, p->counter, s);
+    }
+    if (e != hipSuccess) return e;
+    {
+        PhaseMark pm(p, NMF_PHASE_PRODUCT, s);
+        if (p->V.kind == NMF_CSR) {
+            if (h_update) e = launch_spmm(p->sp_h, p->t_colidx, p->t_vals, A, p->r, p->P, p->sp_partial, s);
+            else e = launch_spmm(p->sp_w, p->V.colidx, p->V.vals, A, p->r, p->P, p->sp_partial, s);
+        } else {
+            const bool bf = p->V16 != nullptr;
+            e = launch_dense_product(bf ? (const void *)p->V16 : (const void *)p->V.dense, bf, p->m, p->n,
+                                     bf ? p->n : p->V.ld, h_update ? 0 : 1, A, p->r, p->P,
+                                     p->dense_scratch, s);
+        }
+    }
+    if (e != hipSuccess) return e;
+    NqpParams q{};
+    q.Q = p->Q; q.dsq = p->dsq; q.P = p->P; q.hsign = -1.f; q.hadd = l1; q.X = X;
+    q.ncols = c; q.r = p->r; q.ldp = p->r; q.ldx = p->r;
+    q.max_inner = p->opt.max_inner; q.eps = p->opt.eps; q.ls_guard = p->opt.ls_guard ? 1 : 0;
+    q.cold = 0; q.iters = nullptr; q.counter = p->counter; q.inner_total = p->inner_total;
+    PhaseMark pm(p, NMF_PHASE_SOLVE, s);
+    return launch_nqp(p->var, q, s);
+}
+
+static int objective_now(nmf_plan *p, const float *W, const float *Ht, double out[2], hipStream_t s) {
+    NMF_HIP(launch_objective(&p->V, p->r, &p->reg, W, Ht, p->obj_scratch, p->obj_out, s));
+    NMF_HIP(hipMemcpyAsync(out, p->obj_out, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    NMF_HIP(hipStreamSynchronize(s));
+    return NMF_OK;
+}
+
+}  // namespace nmfi
+
+extern "C" int nmf_plan_run(nmf_plan *p, float *W, float *Ht, int32_t outer, double *trace,
+                            nmf_stats *stats, void *stream) {
+    if (!p) return fail(NMF_E_INVAL, "plan is NULL");
+    if (!W || !Ht) return fail(NMF_E_INVAL, "W and Ht must be non-NULL");
+    if (outer < 0) return fail(NMF_E_INVAL, "outer must be >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    if (p->opt.check_finite) {
+        int st = check_values(W, p->m * p->r, 1, s);
+        if (!st) st = check_values(Ht, p->n * p->r, 1, s);
+        if (st) return st;
+    }
+    NMF_HIP(launch_zero_u64(p->inner_total, 1, s));
+    double ob[2] = {NAN, NAN};
+    const int every = p->opt.objective_every > 0 ? p->opt.objective_every : 1;
+    if (trace) {
+        for (int t = 0; t <= outer; t++) trace[t] = NAN;
+        if (int st = objective_now(p, W, Ht, ob, s)) return st;
+        trace[0] = ob[0];
+    }
+    double kkt_h = NAN, kkt_w = NAN;
+    for (int t = 0; t < outer; t++) {
+        const bool last = t == outer - 1;
+        hipError_t e = half_update(p, true, W, Ht, s);
+        if (e == hipSuccess && stats && last)
+            e = launch_kkt(p->G, p->r, p->P, -1.f, p->reg.l1_h, Ht, p->n, p->kkt_partial, p->kkt_out, s);
+        if (e == hipSuccess) e = half_update(p, false, Ht, W, s);
+        if (e == hipSuccess && stats && last)
+            e = launch_kkt(p->G, p->r, p->P, -1.f, p->reg.l1_w, W, p->m, p->kkt_partial, p->kkt_out + 1, s);
+        if (e != hipSuccess) return hip_fail(e, "outer iteration");
+        if (trace && ((t + 1) % every == 0 || last)) {
+            if (int st = objective_now(p, W, Ht, ob, s)) return st;
+            trace[t + 1] = ob[0];
+        }
+    }
+    if (int st = collect_timers(p, s)) return st;
+    if (stats) {
+        if (!trace || outer == 0) {
+            if (int st = objective_now(p, W, Ht, ob, s)) return st;
+        }
+        unsigned long long inner = 0;
+        double kk[2] = {NAN, NAN};
+        NMF_HIP(hipMemcpyAsync(&inner, p->inner_total, sizeof inner, hipMemcpyDeviceToHost, s));
+        if (outer > 0) NMF_HIP(hipMemcpyAsync(kk, p->kkt_out, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        NMF_HIP(hipStreamSynchronize(s));
+        kkt_h = kk[0]; kkt_w = kk[1];
+        stats->loss = ob[0];
+        stats->objective = ob[1];
+        stats->kkt_h = kkt_h;
+        stats->kkt_w = kkt_w;
+        stats->inner_total = (int64_t)inner;
+        stats->outer_done = outer;
+        stats->kbar = outer > 0 ? (double)inner / ((double)outer * (double)(p->m + p->n)) : 0.0;
+    }
+    return NMF_OK;
+}
+
+extern "C" int nmf_fit(const nmf_matrix *V, int32_t r, const nmf_reg *reg, const nmf_opts *opt, float *W,
+                       float *Ht, double *trace, nmf_stats *stats, void *stream) {
+    nmf_plan *p = nullptr;
+    if (int st = nmf_plan_create(V, r, reg, opt, &p, stream)) return st;
+    int st = nmf_plan_run(p, W, Ht, opt->max_outer, trace, stats, stream);
+    (void)hipStreamSynchronize((hipStream_t)stream);
+    plan_free(p);
+    return st;
+}
+
+extern "C" int nmf_objective(const nmf_matrix *V, int32_t r, const nmf_reg *reg, const float *W,
+                             const float *Ht, double *loss_host, double *objective_host, void *stream) {
+    if (int st = validate_matrix(V, false)) return st;
+    if (r < 1 || r > NMF_MAX_RANK) return fail(NMF_E_INVAL, "r must be in [1, %d]", NMF_MAX_RANK);
+    if (!reg || !W || !Ht) return fail(NMF_E_INVAL, "reg, W and Ht must be non-NULL");
+    hipStream_t s = (hipStream_t)stream;
+    char *scratch = nullptr;
+    const size_t bytes = objective_scratch_bytes(V, r) + 256;
+    NMF_HIP(hipMallocAsync((void **)&scratch, bytes, s));
+    double *dout = (double *)scratch;
+    hipError_t e = launch_objective(V, r, reg, W, Ht, scratch + 256, dout, s);
+    double h[2] = {NAN, NAN};
+    if (e == hipSuccess) e = hipMemcpyAsync(h, dout, sizeof h, hipMemcpyDeviceToHost, s);
+    (void)hipFreeAsync(scratch, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "nmf_objective");
+    if (loss_host) *loss_host = h[0];
+    if (objective_host) *objective_host = h[1];
+    return NMF_OK;
+}
+
+// ============================================================ fold-in
+struct nmf_basis {
+    float *W = nullptr;  // m x r copy
+    int64_t m = 0;
+    int r = 0;
+    float l1 = 0.f, l2 = 0.f;
+    nmf_opts opt{};
+    NqpVariant var{};
+    int R = 0;
+    char *ws = nullptr;  // G, Q, dsq
+    float *G = nullptr, *Q = nullptr, *dsq = nullptr;
+};
+
+extern "C" int nmf_basis_create(const float *W, int64_t m, int32_t r, float l1, float l2,
+                                const nmf_opts *opt, nmf_basis **out, void *stream) {
+    if (!out) return fail(NMF_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (!W) return fail(NMF_E_INVAL, "W is NULL");
+    if (m < 1) return fail(NMF_E_INVAL, "m must be >= 1");
+    if (r < 1 || r > NMF_MAX_RANK) return fail(NMF_E_INVAL, "r must be in [1, %d]", NMF_MAX_RANK);
+    if (!(l1 >= 0.f) || !(l2 >= 0.f) || !isfinite(l1) || !isfinite(l2))
+        return fail(NMF_E_INVAL, "l1 and l2 must be finite and >= 0");
+    if (int st = validate_opts(opt)) return st;
+    hipStream_t s = (hipStream_t)stream;
+    nmf_basis *b = new nmf_basis();
+    b->m = m; b->r = r; b->l1 = l1; b->l2 = l2; b->opt = *opt;
+    b->var = nqp_pick(r);
+    b->R = b->var.E * b->var.L;
+    const size_t oG = 0, oD = al256((size_t)r * r * 4), oQ = oD + al256(NMF_MAX_RANK * 4),
+                 oS = oQ + al256((size_t)b->R * b->R * 4), total = oS + al256(gram_scratch_bytes(r));
+    hipError_t e = hipMalloc((void **)&b->W, (size_t)m * r * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc((void **)&b->ws, total);
+    if (e == hipSuccess) {
+        b->G = (float *)(b->ws + oG);
+        b->dsq = (float *)(b->ws + oD);
+        b->Q = (float *)(b->ws + oQ);
+        e = hipMemcpyAsync(b->W, W, (size_t)m * r * sizeof(float), hipMemcpyDeviceToDevice, s);
+    }
+    if (e == hipSuccess) e = launch_gram(b->W, m, r, l2, opt->precision, b->G, (float *)(b->ws + oS), s);
+    if (e == hipSuccess) e = launch_rescale(b->G, r, b->R, b->Q, b->dsq, nullptr, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        if (b->W) (void)hipFree(b->W);
+        if (b->ws) (void)hipFree(b->ws);
+        delete b;
+        return hip_fail(e, "nmf_basis_create");
+    }
+    *out = b;
+    return NMF_OK;
+}
+
+extern "C" void nmf_basis_destroy(nmf_basis *b) {
+    if (!b) return;
+    (void)hipDeviceSynchronize();
+    (void)hipFree(b->W);
+    (void)hipFree(b->ws);
+    delete b;
+}
+
+namespace nmfi {
+// Fold-in of c columns whose product rows P (c x r) the caller's stream will
+// produce; returns the P buffer to fill and launches the solve.
+int basis_solve(const nmf_basis *B, const float *P, int64_t c, float *Ht_new, int32_t *iters,
+                unsigned long long *counter, hipStream_t s) {
+    NMF_HIP(launch_zero_u64(counter, 1, s));
+    NqpParams q{};
+    q.Q = B->Q; q.dsq = B->dsq; q.P = P; q.hsign = -1.f; q.hadd = B->l1; q.X = Ht_new;
+    q.ncols = c; q.r = B->r; q.ldp = B->r; q.ldx = B->r;
+    q.max_inner = B->opt.max_inner; q.eps = B->opt.eps; q.ls_guard = B->opt.ls_guard ? 1 : 0;
+    q.cold = 1; q.iters = iters; q.counter = counter; q.inner_total = nullptr;
+    NMF_HIP(launch_nqp(B->var, q, s));
+    return NMF_OK;
+}
+}  // namespace nmfi
+
+extern "C" int nmf_foldin(const nmf_basis *B, const nmf_matrix *Vnew, float *Ht_new, int32_t *iters,
+                          void *stream) {
+    if (!B) return fail(NMF_E_INVAL, "basis is NULL");
+    if (!Vnew || !Ht_new) return fail(NMF_E_INVAL, "Vnew and Ht_new must be non-NULL");
+    if (Vnew->rows != B->m) return fail(NMF_E_INVAL, "Vnew must have m = %lld rows", (long long)B->m);
+    if (Vnew->cols < 0) return fail(NMF_E_INVAL, "Vnew must have >= 0 columns");
+    if (Vnew->cols == 0) return NMF_OK;
+    const int64_t c = Vnew->cols;
+    const int r = B->r;
+    hipStream_t s = (hipStream_t)stream;
+    if (Vnew->kind == NMF_DENSE) {
+        if (!Vnew->dense || Vnew->ld < c) return fail(NMF_E_INVAL, "dense Vnew needs a pointer and ld >= cols");
+    } else if (Vnew->kind == NMF_CSR) {
+        if (!Vnew->t_rowptr || !Vnew->t_colidx || !Vnew->t_vals)
+            return fail(NMF_E_INVAL, "sparse Vnew must be given as CSR(Vnew') (t_* arrays)");
+    } else {
+        return fail(NMF_E_INVAL, "unknown matrix kind");
+    }
+    // per-call workspace: counter, P (c x r), dense scratch
+    const size_t pbytes = al256((size_t)c * r * sizeof(float));
+    const size_t dbytes = Vnew->kind == NMF_DENSE ? dense_scratch_bytes(B->m, c, r) : 0;
+    char *ws = nullptr;
+    NMF_HIP(hipMallocAsync((void **)&ws, 256 + pbytes + dbytes, s));
+    unsigned long long *counter = (unsigned long long *)ws;
+    float *P = (float *)(ws + 256);
+    hipError_t e;
+    if (Vnew->kind == NMF_DENSE)
+        e = launch_dense_product(Vnew->dense, 0, B->m, c, Vnew->ld, 0, B->W, r, P,
+                                 (float *)(ws + 256 + pbytes), s);
+    else
+        e = launch_spmm_rows(Vnew->t_rowptr, c, Vnew->t_colidx, Vnew->t_vals, B->W, r, P, s);
+    int st = NMF_OK;
+    if (e != hipSuccess) st = hip_fail(e, "fold-in product");
+    if (!st) st = basis_solve(B, P, c, Ht_new, iters, counter, s);
+    (void)hipFreeAsync(ws, s);
+    return st;
+}
+
+extern "C" int nmf_plan_profile(nmf_plan *p, int32_t enable) {
+    if (!p) return fail(NMF_E_INVAL, "plan is NULL");
+    p->prof = enable != 0;
+    for (int i = 0; i < NMF_PHASES; i++) { p->ms[i] = 0.0; p->calls[i] = 0; }
+    p->pending.clear();
+    p->ev_used = 0;
+    return NMF_OK;
+}
+
+extern "C" int nmf_plan_timers(const nmf_plan *p, double *ms, int64_t *calls) {
+    if (!p || !ms || !calls) return fail(NMF_E_INVAL, "plan, ms and calls must be non-NULL");
+    for (int i = 0; i < NMF_PHASES; i++) { ms[i] = p->ms[i]; calls[i] = p->calls[i]; }
+    return NMF_OK;
+}

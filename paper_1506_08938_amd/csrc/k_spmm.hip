@@ -1,0 +1,279 @@
+// Sparse data product (Section 4.2: O(r S(mn)) for sparse data): for CSR B,
+// P[row] = sum_t vals[t] * A[colidx[t]] -- one gathered row of the fixed
+// factor A (k x r) per stored entry.  The H-update uses CSR(V') with A = W,
+// the W-update CSR(V) with A = Ht.
+//
+// Work is a list of chunks (row, [start, end)) of at most SPMM_CHUNK entries;
+// one wave per chunk.  A chunk of a row that was split writes its sum to a
+// partial slot and a fix-up kernel adds a split row's slots in chunk order,
+// so results never depend on scheduling.  Lanes are grouped LPN per entry,
+// each lane covering VEC consecutive columns (NV such pieces), so one wave
+// step gathers 64 / LPN entries with full-row contiguous loads.
+#include <algorithm>
+#include <vector>
+
+#include "kernels_common.h"
+#include "nmf_internal.h"
+
+namespace nmfi {
+
+template <int VEC, int LPN, int NV>
+__global__ __launch_bounds__(256) void k_spmm(const SpChunk *__restrict__ chunks, int64_t nchunks,
+                                              const int32_t *__restrict__ colidx,
+                                              const float *__restrict__ vals,
+                                              const float *__restrict__ A, int r,
+                                              float *__restrict__ P, float *__restrict__ partial) {
+    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (w >= nchunks) return;
+    const SpChunk c = chunks[w];
+    const int lane = threadIdx.x & 63;
+    constexpr int NPW = 64 / LPN;
+    constexpr int U = VEC == 4 ? 4 : 8;
+    const int slot = lane / LPN, part = lane % LPN;
+    float acc[NV][VEC];
+#pragma unroll
+    for (int q = 0; q < NV; q++)
+#pragma unroll
+        for (int v = 0; v < VEC; v++) acc[q][v] = 0.f;
+
+    for (int t = c.start + slot; t < c.end; t += NPW * U) {
+        int ci[U];
+        float cv[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int tt = t + u * NPW;
+            const bool ok = tt < c.end;
+            ci[u] = ok ? colidx[tt] : -1;
+            cv[u] = ok ? vals[tt] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            if (ci[u] < 0) continue;
+            const float *arow = A + (int64_t)ci[u] * r;
+#pragma unroll
+            for (int q = 0; q < NV; q++) {
+                const int col0 = (q * LPN + part) * VEC;
+                if (col0 < r) {
+                    if constexpr (VEC == 4) {
+                        const f32x4 a4 = *(const f32x4 *)(arow + col0);
+#pragma unroll
+                        for (int v = 0; v < 4; v++) acc[q][v] = fmaf(cv[u], a4[v], acc[q][v]);
+                    } else if constexpr (VEC == 2) {
+                        const f32x2 a2 = *(const f32x2 *)(arow + col0);
+                        acc[q][0] = fmaf(cv[u], a2[0], acc[q][0]);
+                        acc[q][1] = fmaf(cv[u], a2[1], acc[q][1]);
+                    } else {
+                        acc[q][0] = fmaf(cv[u], arow[col0], acc[q][0]);
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int off = LPN; off < 64; off <<= 1)
+#pragma unroll
+        for (int q = 0; q < NV; q++)
+#pragma unroll
+            for (int v = 0; v < VEC; v++) acc[q][v] += __shfl_xor(acc[q][v], off);
+    if (slot != 0) return;
+    float *dst = c.dest < 0 ? P + (int64_t)c.row * r : partial + (int64_t)c.dest * r;
+#pragma unroll
+    for (int q = 0; q < NV; q++) {
+        const int col0 = (q * LPN + part) * VEC;
+        if (col0 < r) {
+#pragma unroll
+            for (int v = 0; v < VEC; v++) dst[col0 + v] = acc[q][v];
+        }
+    }
+}
+
+// P[row] = sum of the row's partial slots in chunk order
+__global__ __launch_bounds__(128) void k_spmm_fixup(const SpSplit *__restrict__ splits,
+                                                    const float *__restrict__ partial, int r,
+                                                    float *__restrict__ P) {
+    const SpSplit s = splits[blockIdx.x];
+    for (int a = threadIdx.x; a < r; a += 128) {
+        float acc = 0.f;
+        for (int c = 0; c < s.count; c++) acc += partial[(int64_t)(s.first + c) * r + a];
+        P[(int64_t)s.row * r + a] = acc;
+    }
+}
+
+template <int VEC, int LPN, int NV>
+static void launch_spmm_t(const SpmmPlan &pl, const int32_t *colidx, const float *vals,
+                          const float *A, int r, float *P, float *partial, hipStream_t s) {
+    const unsigned blocks = (unsigned)((pl.nchunks + 3) / 4);
+    hipLaunchKernelGGL((k_spmm<VEC, LPN, NV>), dim3(blocks), dim3(256), 0, s, pl.chunks,
+                       pl.nchunks, colidx, vals, A, r, P, partial);
+}
+
+static int pow2_at_least(int v) {
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+hipError_t launch_spmm(const SpmmPlan &pl, const int32_t *colidx, const float *vals, const float *A,
+                       int r, float *P, float *partial, hipStream_t s) {
+    if (pl.nrows == 0) return hipSuccess;
+    if (pl.nchunks > 0) {
+        if (r % 4 == 0) {
+            switch (pow2_at_least(r / 4)) {
+            case 1: launch_spmm_t<4, 1, 1>(pl, colidx, vals, A, r, P, partial, s); break;
+            case 2: launch_spmm_t<4, 2, 1>(pl, colidx, vals, A, r, P, partial, s); break;
+            case 4: launch_spmm_t<4, 4, 1>(pl, colidx, vals, A, r, P, partial, s); break;
+            case 8: launch_spmm_t<4, 8, 1>(pl, colidx, vals, A, r, P, partial, s); break;
+            case 16: launch_spmm_t<4, 16, 1>(pl, colidx, vals, A, r, P, partial, s); break;
+            default: launch_spmm_t<4, 32, 1>(pl, colidx, vals, A, r, P, partial, s); break;
+            }
+        } else if (r % 2 == 0) {
+            switch (pow2_at_least(r / 2)) {
+            case 1: launch_spmm_t<2, 1, 1>(pl, colidx, vals, A, r, P, partial, s); break;
+            case 2: launch_spmm_t<2, 2, 1>(pl, colidx, vals, A, r, P, partial, s); break;
+            case 4: launch_spmm_t<2, 4, 1>(pl, colidx, vals, A, r, P, partial, s); break;
+            case 8: launch_spmm_t<2, 8, 1>(pl, colidx, vals, A, r, P, partial, s); break;
+            case 16: launch_spmm_t<2, 16, 1>(pl, colidx, vals, A, r, P, partial, s); break;
+            case 32: launch_spmm_t<2, 32, 1>(pl, colidx, vals, A, r, P, partial, s); break;
+            default: launch_spmm_t<2, 64, 1>(pl, colidx, vals, A, r, P, partial, s); break;
+            }
+        } else if (r <= 64) {
+            switch (pow2_at_least(r)) {
+            case 1: launch_spmm_t<1, 1, 1>(pl, colidx, vals, A, r, P, partial, s); break;
+            case 2: launch_spmm_t<1, 2, 1>(pl, colidx, vals, A, r, P, partial, s); break;
+            case 4: launch_spmm_t<1, 4, 1>(pl, colidx, vals, A, r, P, partial, s); break;
+            case 8: launch_spmm_t<1, 8, 1>(pl, colidx, vals, A, r, P, partial, s); break;
+            case 16: launch_spmm_t<1, 16, 1>(pl, colidx, vals, A, r, P, partial, s); break;
+            case 32: launch_spmm_t<1, 32, 1>(pl, colidx, vals, A, r, P, partial, s); break;
+            default: launch_spmm_t<1, 64, 1>(pl, colidx, vals, A, r, P, partial, s); break;
+            }
+        } else {
+            launch_spmm_t<1, 64, 2>(pl, colidx, vals, A, r, P, partial, s);
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (pl.nsplits > 0) {
+        hipLaunchKernelGGL(k_spmm_fixup, dim3((unsigned)pl.nsplits), dim3(128), 0, s, pl.splits,
+                           partial, r, P);
+        return hipGetLastError();
+    }
+    return hipSuccess;
+}
+
+// Chunk list of a CSR matrix from its host row pointers.
+int build_spmm_plan(const std::vector<int32_t> &rowptr, SpmmPlan *pl, hipStream_t s) {
+    const int64_t nrows = (int64_t)rowptr.size() - 1;
+    std::vector<SpChunk> ch;
+    std::vector<SpSplit> sp;
+    ch.reserve(nrows + 16);
+    int32_t slots = 0;
+    for (int64_t i = 0; i < nrows; i++) {
+        const int32_t b = rowptr[i], e = rowptr[i + 1];
+        const int32_t len = e - b;
+        if (len <= SPMM_CHUNK) {
+            ch.push_back({(int32_t)i, b, e, -1});
+        } else {
+            const int32_t n = (len + SPMM_CHUNK - 1) / SPMM_CHUNK;
+            sp.push_back({(int32_t)i, slots, n});
+            for (int32_t c = 0; c < n; c++) {
+                const int32_t cb = b + c * SPMM_CHUNK;
+                ch.push_back({(int32_t)i, cb, std::min(e, cb + SPMM_CHUNK), slots++});
+            }
+        }
+    }
+    // long rows' chunks first: they are the stragglers
+    std::stable_partition(ch.begin(), ch.end(), [](const SpChunk &c) { return c.dest >= 0; });
+    pl->nrows = nrows;
+    pl->nchunks = (int64_t)ch.size();
+    pl->nsplits = (int64_t)sp.size();
+    pl->nslots = slots;
+    pl->chunks = nullptr;
+    pl->splits = nullptr;
+    if (!ch.empty()) {
+        NMF_HIP(hipMalloc((void **)&pl->chunks, ch.size() * sizeof(SpChunk)));
+        NMF_HIP(hipMemcpyAsync(pl->chunks, ch.data(), ch.size() * sizeof(SpChunk),
+                               hipMemcpyHostToDevice, s));
+    }
+    if (!sp.empty()) {
+        NMF_HIP(hipMalloc((void **)&pl->splits, sp.size() * sizeof(SpSplit)));
+        NMF_HIP(hipMemcpyAsync(pl->splits, sp.data(), sp.size() * sizeof(SpSplit),
+                               hipMemcpyHostToDevice, s));
+    }
+    NMF_HIP(hipStreamSynchronize(s));
+    return NMF_OK;
+}
+
+void free_spmm_plan(SpmmPlan *pl) {
+    if (pl->chunks) (void)hipFree(pl->chunks);
+    if (pl->splits) (void)hipFree(pl->splits);
+    pl->chunks = nullptr;
+    pl->splits = nullptr;
+}
+
+}  // namespace nmfi
+
+namespace nmfi {
+
+// one wave per row, rows read straight from the row pointers
+template <int VEC, int LPN, int NV>
+__global__ __launch_bounds__(256) void k_spmm_rows(const int32_t *__restrict__ rowptr, int64_t nrows,
+                                                   const int32_t *__restrict__ colidx,
+                                                   const float *__restrict__ vals,
+                                                   const float *__restrict__ A, int r,
+                                                   float *__restrict__ P) {
+    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (w >= nrows) return;
+    const int lane = threadIdx.x & 63;
+    constexpr int NPW = 64 / LPN;
+    const int slot = lane / LPN, part = lane % LPN;
+    float acc[NV][VEC];
+#pragma unroll
+    for (int q = 0; q < NV; q++)
+#pragma unroll
+        for (int v = 0; v < VEC; v++) acc[q][v] = 0.f;
+    const int end = rowptr[w + 1];
+    for (int t = rowptr[w] + slot; t < end; t += NPW) {
+        const int ci = colidx[t];
+        const float cv = vals[t];
+        const float *arow = A + (int64_t)ci * r;
+#pragma unroll
+        for (int q = 0; q < NV; q++) {
+            const int col0 = (q * LPN + part) * VEC;
+            if (col0 < r) {
+#pragma unroll
+                for (int v = 0; v < VEC; v++) acc[q][v] = fmaf(cv, arow[col0 + v], acc[q][v]);
+            }
+        }
+    }
+#pragma unroll
+    for (int off = LPN; off < 64; off <<= 1)
+#pragma unroll
+        for (int q = 0; q < NV; q++)
+#pragma unroll
+            for (int v = 0; v < VEC; v++) acc[q][v] += __shfl_xor(acc[q][v], off);
+    if (slot != 0) return;
+    float *dst = P + w * r;
+#pragma unroll
+    for (int q = 0; q < NV; q++) {
+        const int col0 = (q * LPN + part) * VEC;
+        if (col0 < r) {
+#pragma unroll
+            for (int v = 0; v < VEC; v++) dst[col0 + v] = acc[q][v];
+        }
+    }
+}
+
+hipError_t launch_spmm_rows(const int32_t *rowptr, int64_t nrows, const int32_t *colidx,
+                            const float *vals, const float *A, int r, float *P, hipStream_t s) {
+    if (nrows <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((nrows + 3) / 4)), blk(256);
+    if (r % 4 == 0 && r <= 128)
+        hipLaunchKernelGGL((k_spmm_rows<4, 32, 1>), grid, blk, 0, s, rowptr, nrows, colidx, vals, A, r, P);
+    else if (r <= 64)
+        hipLaunchKernelGGL((k_spmm_rows<1, 64, 1>), grid, blk, 0, s, rowptr, nrows, colidx, vals, A, r, P);
+    else
+        hipLaunchKernelGGL((k_spmm_rows<1, 64, 2>), grid, blk, 0, s, rowptr, nrows, colidx, vals, A, r, P);
+    return hipGetLastError();
+}
+
+}  // namespace nmfi

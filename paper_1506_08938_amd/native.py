@@ -21,7 +21,8 @@ MAX_RANK = 128
 # every entry point include/nmf.h declares
 EXPORTS = [
     "nmf_default_opts", "nmf_last_error", "nnls_solve_batch", "nmf_gram", "nmf_product",
-    "nmf_plan_create", "nmf_plan_run", "nmf_plan_destroy", "nmf_fit", "nmf_objective",
+    "nmf_plan_create", "nmf_plan_run", "nmf_plan_destroy", "nmf_plan_profile", "nmf_plan_timers",
+    "nmf_fit", "nmf_objective",
     "nmf_basis_create", "nmf_foldin", "nmf_basis_destroy",
 ]
 
@@ -88,6 +89,9 @@ def lib():
                                       ctypes.POINTER(_vp), _vp]
         L.nmf_plan_run.argtypes = [_vp, _vp, _vp, ctypes.c_int32, _vp, ctypes.POINTER(NmfStats),
                                    _vp]
+        L.nmf_plan_profile.argtypes = [_vp, ctypes.c_int32]
+        L.nmf_plan_timers.argtypes = [_vp, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_int64)]
         L.nmf_plan_destroy.argtypes = [_vp]
         L.nmf_plan_destroy.restype = None
         L.nmf_fit.argtypes = [ctypes.POINTER(NmfMatrix), ctypes.c_int32, ctypes.POINTER(NmfReg),
@@ -261,6 +265,16 @@ class Plan:
                                  None if st is None else ctypes.byref(st), stream_ptr()))
         return trace, (st.as_dict() if st is not None else None)
 
+    PHASES = ("gram", "rescale", "product", "solve")
+
+    def profile(self, enable=True):
+        check(lib().nmf_plan_profile(self.h, 1 if enable else 0))
+
+    def timers(self):
+        ms = (ctypes.c_double * 4)(); calls = (ctypes.c_int64 * 4)()
+        check(lib().nmf_plan_timers(self.h, ms, calls))
+        return {k: (ms[i], calls[i]) for i, k in enumerate(self.PHASES)}
+
     def close(self):
         if self.h:
             lib().nmf_plan_destroy(self.h)
@@ -309,7 +323,7 @@ class Basis:
 
     def foldin(self, Vnew: DeviceMatrix, out=None, iters=None):
         torch = _torch()
-        c = Vnew.m.cols if Vnew.m.kind == NMF_DENSE else Vnew.m.rows
+        c = Vnew.m.cols
         if out is None:
             out = torch.empty((c, self.r), dtype=torch.float32, device="cuda")
         _dev(out, torch.float32, "Ht_new", (c, self.r))
