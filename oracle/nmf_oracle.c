@@ -232,15 +232,21 @@ long oracle_nqp_batch(int r, long ncols, const double *H, const double *h, doubl
  *   min_x 0.5||B_j - A x||^2 + l1 1'x + l2 ||x||^2,
  * an NQP with H = A'A + 2 l2 I and h = -A'B_j + l1 1. */
 
-/* G = A'A + 2 l2 I   (A k x r row-major, G r x r) */
+/* G = A'A + 2 l2 I   (A k x r row-major, G r x r).  Each entry is summed in
+ * ascending t; the t loop sits outside the (a, b) loops only so that rows of
+ * A are read contiguously (the same additions in the same order). */
 void oracle_gram(long k, int r, const double *A, double l2, double *G) {
 #pragma omp parallel for schedule(static)
-    for (int a = 0; a < r; a++)
-        for (int b = 0; b < r; b++) {
-            double s = 0.0;
-            for (long t = 0; t < k; t++) s += A[(size_t)t * r + a] * A[(size_t)t * r + b];
-            G[(size_t)a * r + b] = s + (a == b ? 2.0 * l2 : 0.0);
+    for (int a = 0; a < r; a++) {
+        double *row = G + (size_t)a * r;
+        for (int b = 0; b < r; b++) row[b] = 0.0;
+        for (long t = 0; t < k; t++) {
+            const double at = A[(size_t)t * r + a];
+            const double *At = A + (size_t)t * r;
+            for (int b = 0; b < r; b++) row[b] += at * At[b];
         }
+        row[a] += 2.0 * l2;
+    }
 }
 
 /* P = (A'B)' : c x r, P[j][a] = sum_t A[t][a] B[t][j].
