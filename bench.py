@@ -14,9 +14,11 @@ is counted per solved column as  init(r) = r^2 + 5r  plus, per inner
 iteration,  iter(r) = 7r^2 + 13r  lane operations, against
 the VALU issue rate of 256 CUs x 64 lanes x 2.4 GHz.  The CPU baseline is
 the FP64 oracle timed on the host cores for one outer iteration of the same
-workload from the same start point.
+workload from the same start point (its first --cpu-iters outer
+iterations).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--cpu-iters T]
+       python bench.py --calibrate-copy   (1 GiB device copy, for counter scaling)
 """
 import argparse
 import json
@@ -49,20 +51,33 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
-    ap.add_argument("--profile-steps", type=int, default=0,
-                    help="run only this many steps and print nothing else (for rocprofv3)")
+    ap.add_argument("--cpu-iters", type=int, default=8,
+                    help="outer iterations of the CPU-oracle sample")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only copy a 1 GiB device buffer (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU sharding is a design, not part of this build)", file=sys.stderr)
         sys.exit(2)
 
+    log("[bench] importing torch")
     import numpy as np
     import torch
+
+    if args.calibrate_copy:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("[bench] copied 1 GiB (read 1 GiB, write 1 GiB)")
+        return
 
     from paper_1506_08938_amd import native, synth
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    log("[bench] generating the sparse workload")
     t_gen = time.perf_counter()
     wl = synth.workload3()
     V = wl["V"]
@@ -78,12 +93,6 @@ def main():
     Ht = torch.from_numpy(wl["Ht0"]).cuda()
     torch.cuda.synchronize()
     log("[bench] plan ready")
-
-    if args.profile_steps:
-        plan.run(W, Ht, args.profile_steps)
-        torch.cuda.synchronize()
-        log("[bench] profile steps done")
-        return
 
     for _ in range(args.warmup):
         plan.run(W, Ht, 1)
@@ -149,20 +158,21 @@ def main():
     if not args.no_cpu:
         import oracle
         cores = oracle.num_threads()
-        log(f"[bench] CPU oracle: one outer iteration on {cores} threads")
+        T_cpu = args.cpu_iters
+        log(f"[bench] CPU oracle: {T_cpu} outer iterations on {cores} threads")
         tc = time.perf_counter()
-        res = oracle.nmf_fit(V, r, wl["reg"], wl["W0"], wl["Ht0"], T=1, max_inner=100,
+        res = oracle.nmf_fit(V, r, wl["reg"], wl["W0"], wl["Ht0"], T=T_cpu, max_inner=100,
                              eps=1e-3, ls_guard=1, want_trace=False)
         tcpu = time.perf_counter() - tc
-        kbar_cpu = res["inner"].sum() / (m + n)
+        kbar_cpu = res["inner"].sum() / (T_cpu * (m + n))
         out["cpu_baseline"] = {
-            "value": (m + n) / tcpu,
+            "value": T_cpu * (m + n) / tcpu,
             "unit": "column NNLS solves/s",
             "cores": cores,
             "kind": "oracle",
-            "sample": f"one full outer iteration ({m + n} column NQP solves plus the Gram "
-                      f"and CSR products, FP64) of the same workload from the same start "
-                      f"point; {tcpu:.1f}s; kbar {kbar_cpu:.3f}",
+            "sample": f"the first {T_cpu} outer iterations ({T_cpu * (m + n)} column NQP solves "
+                      f"plus the Gram and CSR products, FP64) of the same workload from the same "
+                      f"start point; {tcpu:.1f}s; kbar {kbar_cpu:.3f}",
         }
         log(f"[bench] CPU oracle {tcpu:.1f}s")
     print(json.dumps(out), flush=True)

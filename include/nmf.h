@@ -192,6 +192,29 @@ NMF_API int nmf_fit(const nmf_matrix *V, int32_t r, const nmf_reg *reg, const nm
 NMF_API int nmf_objective(const nmf_matrix *V, int32_t r, const nmf_reg *reg, const float *W,
                   const float *Ht, double *loss_host, double *objective_host, void *stream);
 
+/* ---------------------------------------------------------------- batched
+ * Many independent NMF problems of uneven sizes, each fitted as nmf_fit does
+ * (Algorithm 2 with the regularised NQPs of Section 3.5), run together: each
+ * phase of a half-iteration is one launch across all problems, and all
+ * opt->max_outer outer iterations are captured in one hipGraph launched once.
+ * A problem's result does not depend on the other problems in the batch.
+ *   probs       HOST array of `count` problems; V dense (m x n) on the device,
+ *               r in [1, NMF_MAX_RANK], W (m x r) and Ht (n x r) device
+ *               start points, overwritten with the results.
+ *   per_problem optional HOST array of `count` statistics (loss, objective,
+ *               kbar, inner_total; KKT fields are NaN).
+ * Synchronises `stream`. */
+typedef struct {
+    nmf_matrix V;
+    int32_t r;
+    nmf_reg reg;
+    float *W;
+    float *Ht;
+} nmf_problem;
+
+NMF_API int nmf_fit_batched(int32_t count, const nmf_problem *probs, const nmf_opts *opt,
+                            nmf_stats *per_problem, void *stream);
+
 /* ---------------------------------------------------------------- fold-in
  * The E-step alone against a resident basis (Section 3.1: the new columns'
  * coefficients F+ in the space of the learned components): for every column
@@ -208,6 +231,48 @@ NMF_API int nmf_basis_create(const float *W, int64_t m, int32_t r, float l1, flo
 NMF_API int nmf_foldin(const nmf_basis *B, const nmf_matrix *Vnew, float *Ht_new, int32_t *iters,
                void *stream);
 NMF_API void nmf_basis_destroy(nmf_basis *B);
+
+/* ---------------------------------------------------------------- serving
+ * A request loop over a resident basis: fold-in requests (the E-step of
+ * nmf_foldin for new columns) and small full fits (nmf_fit), continuously
+ * batched.  max_slots worker threads each own a stream; each admits work
+ * from the head of the arrival-ordered queue while the HBM footprint of the
+ * admitted work stays within hbm_budget bytes, packing consecutive fold-in
+ * requests (up to max_batch_cols columns) into one batch with a single solve
+ * launch; a fit request runs alone on its slot.  Requests arriving while
+ * others run are picked up by the next free slot, so batches overlap on the
+ * device.  A request's result does not depend on what it is batched with.
+ * Request memory is the caller's (device pointers): its inputs must be
+ * written before submission (workers run on their own streams, unordered with
+ * the caller's) and it must stay valid until the request is done.  Fold-in requests use the basis' options; fit requests
+ * carry their own (max_outer, ...). */
+enum { NMF_REQ_FOLDIN = 0, NMF_REQ_FIT = 1 };
+
+typedef struct {
+    int32_t kind;
+    nmf_matrix V;    /* fold-in: Vnew (m x c), dense or CSR(Vnew') in t_*; fit: dense V */
+    float *out;      /* fold-in: c x r result (device) */
+    int32_t *iters;  /* fold-in: optional device int32[c] */
+    int32_t r;       /* fit: rank */
+    nmf_reg reg;     /* fit */
+    nmf_opts fit_opts; /* fit */
+    float *W, *Ht;   /* fit: start points, overwritten with the results */
+} nmf_request;
+
+typedef struct nmf_server nmf_server;
+
+NMF_API int nmf_server_create(const nmf_basis *B, size_t hbm_budget, int32_t max_slots,
+                              int64_t max_batch_cols, nmf_server **out);
+/* Queues a request; NMF_E_BUSY iff its footprint exceeds the whole budget. */
+NMF_API int nmf_server_submit(nmf_server *s, const nmf_request *req, uint64_t *ticket);
+/* *done = 1 once finished; latency_ms (optional) = completion - submission.
+ * Returns the request's status once done. */
+NMF_API int nmf_server_poll(nmf_server *s, uint64_t ticket, int32_t *done, double *latency_ms);
+/* Blocks until the request (ticket 0: every request submitted so far) is done. */
+NMF_API int nmf_server_wait(nmf_server *s, uint64_t ticket, double *latency_ms);
+NMF_API int nmf_server_stats(nmf_server *s, int64_t *completed, int64_t *columns, int64_t *batches);
+/* Finishes the queued work, stops the workers and frees the server. */
+NMF_API void nmf_server_destroy(nmf_server *s);
 
 #ifdef __cplusplus
 }

@@ -28,6 +28,11 @@ FLAGS = [
 ]
 
 
+# The solve kernels work on finite values only: IEEE mode off lets min/max map
+# to single v_min/v_max instructions (no NaN quieting).
+PER_FILE = {"k_nqp_": ["-fno-honor-nans", "-mno-amdgpu-ieee"]}
+
+
 def _headers():
     return glob.glob(os.path.join(CSRC, "*.h")) + glob.glob(os.path.join(INCLUDE, "*.h"))
 
@@ -38,7 +43,8 @@ def _compile(src: str, incremental: bool) -> str:
         newest = max(os.path.getmtime(p) for p in [src] + _headers())
         if os.path.getmtime(obj) >= newest:
             return obj
-    cmd = [HIPCC] + FLAGS + ["-DNMF_BUILDING_LIBRARY", "-c", src, "-o", obj + ".tmp"]
+    extra = [f for key, fl in PER_FILE.items() if os.path.basename(src).startswith(key) for f in fl]
+    cmd = [HIPCC] + FLAGS + extra + ["-DNMF_BUILDING_LIBRARY", "-c", src, "-o", obj + ".tmp"]
     res = subprocess.run(cmd, capture_output=True, text=True)
     err = "\n".join(l for l in res.stderr.splitlines() if "packed-fp32-ops" not in l)
     if res.returncode != 0:

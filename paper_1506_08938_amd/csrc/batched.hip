@@ -1,0 +1,263 @@
+// Batched fit of many independent, unevenly sized dense NMF problems
+// (Algorithm 2 on each, with the regularised NQPs of Section 3.5).
+//
+// Every phase of a half-iteration is one launch across all problems: the
+// Gram partials (work item = problem x 512 rows), the Gram finish (one block
+// per problem), the data product (work item = problem x 64 output rows), and
+// one persistent solve per kernel variant whose blocks take (problem, column
+// range) chunks from a queue.  All max_outer outer iterations are captured
+// into one hipGraph and launched once.  Problems only ever read their own
+// buffers, so a problem's result does not depend on the batch it runs in.
+#include <math.h>
+
+#include <map>
+#include <vector>
+
+#include "nmf_internal.h"
+
+using namespace nmfi;
+
+namespace {
+
+size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+struct HalfLists {
+    std::vector<BItem> gram_items, prod_items, red_items;
+    std::vector<BGramProb> gram;
+    std::vector<BProdProb> prod;
+    std::vector<BSolveProb> solve;
+    std::map<std::pair<int, int>, std::vector<BSolveChunk>> chunks;  // per (E, L)
+};
+
+struct DevHalf {
+    BItem *gram_items = nullptr, *prod_items = nullptr, *red_items = nullptr;
+    BGramProb *gram = nullptr;
+    BProdProb *prod = nullptr;
+    BSolveProb *solve = nullptr;
+    std::vector<std::pair<NqpVariant, std::pair<BSolveChunk *, int>>> groups;
+    int64_t n_gram_items = 0, n_prod_items = 0, n_red_items = 0;
+};
+
+template <class T>
+int upload(const std::vector<T> &v, T **dst, char *&cursor, hipStream_t s) {
+    *dst = (T *)cursor;
+    cursor += al256(v.size() * sizeof(T) + 1);
+    if (!v.empty()) NMF_HIP(hipMemcpyAsync(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    return NMF_OK;
+}
+
+}  // namespace
+
+extern "C" int nmf_fit_batched(int32_t count, const nmf_problem *probs, const nmf_opts *opt,
+                               nmf_stats *per_problem, void *stream) {
+    if (count < 0) return fail(NMF_E_INVAL, "count must be >= 0");
+    if (count == 0) return NMF_OK;
+    if (!probs) return fail(NMF_E_INVAL, "probs is NULL");
+    if (int st = validate_opts(opt)) return st;
+    if (opt->max_outer < 0) return fail(NMF_E_INVAL, "max_outer must be >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    const bool bf16 = opt->precision == NMF_BF16;
+    int ntmax = 1;
+    for (int p = 0; p < count; p++) {
+        const nmf_problem &q = probs[p];
+        if (q.V.kind != NMF_DENSE)
+            return fail(NMF_E_UNSUPPORTED, "problem %d: the batched fit takes dense V", p);
+        if (q.V.rows < 1 || q.V.cols < 1 || !q.V.dense || q.V.ld < q.V.cols)
+            return fail(NMF_E_INVAL, "problem %d: bad dense V", p);
+        if (q.r < 1 || q.r > NMF_MAX_RANK) return fail(NMF_E_INVAL, "problem %d: r out of range", p);
+        if (!q.W || !q.Ht) return fail(NMF_E_INVAL, "problem %d: W and Ht must be non-NULL", p);
+        const float rg[4] = {q.reg.l1_w, q.reg.l2_w, q.reg.l1_h, q.reg.l2_h};
+        for (float v : rg)
+            if (!(v >= 0.f) || !isfinite(v)) return fail(NMF_E_INVAL, "problem %d: bad regularisation", p);
+        const int nt = (q.r + 31) / 32;
+        if (nt > ntmax) ntmax = nt;
+    }
+
+    // ---------------------------------------------------------------- buffers
+    struct Slot {
+        size_t G, part, P, V16, inner, kpart[2];
+    };
+    std::vector<Slot> slot(count);
+    size_t off = 0;
+    auto place = [&](size_t bytes) { size_t o = off; off += al256(bytes); return o; };
+    for (int p = 0; p < count; p++) {
+        const nmf_problem &q = probs[p];
+        const int64_t m = q.V.rows, n = q.V.cols, r = q.r;
+        slot[p].G = place((size_t)r * r * 4);
+        slot[p].part = place(std::max(bgram_partial_floats(q.r, m), bgram_partial_floats(q.r, n)) * 4);
+        slot[p].P = place((size_t)std::max(m, n) * r * 4);
+        slot[p].V16 = bf16 ? place((size_t)m * n * 2) : 0;
+        slot[p].inner = place(8);
+        for (int h = 0; h < 2; h++) {  // split-K partials of each half's product
+            const int64_t C = h == 0 ? n : m, K = h == 0 ? m : n;
+            const int64_t kc = dense_kchunk(C, K);
+            const int64_t ns = (K + kc - 1) / kc;
+            slot[p].kpart[h] = ns > 1 ? place((size_t)ns * C * r * 4) : 0;
+        }
+    }
+    const size_t data_bytes = off;
+
+    // ---------------------------------------------------------------- work lists
+    HalfLists hl[2];  // 0: H-update (A = W, data V'), 1: W-update (A = Ht, data V)
+    char *base = nullptr;  // set after allocation; lists hold offsets until then
+    auto dptr = [&](size_t o) { return (void *)(base + o); };
+    NMF_HIP(hipMalloc((void **)&base, data_bytes + 256));
+    for (int h = 0; h < 2; h++) {
+        for (int p = 0; p < count; p++) {
+            const nmf_problem &q = probs[p];
+            const int64_t m = q.V.rows, n = q.V.cols;
+            const int r = q.r;
+            const bool H = h == 0;
+            const int64_t k = H ? m : n, C = H ? n : m;
+            const float *A = H ? q.W : q.Ht;
+            BGramProb g{A, k, r, H ? q.reg.l2_h : q.reg.l2_w, (float *)dptr(slot[p].part),
+                        (float *)dptr(slot[p].G), (int)((k + BGRAM_ROWS - 1) / BGRAM_ROWS)};
+            hl[h].gram.push_back(g);
+            for (int c = 0; c < g.nchunks; c++) hl[h].gram_items.push_back({p, c});
+            const void *V = bf16 ? dptr(slot[p].V16) : (const void *)q.V.dense;
+            const int64_t kc = dense_kchunk(C, k);
+            const int ns = (int)((k + kc - 1) / kc);
+            BProdProb pr{V, bf16 ? n : q.V.ld, C, k, A, r, (float *)dptr(slot[p].P),
+                         ns > 1 ? (float *)dptr(slot[p].kpart[h]) : nullptr, kc, ns};
+            hl[h].prod.push_back(pr);
+            for (int64_t cb = 0; cb < (C + 63) / 64; cb++)
+                for (int sl = 0; sl < ns; sl++) hl[h].prod_items.push_back({p, (int32_t)(cb * ns + sl)});
+            if (ns > 1)
+                for (int64_t eb = 0; eb < (C * r + 4095) / 4096; eb++) hl[h].red_items.push_back({p, (int32_t)eb});
+            BSolveProb sv{(const float *)dptr(slot[p].G), (const float *)dptr(slot[p].P), H ? q.Ht : q.W,
+                          r, H ? q.reg.l1_h : q.reg.l1_w, (unsigned long long *)dptr(slot[p].inner),
+                          nullptr, 0};
+            hl[h].solve.push_back(sv);
+            const NqpVariant v = nqp_pick(r);
+            const int chunk = 4 * (64 / v.L) * 4;  // four trips of every lane group of a block
+            auto &lst = hl[h].chunks[{v.E, v.L}];
+            for (int64_t c0 = 0; c0 < C; c0 += chunk)
+                lst.push_back({p, (int32_t)c0, (int32_t)std::min<int64_t>(C, c0 + chunk)});
+        }
+    }
+    // device copies of the lists (one allocation)
+    size_t list_bytes = 0;
+    for (int h = 0; h < 2; h++) {
+        list_bytes += al256(hl[h].gram_items.size() * sizeof(BItem) + 1) + al256(hl[h].prod_items.size() * sizeof(BItem) + 1);
+        list_bytes += al256(hl[h].red_items.size() * sizeof(BItem) + 1);
+        list_bytes += al256(hl[h].gram.size() * sizeof(BGramProb) + 1) + al256(hl[h].prod.size() * sizeof(BProdProb) + 1);
+        list_bytes += al256(hl[h].solve.size() * sizeof(BSolveProb) + 1);
+        for (auto &kv : hl[h].chunks) list_bytes += al256(kv.second.size() * sizeof(BSolveChunk) + 1);
+    }
+    const int ngroups = (int)(hl[0].chunks.size() + hl[1].chunks.size());
+    list_bytes += al256((size_t)(ngroups + 1) * sizeof(unsigned int));
+    char *lists = nullptr;
+    hipError_t e = hipMalloc((void **)&lists, list_bytes + 256);
+    if (e != hipSuccess) { (void)hipFree(base); return hip_fail(e, "batched work lists"); }
+    int st = NMF_OK;
+    DevHalf dh[2];
+    char *cur = lists;
+    for (int h = 0; h < 2 && !st; h++) {
+        st = upload(hl[h].gram_items, &dh[h].gram_items, cur, s);
+        if (!st) st = upload(hl[h].prod_items, &dh[h].prod_items, cur, s);
+        if (!st) st = upload(hl[h].red_items, &dh[h].red_items, cur, s);
+        if (!st) st = upload(hl[h].gram, &dh[h].gram, cur, s);
+        if (!st) st = upload(hl[h].prod, &dh[h].prod, cur, s);
+        if (!st) st = upload(hl[h].solve, &dh[h].solve, cur, s);
+        dh[h].n_gram_items = (int64_t)hl[h].gram_items.size();
+        dh[h].n_prod_items = (int64_t)hl[h].prod_items.size();
+        dh[h].n_red_items = (int64_t)hl[h].red_items.size();
+        for (auto &kv : hl[h].chunks) {
+            BSolveChunk *d = nullptr;
+            if (!st) st = upload(kv.second, &d, cur, s);
+            dh[h].groups.push_back({NqpVariant{kv.first.first, kv.first.second}, {d, (int)kv.second.size()}});
+        }
+    }
+    unsigned int *queues = (unsigned int *)cur;
+    // BF16 copies of V and zeroed iteration counters
+    for (int p = 0; p < count && !st; p++) {
+        const nmf_problem &q = probs[p];
+        if (bf16) {
+            e = launch_to_bf16(q.V.dense, q.V.rows, q.V.cols, q.V.ld, (__bf16 *)dptr(slot[p].V16), s);
+            if (e != hipSuccess) st = hip_fail(e, "BF16 copies");
+        }
+        if (!st) {
+            e = launch_zero_u64((unsigned long long *)dptr(slot[p].inner), 1, s);
+            if (e != hipSuccess) st = hip_fail(e, "zero counters");
+        }
+    }
+    if (!st) {
+        e = hipStreamSynchronize(s);
+        if (e != hipSuccess) st = hip_fail(e, "batched set-up");
+    }
+
+    // ---------------------------------------------------------------- graph
+    hipStream_t cs = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    if (!st && opt->max_outer > 0) {
+        e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        for (int t = 0; t < opt->max_outer && e == hipSuccess; t++) {
+            for (int h = 0; h < 2 && e == hipSuccess; h++) {
+                int gi = h * (int)hl[0].chunks.size();
+                e = launch_zero_u32(queues + gi, (int)dh[h].groups.size(), cs);
+                if (e == hipSuccess)
+                    e = launch_bgram(dh[h].gram_items, dh[h].n_gram_items, dh[h].gram, count, ntmax,
+                                     opt->precision, cs);
+                if (e == hipSuccess)
+                    e = launch_bdense(dh[h].prod_items, dh[h].n_prod_items, dh[h].prod, ntmax, h == 0,
+                                      bf16, dh[h].red_items, dh[h].n_red_items, cs);
+                for (size_t g = 0; g < dh[h].groups.size() && e == hipSuccess; g++)
+                    e = launch_bnqp(dh[h].groups[g].first, dh[h].groups[g].second.first,
+                                    dh[h].groups[g].second.second, queues + gi + (int)g,
+                                    dh[h].solve, opt->max_inner, opt->eps, opt->ls_guard ? 1 : 0, cs);
+            }
+        }
+        hipError_t e2 = hipStreamEndCapture(cs, &graph);
+        if (e == hipSuccess) e = e2;
+        if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e == hipSuccess) e = hipGraphLaunch(exec, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) st = hip_fail(e, "batched graph");
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cs) (void)hipStreamDestroy(cs);
+
+    // ---------------------------------------------------------------- statistics
+    if (!st && per_problem) {
+        for (int p = 0; p < count && !st; p++) {
+            const nmf_problem &q = probs[p];
+            double loss = NAN, obj = NAN;
+            st = nmf_objective(&q.V, q.r, &q.reg, q.W, q.Ht, &loss, &obj, stream);
+            unsigned long long inner = 0;
+            if (!st) {
+                e = hipMemcpy(&inner, dptr(slot[p].inner), sizeof inner, hipMemcpyDeviceToHost);
+                if (e != hipSuccess) st = hip_fail(e, "batched stats");
+            }
+            nmf_stats &o = per_problem[p];
+            o.loss = loss;
+            o.objective = obj;
+            o.kkt_w = NAN;
+            o.kkt_h = NAN;
+            o.inner_total = (int64_t)inner;
+            o.outer_done = opt->max_outer;
+            o.kbar = opt->max_outer > 0
+                         ? (double)inner / ((double)opt->max_outer * (double)(q.V.rows + q.V.cols))
+                         : 0.0;
+        }
+    }
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(lists);
+    (void)hipFree(base);
+    return st;
+}
+
+namespace nmfi {
+hipError_t launch_bnqp(const NqpVariant &v, const BSolveChunk *chunks, int nchunks,
+                       unsigned int *queue, const BSolveProb *probs, int max_inner, double eps,
+                       int ls_guard, hipStream_t s) {
+    switch (v.L) {
+    case 1: return launch_bnqp_l1(v.E, chunks, nchunks, queue, probs, max_inner, eps, ls_guard, s);
+    case 2: return launch_bnqp_l2(v.E, chunks, nchunks, queue, probs, max_inner, eps, ls_guard, s);
+    case 4: return launch_bnqp_l4(v.E, chunks, nchunks, queue, probs, max_inner, eps, ls_guard, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+}  // namespace nmfi

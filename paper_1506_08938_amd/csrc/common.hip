@@ -102,3 +102,17 @@ hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t s) {
 }
 
 }  // namespace nmfi
+
+namespace nmfi {
+
+__global__ void k_zero_u32(unsigned int *p, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
+}
+
+hipError_t launch_zero_u32(unsigned int *p, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+}  // namespace nmfi

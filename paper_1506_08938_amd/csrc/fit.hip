@@ -118,7 +118,7 @@ extern "C" int nmf_gram(const float *A, int64_t k, int32_t r, float l2, int32_t 
     if (precision != NMF_FP32 && precision != NMF_BF16) return fail(NMF_E_INVAL, "bad precision");
     hipStream_t s = (hipStream_t)stream;
     float *scratch = nullptr;
-    NMF_HIP(hipMallocAsync((void **)&scratch, gram_scratch_bytes(r), s));
+    NMF_HIP(hipMallocAsync((void **)&scratch, gram_scratch_bytes(r, k), s));
     hipError_t e = launch_gram(A, k, r, l2, precision, G, scratch, s);
     hipError_t e2 = hipFreeAsync(scratch, s);
     if (e != hipSuccess) return hip_fail(e, "nmf_gram");
@@ -204,7 +204,7 @@ struct nmf_plan {
     float *dense_scratch = nullptr;
     // workspace
     char *ws = nullptr;
-    float *G = nullptr, *gram_scratch = nullptr, *Q = nullptr, *dsq = nullptr, *P = nullptr;
+    float *G = nullptr, *gram_scratch = nullptr, *P = nullptr;
     unsigned long long *counter = nullptr, *inner_total = nullptr;
     char *obj_scratch = nullptr;
     double *obj_out = nullptr, *kkt_partial = nullptr, *kkt_out = nullptr;
@@ -294,10 +294,8 @@ extern "C" int nmf_plan_create(const nmf_matrix *V, int32_t r, const nmf_reg *re
         size_t off = 0;
         auto place = [&](size_t bytes) { size_t o = off; off += al256(bytes); return o; };
         const size_t o_cnt = place(2 * sizeof(unsigned long long));
-        const size_t o_dsq = place(NMF_MAX_RANK * sizeof(float));
         const size_t o_G = place((size_t)r * r * sizeof(float));
-        const size_t o_Q = place((size_t)p->R * p->R * sizeof(float));
-        const size_t o_gs = place(gram_scratch_bytes(r));
+        const size_t o_gs = place(gram_scratch_bytes(r, cmax));
         const size_t o_P = place((size_t)cmax * r * sizeof(float));
         const size_t o_oo = place(4 * sizeof(double));
         const size_t o_ko = place(4 * sizeof(double));
@@ -309,9 +307,7 @@ extern "C" int nmf_plan_create(const nmf_matrix *V, int32_t r, const nmf_reg *re
         } else {
             p->counter = (unsigned long long *)(p->ws + o_cnt);
             p->inner_total = p->counter + 1;
-            p->dsq = (float *)(p->ws + o_dsq);
             p->G = (float *)(p->ws + o_G);
-            p->Q = (float *)(p->ws + o_Q);
             p->gram_scratch = (float *)(p->ws + o_gs);
             p->P = (float *)(p->ws + o_P);
             p->obj_out = (double *)(p->ws + o_oo);
@@ -331,6 +327,26 @@ extern "C" int nmf_plan_create(const nmf_matrix *V, int32_t r, const nmf_reg *re
     *out = p;
     return NMF_OK;
 }
+
+namespace nmfi {
+// Device bytes nmf_plan_create + nmf_plan_run need for V (the server's
+// admission estimate of a full-fit request).
+size_t plan_footprint(const nmf_matrix *V, int r, const nmf_opts *opt) {
+    const int64_t m = V->rows, n = V->cols, cmax = m > n ? m : n;
+    size_t b = 0;
+    b += al256(64) + al256((size_t)r * r * 4) + al256(gram_scratch_bytes(r, cmax));
+    b += al256((size_t)cmax * r * 4) + 2 * al256(32) + al256((size_t)cmax * 8);
+    b += al256(objective_scratch_bytes(V, r));
+    if (V->kind == NMF_DENSE) {
+        b += al256(dense_scratch_bytes(m, n, r));
+        if (opt->precision == NMF_BF16) b += al256((size_t)m * n * 2);
+    } else {
+        b += 3 * al256((size_t)(V->nnz + n + 1) * 4);  // CSR(V') when built here
+        b += al256((size_t)(V->nnz / SPMM_CHUNK + m + n + 2) * (sizeof(SpChunk) + sizeof(SpSplit)));
+    }
+    return b + 65536;
+}
+}  // namespace nmfi
 
 extern "C" void nmf_plan_destroy(nmf_plan *p) {
     if (!p) return;
@@ -389,12 +405,10 @@ static hipError_t half_update(nmf_plan *p, bool h_update, const float *A, float 
     const float l2 = h_update ? p->reg.l2_h : p->reg.l2_w;
     hipError_t e;
     {
+        // the Gram also zeroes the solve's work counter; the anti-lopsided
+        // rescale happens inside the solve kernel while it stages Gamma
         PhaseMark pm(p, NMF_PHASE_GRAM, s);
-        e = launch_gram(A, k, p->r, l2, p->opt.precision, p->G, p->gram_scratch, s);
-    }
-    if (e == hipSuccess) {
-        PhaseMark pm(p, NMF_PHASE_RESCALE, s);
-        e = launch_rescale(p->G, p->r, p->R, p->Q, p->dsq, p->counter, s);
+        e = launch_gram(A, k, p->r, l2, p->opt.precision, p->G, p->gram_scratch, s, p->counter);
     }
     if (e != hipSuccess) return e;
     {
@@ -411,7 +425,7 @@ static hipError_t half_update(nmf_plan *p, bool h_update, const float *A, float 
     }
     if (e != hipSuccess) return e;
     NqpParams q{};
-    q.Q = p->Q; q.dsq = p->dsq; q.P = p->P; q.hsign = -1.f; q.hadd = l1; q.X = X;
+    q.gram = p->G; q.P = p->P; q.hsign = -1.f; q.hadd = l1; q.X = X;
     q.ncols = c; q.r = p->r; q.ldp = p->r; q.ldx = p->r;
     q.max_inner = p->opt.max_inner; q.eps = p->opt.eps; q.ls_guard = p->opt.ls_guard ? 1 : 0;
     q.cold = 0; q.iters = nullptr; q.counter = p->counter; q.inner_total = p->inner_total;
@@ -516,18 +530,6 @@ extern "C" int nmf_objective(const nmf_matrix *V, int32_t r, const nmf_reg *reg,
 }
 
 // ============================================================ fold-in
-struct nmf_basis {
-    float *W = nullptr;  // m x r copy
-    int64_t m = 0;
-    int r = 0;
-    float l1 = 0.f, l2 = 0.f;
-    nmf_opts opt{};
-    NqpVariant var{};
-    int R = 0;
-    char *ws = nullptr;  // G, Q, dsq
-    float *G = nullptr, *Q = nullptr, *dsq = nullptr;
-};
-
 extern "C" int nmf_basis_create(const float *W, int64_t m, int32_t r, float l1, float l2,
                                 const nmf_opts *opt, nmf_basis **out, void *stream) {
     if (!out) return fail(NMF_E_INVAL, "out is NULL");
@@ -543,18 +545,14 @@ extern "C" int nmf_basis_create(const float *W, int64_t m, int32_t r, float l1, 
     b->m = m; b->r = r; b->l1 = l1; b->l2 = l2; b->opt = *opt;
     b->var = nqp_pick(r);
     b->R = b->var.E * b->var.L;
-    const size_t oG = 0, oD = al256((size_t)r * r * 4), oQ = oD + al256(NMF_MAX_RANK * 4),
-                 oS = oQ + al256((size_t)b->R * b->R * 4), total = oS + al256(gram_scratch_bytes(r));
+    const size_t oG = 0, oS = al256((size_t)r * r * 4), total = oS + al256(gram_scratch_bytes(r, m));
     hipError_t e = hipMalloc((void **)&b->W, (size_t)m * r * sizeof(float));
     if (e == hipSuccess) e = hipMalloc((void **)&b->ws, total);
     if (e == hipSuccess) {
         b->G = (float *)(b->ws + oG);
-        b->dsq = (float *)(b->ws + oD);
-        b->Q = (float *)(b->ws + oQ);
         e = hipMemcpyAsync(b->W, W, (size_t)m * r * sizeof(float), hipMemcpyDeviceToDevice, s);
     }
     if (e == hipSuccess) e = launch_gram(b->W, m, r, l2, opt->precision, b->G, (float *)(b->ws + oS), s);
-    if (e == hipSuccess) e = launch_rescale(b->G, r, b->R, b->Q, b->dsq, nullptr, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         if (b->W) (void)hipFree(b->W);
@@ -581,7 +579,7 @@ int basis_solve(const nmf_basis *B, const float *P, int64_t c, float *Ht_new, in
                 unsigned long long *counter, hipStream_t s) {
     NMF_HIP(launch_zero_u64(counter, 1, s));
     NqpParams q{};
-    q.Q = B->Q; q.dsq = B->dsq; q.P = P; q.hsign = -1.f; q.hadd = B->l1; q.X = Ht_new;
+    q.gram = B->G; q.P = P; q.hsign = -1.f; q.hadd = B->l1; q.X = Ht_new;
     q.ncols = c; q.r = B->r; q.ldp = B->r; q.ldx = B->r;
     q.max_inner = B->opt.max_inner; q.eps = B->opt.eps; q.ls_guard = B->opt.ls_guard ? 1 : 0;
     q.cold = 1; q.iters = iters; q.counter = counter; q.inner_total = nullptr;

@@ -16,20 +16,25 @@ namespace nmfi {
 constexpr int DP_BC = 64;  // rows of P per block
 constexpr int DP_KT = 32;  // k per LDS stage
 
+// LDS a block needs for the FP32 product body
+template <int NT>
+constexpr int dense_fp32_lds_floats() {
+    return DP_BC * (DP_KT + 1) + DP_KT * NT * 32;
+}
+
+// 64 rows of P = X A starting at row c0, summed over k in [kb, ke), written
+// to o (C x r).  lds: dense_fp32_lds_floats<NT>() floats.
 template <int NT, bool XT>
-__global__ __launch_bounds__(256) void k_dense_fp32(const float *__restrict__ V, int64_t ld,
-                                                    int64_t C, int64_t K,
-                                                    const float *__restrict__ A, int r,
-                                                    int64_t kchunk, float *__restrict__ out) {
+__device__ __forceinline__ void dense_fp32_body(const float *__restrict__ V, int64_t ld, int64_t C,
+                                                const float *__restrict__ A, int r, int64_t c0,
+                                                int64_t kb, int64_t ke, float *lds,
+                                                float *__restrict__ o) {
     constexpr int R32 = NT * 32;
     constexpr int NTILES = 2 * NT;
     constexpr int TPW = (NTILES + 3) / 4;
-    __shared__ float Xs[DP_BC][DP_KT + 1];
-    __shared__ float As[DP_KT][R32];
+    float(*Xs)[DP_KT + 1] = (float(*)[DP_KT + 1])lds;
+    float(*As)[R32] = (float(*)[R32])(lds + DP_BC * (DP_KT + 1));
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t c0 = (int64_t)blockIdx.x * DP_BC;
-    const int64_t kb = (int64_t)blockIdx.y * kchunk;
-    const int64_t ke = min(K, kb + kchunk);
 
     f32x16 acc[TPW];
 #pragma unroll
@@ -70,7 +75,6 @@ __global__ __launch_bounds__(256) void k_dense_fp32(const float *__restrict__ V,
         }
         __syncthreads();
     }
-    float *o = out + (int64_t)blockIdx.y * C * r;
 #pragma unroll
     for (int q = 0; q < TPW; q++) {
         const int tile = wave + 4 * q;
@@ -87,22 +91,35 @@ __global__ __launch_bounds__(256) void k_dense_fp32(const float *__restrict__ V,
     }
 }
 
-// BF16 operands (V16: the BF16 copy of V; A converted while staging)
 template <int NT, bool XT>
-__global__ __launch_bounds__(256) void k_dense_bf16(const __bf16 *__restrict__ V16, int64_t ld,
+__global__ __launch_bounds__(256) void k_dense_fp32(const float *__restrict__ V, int64_t ld,
                                                     int64_t C, int64_t K,
                                                     const float *__restrict__ A, int r,
                                                     int64_t kchunk, float *__restrict__ out) {
+    __shared__ float lds[dense_fp32_lds_floats<NT>()];
+    const int64_t kb = (int64_t)blockIdx.y * kchunk;
+    dense_fp32_body<NT, XT>(V, ld, C, A, r, (int64_t)blockIdx.x * DP_BC, kb, min(K, kb + kchunk),
+                            lds, out + (int64_t)blockIdx.y * C * r);
+}
+
+// BF16 operands (V16: the BF16 copy of V; A converted while staging)
+template <int NT>
+constexpr int dense_bf16_lds_bytes() {
+    return (DP_BC + NT * 32) * (DP_KT + 8) * 2;
+}
+
+template <int NT, bool XT>
+__device__ __forceinline__ void dense_bf16_body(const __bf16 *__restrict__ V16, int64_t ld,
+                                                int64_t C, const float *__restrict__ A, int r,
+                                                int64_t c0, int64_t kb, int64_t ke, void *lds,
+                                                float *__restrict__ o) {
     constexpr int R32 = NT * 32;
     constexpr int NTILES = 2 * NT;
     constexpr int TPW = (NTILES + 3) / 4;
     // k-major staging so that a lane's eight consecutive k are contiguous
-    __shared__ __bf16 Xs[DP_BC][DP_KT + 8];
-    __shared__ __bf16 As[R32][DP_KT + 8];
+    __bf16(*Xs)[DP_KT + 8] = (__bf16(*)[DP_KT + 8])lds;
+    __bf16(*As)[DP_KT + 8] = (__bf16(*)[DP_KT + 8])((char *)lds + DP_BC * (DP_KT + 8) * 2);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t c0 = (int64_t)blockIdx.x * DP_BC;
-    const int64_t kb = (int64_t)blockIdx.y * kchunk;
-    const int64_t ke = min(K, kb + kchunk);
 
     f32x16 acc[TPW];
 #pragma unroll
@@ -149,7 +166,6 @@ __global__ __launch_bounds__(256) void k_dense_bf16(const __bf16 *__restrict__ V
         }
         __syncthreads();
     }
-    float *o = out + (int64_t)blockIdx.y * C * r;
 #pragma unroll
     for (int q = 0; q < TPW; q++) {
         const int tile = wave + 4 * q;
@@ -164,6 +180,17 @@ __global__ __launch_bounds__(256) void k_dense_bf16(const __bf16 *__restrict__ V
             }
         }
     }
+}
+
+template <int NT, bool XT>
+__global__ __launch_bounds__(256) void k_dense_bf16(const __bf16 *__restrict__ V16, int64_t ld,
+                                                    int64_t C, int64_t K,
+                                                    const float *__restrict__ A, int r,
+                                                    int64_t kchunk, float *__restrict__ out) {
+    __shared__ __attribute__((aligned(16))) char lds[dense_bf16_lds_bytes<NT>()];
+    const int64_t kb = (int64_t)blockIdx.y * kchunk;
+    dense_bf16_body<NT, XT>(V16, ld, C, A, r, (int64_t)blockIdx.x * DP_BC, kb, min(K, kb + kchunk),
+                            lds, out + (int64_t)blockIdx.y * C * r);
 }
 
 // P = sum over split-K slices in slice order
@@ -197,7 +224,7 @@ hipError_t launch_to_bf16(const float *x, int64_t rows, int64_t cols, int64_t ld
 }
 
 // split-K factor: enough blocks to fill the chip, at least 256 k per slice
-static int dense_nsplit(int64_t C, int64_t K) {
+int dense_nsplit(int64_t C, int64_t K) {
     const int64_t rb = (C + DP_BC - 1) / DP_BC;
     int64_t ns = (2048 + rb - 1) / rb;
     const int64_t maxs = (K + 255) / 256;
@@ -205,6 +232,13 @@ static int dense_nsplit(int64_t C, int64_t K) {
     if (ns < 1) ns = 1;
     if (ns > 64) ns = 64;
     return (int)ns;
+}
+
+int64_t dense_kchunk(int64_t C, int64_t K) {
+    const int ns = dense_nsplit(C, K);
+    int64_t kchunk = (K + ns - 1) / ns;
+    kchunk = ((kchunk + DP_KT - 1) / DP_KT) * DP_KT;
+    return kchunk < DP_KT ? DP_KT : kchunk;
 }
 
 size_t dense_scratch_bytes(int64_t m, int64_t n, int r) {
@@ -240,10 +274,7 @@ hipError_t launch_dense_product(const void *V, int bf16, int64_t m, int64_t n, i
     const bool xt = trans == 0;
     const int64_t C = xt ? n : m, K = xt ? m : n;
     if (C == 0) return hipSuccess;
-    const int ns = dense_nsplit(C, K);
-    int64_t kchunk = (K + ns - 1) / ns;
-    kchunk = ((kchunk + DP_KT - 1) / DP_KT) * DP_KT;
-    if (kchunk < DP_KT) kchunk = DP_KT;
+    const int64_t kchunk = dense_kchunk(C, K);
     const int nsplit = (int)((K + kchunk - 1) / kchunk);
     float *out = nsplit > 1 ? scratch : P;
     dim3 grid((unsigned)((C + DP_BC - 1) / DP_BC), (unsigned)(nsplit > 0 ? nsplit : 1));
@@ -262,6 +293,74 @@ hipError_t launch_dense_product(const void *V, int bf16, int64_t m, int64_t n, i
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(k_split_reduce, dim3((unsigned)blocks), dim3(256), 0, s, scratch, nsplit,
                        nel, P);
+    return hipGetLastError();
+}
+
+}  // namespace nmfi
+
+// ------------------------------------------------------------------ batched
+namespace nmfi {
+
+// Many problems at once: block b computes 64 rows of one problem's P over
+// one k slice (items[b].idx = row block * nsplit + slice), exactly as the
+// single-problem product does, so the result is bitwise the same.
+template <int NTMAX, bool XT, bool BF16>
+__global__ __launch_bounds__(256) void k_bdense(const BItem *__restrict__ items,
+                                                const BProdProb *__restrict__ probs) {
+    constexpr int FP32_BYTES = dense_fp32_lds_floats<NTMAX>() * 4;
+    constexpr int BF16_BYTES = dense_bf16_lds_bytes<NTMAX>();
+    __shared__ __attribute__((aligned(16))) char lds[BF16 ? BF16_BYTES : FP32_BYTES];
+    const BItem it = items[blockIdx.x];
+    const BProdProb P = probs[it.prob];
+    const int NT = (P.r + 31) / 32;
+    const int slice = it.idx % P.nsplit;
+    const int64_t c0 = (int64_t)(it.idx / P.nsplit) * DP_BC;
+    const int64_t kb = (int64_t)slice * P.kchunk;
+    const int64_t ke = min(P.K, kb + P.kchunk);
+    float *o = P.nsplit > 1 ? P.part + (int64_t)slice * P.C * P.r : P.P;
+#define NMF_BDENSE_CASE(N)                                                                     \
+    if constexpr (BF16)                                                                        \
+        dense_bf16_body<N, XT>((const __bf16 *)P.V, P.ld, P.C, P.A, P.r, c0, kb, ke, lds, o);  \
+    else                                                                                       \
+        dense_fp32_body<N, XT>((const float *)P.V, P.ld, P.C, P.A, P.r, c0, kb, ke,            \
+                               (float *)lds, o);
+    switch (NT) {
+    case 1: { NMF_BDENSE_CASE(1) } break;
+    case 2: if constexpr (NTMAX >= 2) { NMF_BDENSE_CASE(2) } break;
+    case 3: if constexpr (NTMAX >= 3) { NMF_BDENSE_CASE(3) } break;
+    default: if constexpr (NTMAX >= 4) { NMF_BDENSE_CASE(4) } break;
+    }
+#undef NMF_BDENSE_CASE
+}
+
+// split-K sums of many problems, the same loop as k_split_reduce
+__global__ void k_bsplit_reduce(const BItem *__restrict__ items, const BProdProb *__restrict__ probs) {
+    const BItem it = items[blockIdx.x];
+    const BProdProb P = probs[it.prob];
+    const int64_t n = P.C * P.r;
+    const int64_t e0 = (int64_t)it.idx * 4096;
+    for (int64_t i = e0 + threadIdx.x; i < min(n, e0 + 4096); i += blockDim.x) {
+        float s = 0.f;
+        for (int k = 0; k < P.nsplit; k++) s += P.part[(int64_t)k * n + i];
+        P.P[i] = s;
+    }
+}
+
+hipError_t launch_bdense(const BItem *items, int64_t nitems, const BProdProb *probs, int ntmax,
+                         bool xt, bool bf16, const BItem *red_items, int64_t nred, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    const dim3 g((unsigned)nitems), b(256);
+#define NMF_BD(NTM, X, B) hipLaunchKernelGGL((k_bdense<NTM, X, B>), g, b, 0, s, items, probs)
+    if (ntmax <= 2) {
+        if (xt) { if (bf16) NMF_BD(2, true, true); else NMF_BD(2, true, false); }
+        else { if (bf16) NMF_BD(2, false, true); else NMF_BD(2, false, false); }
+    } else {
+        if (xt) { if (bf16) NMF_BD(4, true, true); else NMF_BD(4, true, false); }
+        else { if (bf16) NMF_BD(4, false, true); else NMF_BD(4, false, false); }
+    }
+#undef NMF_BD
+    if (nred > 0)
+        hipLaunchKernelGGL(k_bsplit_reduce, dim3((unsigned)nred), dim3(256), 0, s, red_items, probs);
     return hipGetLastError();
 }
 

@@ -19,7 +19,6 @@
 namespace nmfi {
 
 constexpr int GRAM_BLOCK = 256;
-constexpr int GRAM_MAX_BLOCKS = 240;
 
 // tile index of (ta <= tb) in row-major upper-triangle order
 template <int NT>
@@ -30,18 +29,17 @@ __device__ __forceinline__ void tile_of(int ti, int &ta, int &tb) {
     tb = ta + t;
 }
 
+// One block's partial Gram over rows [b0, b1) of A (k x r), written to out
+// (NTILE * 1024 floats in MFMA accumulator order).  red: LDS of NTILE * 1024.
 template <int NT, int PREC>
-__global__ __launch_bounds__(GRAM_BLOCK) void k_gram_partial(const float *__restrict__ A, int64_t k,
-                                                             int r, int64_t rows_per_block,
-                                                             float *__restrict__ partial) {
+__device__ __forceinline__ void gram_partial_rows(const float *__restrict__ A, int r, int64_t b0,
+                                                  int64_t b1, float *red,
+                                                  float *__restrict__ out) {
     constexpr int NTILE = NT * (NT + 1) / 2;
     constexpr int RSTEP = PREC == NMF_BF16 ? 16 : 2;  // rows per MFMA
-    __shared__ float red[NTILE * 1024];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int half = lane >> 5, col = lane & 31;
 
-    const int64_t b0 = (int64_t)blockIdx.x * rows_per_block;
-    const int64_t b1 = min(k, b0 + rows_per_block);
     // the block's rows split over its four waves in RSTEP-aligned pieces
     const int64_t nsteps = (b1 - b0 + RSTEP - 1) / RSTEP;
     const int64_t s0 = b0 + (nsteps * wave / 4) * RSTEP;
@@ -110,18 +108,34 @@ __global__ __launch_bounds__(GRAM_BLOCK) void k_gram_partial(const float *__rest
         }
         __syncthreads();
     }
-    float *out = partial + (size_t)blockIdx.x * NTILE * 1024;
     for (int e = threadIdx.x; e < NTILE * 1024; e += GRAM_BLOCK) out[e] = red[e];
 }
 
-template <int NT>
-__global__ __launch_bounds__(256) void k_gram_reduce(const float *__restrict__ partial, int nblocks,
-                                                     int r, float l2, float *__restrict__ G) {
+template <int NT, int PREC>
+__global__ __launch_bounds__(GRAM_BLOCK) void k_gram_partial(const float *__restrict__ A, int64_t k,
+                                                             int r, int64_t rows_per_block,
+                                                             float *__restrict__ partial) {
     constexpr int NTILE = NT * (NT + 1) / 2;
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= NTILE * 1024) return;
-    float s = 0.f;
-    for (int b = 0; b < nblocks; b++) s += partial[(size_t)b * NTILE * 1024 + e];
+    __shared__ float red[NTILE * 1024];
+    const int64_t b0 = (int64_t)blockIdx.x * rows_per_block;
+    const int64_t b1 = min(k, b0 + rows_per_block);
+    gram_partial_rows<NT, PREC>(A, r, b0, b1, red, partial + (size_t)blockIdx.x * NTILE * 1024);
+}
+
+// Gram entry e (of NTILE * 1024, accumulator order) summed over nblocks
+// partials (eight interleaved sums, combined in a fixed order), written to
+// the symmetric r x r G with 2 l2 on the diagonal.
+template <int NT>
+__device__ __forceinline__ void gram_reduce_entry(const float *__restrict__ partial, int nblocks,
+                                                  int r, float l2, float *__restrict__ G, int e) {
+    constexpr int NTILE = NT * (NT + 1) / 2;
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    int pb = 0;
+    for (; pb + 8 <= nblocks; pb += 8)
+#pragma unroll
+        for (int q = 0; q < 8; q++) acc[q] += partial[(size_t)(pb + q) * NTILE * 1024 + e];
+    for (int q = 0; pb < nblocks; pb++, q++) acc[q] += partial[(size_t)pb * NTILE * 1024 + e];
+    float s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
     const int ti = e >> 10, rem = e & 1023, q = rem >> 6, lane = rem & 63;
     int ta, tb;
     tile_of<NT>(ti, ta, tb);
@@ -134,50 +148,123 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const float *__restrict__ p
     G[(size_t)b * r + a] = s;
 }
 
+template <int NT>
+__global__ __launch_bounds__(256) void k_gram_reduce(const float *__restrict__ partial, int nblocks,
+                                                     int r, float l2, float *__restrict__ G,
+                                                     unsigned long long *counter) {
+    constexpr int NTILE = NT * (NT + 1) / 2;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e == 0 && counter) *counter = 0ull;
+    if (e >= NTILE * 1024) return;
+    gram_reduce_entry<NT>(partial, nblocks, r, l2, G, e);
+}
+
+// Blocks of BGRAM_ROWS rows (the batched fit uses the same blocks, so a
+// problem's Gram is bitwise the same alone or in a batch).
 template <int NT, int PREC>
 static hipError_t gram_t(const float *A, int64_t k, int r, float l2, float *G, float *scratch,
-                         hipStream_t s) {
+                         hipStream_t s, unsigned long long *counter) {
     constexpr int NTILE = NT * (NT + 1) / 2;
-    int64_t nb = (k + 511) / 512;
-    if (nb < 1) nb = 1;
-    if (nb > GRAM_MAX_BLOCKS) nb = GRAM_MAX_BLOCKS;
-    const int step = PREC == NMF_BF16 ? 16 : 2;
-    int64_t rpb = (k + nb - 1) / nb;
-    rpb = ((rpb + 4 * step - 1) / (4 * step)) * (4 * step);
-    if (rpb < 4 * step) rpb = 4 * step;
-    nb = (k + rpb - 1) / rpb;
-    if (nb < 1) nb = 1;
+    const int64_t nb = k > 0 ? (k + BGRAM_ROWS - 1) / BGRAM_ROWS : 1;
     hipLaunchKernelGGL((k_gram_partial<NT, PREC>), dim3((unsigned)nb), dim3(GRAM_BLOCK), 0, s, A, k,
-                       r, rpb, scratch);
+                       r, (int64_t)BGRAM_ROWS, scratch);
     hipLaunchKernelGGL((k_gram_reduce<NT>), dim3((NTILE * 1024 + 255) / 256), dim3(256), 0, s,
-                       scratch, (int)nb, r, l2, G);
+                       scratch, (int)nb, r, l2, G, counter);
     return hipGetLastError();
 }
 
-size_t gram_scratch_bytes(int r) {
+size_t gram_scratch_bytes(int r, int64_t k) {
     const int NT = (r + 31) / 32;
-    return (size_t)GRAM_MAX_BLOCKS * (NT * (NT + 1) / 2) * 1024 * sizeof(float);
+    const int64_t nb = k > 0 ? (k + BGRAM_ROWS - 1) / BGRAM_ROWS : 1;
+    return (size_t)nb * (NT * (NT + 1) / 2) * 1024 * sizeof(float);
 }
 
 hipError_t launch_gram(const float *A, int64_t k, int r, float l2, int precision, float *G,
-                       float *scratch, hipStream_t s) {
+                       float *scratch, hipStream_t s, unsigned long long *counter) {
     const int NT = (r + 31) / 32;
     if (precision == NMF_BF16) {
         switch (NT) {
-        case 1: return gram_t<1, NMF_BF16>(A, k, r, l2, G, scratch, s);
-        case 2: return gram_t<2, NMF_BF16>(A, k, r, l2, G, scratch, s);
-        case 3: return gram_t<3, NMF_BF16>(A, k, r, l2, G, scratch, s);
-        case 4: return gram_t<4, NMF_BF16>(A, k, r, l2, G, scratch, s);
+        case 1: return gram_t<1, NMF_BF16>(A, k, r, l2, G, scratch, s, counter);
+        case 2: return gram_t<2, NMF_BF16>(A, k, r, l2, G, scratch, s, counter);
+        case 3: return gram_t<3, NMF_BF16>(A, k, r, l2, G, scratch, s, counter);
+        case 4: return gram_t<4, NMF_BF16>(A, k, r, l2, G, scratch, s, counter);
         }
     } else {
         switch (NT) {
-        case 1: return gram_t<1, NMF_FP32>(A, k, r, l2, G, scratch, s);
-        case 2: return gram_t<2, NMF_FP32>(A, k, r, l2, G, scratch, s);
-        case 3: return gram_t<3, NMF_FP32>(A, k, r, l2, G, scratch, s);
-        case 4: return gram_t<4, NMF_FP32>(A, k, r, l2, G, scratch, s);
+        case 1: return gram_t<1, NMF_FP32>(A, k, r, l2, G, scratch, s, counter);
+        case 2: return gram_t<2, NMF_FP32>(A, k, r, l2, G, scratch, s, counter);
+        case 3: return gram_t<3, NMF_FP32>(A, k, r, l2, G, scratch, s, counter);
+        case 4: return gram_t<4, NMF_FP32>(A, k, r, l2, G, scratch, s, counter);
         }
     }
     return hipErrorInvalidValue;
+}
+
+}  // namespace nmfi
+
+// ------------------------------------------------------------------ batched
+namespace nmfi {
+
+// Phase 1 for many problems at once: block b computes items[b] = (problem,
+// chunk), the partial Gram of rows [chunk * rows_per_chunk, ...) of that
+// problem's A.
+template <int NTMAX, int PREC>
+__global__ __launch_bounds__(GRAM_BLOCK) void k_bgram_partial(const BItem *__restrict__ items,
+                                                              const BGramProb *__restrict__ probs,
+                                                              int64_t rows_per_chunk) {
+    __shared__ float red[NTMAX * (NTMAX + 1) / 2 * 1024];
+    const BItem it = items[blockIdx.x];
+    const BGramProb P = probs[it.prob];
+    const int64_t b0 = (int64_t)it.idx * rows_per_chunk;
+    const int64_t b1 = min(P.k, b0 + rows_per_chunk);
+    const int NT = (P.r + 31) / 32;
+    float *out = P.partial + (size_t)it.idx * (NT * (NT + 1) / 2) * 1024;
+    switch (NT) {
+    case 1: gram_partial_rows<1, PREC>(P.A, P.r, b0, b1, red, out); break;
+    case 2: if constexpr (NTMAX >= 2) gram_partial_rows<2, PREC>(P.A, P.r, b0, b1, red, out); break;
+    case 3: if constexpr (NTMAX >= 3) gram_partial_rows<3, PREC>(P.A, P.r, b0, b1, red, out); break;
+    default: if constexpr (NTMAX >= 4) gram_partial_rows<4, PREC>(P.A, P.r, b0, b1, red, out); break;
+    }
+}
+
+// Phase 2: one block per problem sums its partials into Gamma.
+template <int NTMAX>
+__global__ __launch_bounds__(256) void k_bgram_finish(const BGramProb *__restrict__ probs) {
+    const BGramProb P = probs[blockIdx.x];
+    const int NT = (P.r + 31) / 32;
+    const int n = NT * (NT + 1) / 2 * 1024;
+    for (int e = threadIdx.x; e < n; e += 256) {
+        switch (NT) {
+        case 1: gram_reduce_entry<1>(P.partial, P.nchunks, P.r, P.l2, P.G, e); break;
+        case 2: if constexpr (NTMAX >= 2) gram_reduce_entry<2>(P.partial, P.nchunks, P.r, P.l2, P.G, e); break;
+        case 3: if constexpr (NTMAX >= 3) gram_reduce_entry<3>(P.partial, P.nchunks, P.r, P.l2, P.G, e); break;
+        default: if constexpr (NTMAX >= 4) gram_reduce_entry<4>(P.partial, P.nchunks, P.r, P.l2, P.G, e); break;
+        }
+    }
+}
+
+size_t bgram_partial_floats(int r, int64_t k) {
+    const int NT = (r + 31) / 32;
+    return (size_t)((k + BGRAM_ROWS - 1) / BGRAM_ROWS) * (NT * (NT + 1) / 2) * 1024;
+}
+
+hipError_t launch_bgram(const BItem *items, int64_t nitems, const BGramProb *probs, int nprobs,
+                        int ntmax, int precision, hipStream_t s) {
+    if (nitems > 0) {
+        const dim3 g((unsigned)nitems), b(GRAM_BLOCK);
+        if (ntmax <= 2) {
+            if (precision == NMF_BF16) hipLaunchKernelGGL((k_bgram_partial<2, NMF_BF16>), g, b, 0, s, items, probs, (int64_t)BGRAM_ROWS);
+            else hipLaunchKernelGGL((k_bgram_partial<2, NMF_FP32>), g, b, 0, s, items, probs, (int64_t)BGRAM_ROWS);
+        } else {
+            if (precision == NMF_BF16) hipLaunchKernelGGL((k_bgram_partial<4, NMF_BF16>), g, b, 0, s, items, probs, (int64_t)BGRAM_ROWS);
+            else hipLaunchKernelGGL((k_bgram_partial<4, NMF_FP32>), g, b, 0, s, items, probs, (int64_t)BGRAM_ROWS);
+        }
+    }
+    if (nprobs > 0) {
+        if (ntmax <= 2) hipLaunchKernelGGL((k_bgram_finish<2>), dim3(nprobs), dim3(256), 0, s, probs);
+        else hipLaunchKernelGGL((k_bgram_finish<4>), dim3(nprobs), dim3(256), 0, s, probs);
+    }
+    return hipGetLastError();
 }
 
 }  // namespace nmfi

@@ -17,58 +17,65 @@
 
 namespace nmfi {
 
+// Gathers of one chunk: the chunk's (column, value) pairs are loaded 64 at a
+// time with one coalesced load per lane and handed to the lane groups with
+// ds_bpermute, so every gather's address is known up front and U row
+// gathers per lane are in flight at once.
 template <int VEC, int LPN, int NV>
-__global__ __launch_bounds__(256) void k_spmm(const SpChunk *__restrict__ chunks, int64_t nchunks,
-                                              const int32_t *__restrict__ colidx,
-                                              const float *__restrict__ vals,
-                                              const float *__restrict__ A, int r,
-                                              float *__restrict__ P, float *__restrict__ partial) {
-    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (w >= nchunks) return;
-    const SpChunk c = chunks[w];
+__device__ __forceinline__ void spmm_range(int start, int end, const int32_t *__restrict__ colidx,
+                                           const float *__restrict__ vals,
+                                           const float *__restrict__ A, int r,
+                                           float (&acc)[NV][VEC]) {
     const int lane = threadIdx.x & 63;
     constexpr int NPW = 64 / LPN;
-    constexpr int U = VEC == 4 ? 4 : 8;
+    constexpr int U = NPW >= 16 ? 1 : 16 / NPW;  // entries per slot per trip
     const int slot = lane / LPN, part = lane % LPN;
-    float acc[NV][VEC];
+    for (int b = start; b < end; b += 64) {
+        const int nb = min(64, end - b);
+        const int my_ci = lane < nb ? colidx[b + lane] : 0;
+        const float my_cv = lane < nb ? vals[b + lane] : 0.f;
+        for (int j0 = 0; j0 < nb; j0 += NPW * U) {
+            int ci[U];
+            float cv[U];
 #pragma unroll
-    for (int q = 0; q < NV; q++)
+            for (int u = 0; u < U; u++) {
+                const int j = j0 + u * NPW + slot;  // entry of this slot (< 64)
+                ci[u] = __builtin_amdgcn_ds_bpermute(j << 2, my_ci);
+                cv[u] = __builtin_bit_cast(
+                    float, __builtin_amdgcn_ds_bpermute(j << 2, __builtin_bit_cast(int, my_cv)));
+                if (j >= nb) cv[u] = 0.f, ci[u] = -1;
+            }
 #pragma unroll
-        for (int v = 0; v < VEC; v++) acc[q][v] = 0.f;
-
-    for (int t = c.start + slot; t < c.end; t += NPW * U) {
-        int ci[U];
-        float cv[U];
+            for (int u = 0; u < U; u++) {
+                if (ci[u] < 0) continue;
+                const float *arow = A + (int64_t)ci[u] * r;
 #pragma unroll
-        for (int u = 0; u < U; u++) {
-            const int tt = t + u * NPW;
-            const bool ok = tt < c.end;
-            ci[u] = ok ? colidx[tt] : -1;
-            cv[u] = ok ? vals[tt] : 0.f;
-        }
+                for (int q = 0; q < NV; q++) {
+                    const int col0 = (q * LPN + part) * VEC;
+                    if (col0 < r) {
+                        if constexpr (VEC == 4) {
+                            const f32x4 a4 = *(const f32x4 *)(arow + col0);
 #pragma unroll
-        for (int u = 0; u < U; u++) {
-            if (ci[u] < 0) continue;
-            const float *arow = A + (int64_t)ci[u] * r;
-#pragma unroll
-            for (int q = 0; q < NV; q++) {
-                const int col0 = (q * LPN + part) * VEC;
-                if (col0 < r) {
-                    if constexpr (VEC == 4) {
-                        const f32x4 a4 = *(const f32x4 *)(arow + col0);
-#pragma unroll
-                        for (int v = 0; v < 4; v++) acc[q][v] = fmaf(cv[u], a4[v], acc[q][v]);
-                    } else if constexpr (VEC == 2) {
-                        const f32x2 a2 = *(const f32x2 *)(arow + col0);
-                        acc[q][0] = fmaf(cv[u], a2[0], acc[q][0]);
-                        acc[q][1] = fmaf(cv[u], a2[1], acc[q][1]);
-                    } else {
-                        acc[q][0] = fmaf(cv[u], arow[col0], acc[q][0]);
+                            for (int v = 0; v < 4; v++) acc[q][v] = fmaf(cv[u], a4[v], acc[q][v]);
+                        } else if constexpr (VEC == 2) {
+                            const f32x2 a2 = *(const f32x2 *)(arow + col0);
+                            acc[q][0] = fmaf(cv[u], a2[0], acc[q][0]);
+                            acc[q][1] = fmaf(cv[u], a2[1], acc[q][1]);
+                        } else {
+                            acc[q][0] = fmaf(cv[u], arow[col0], acc[q][0]);
+                        }
                     }
                 }
             }
         }
     }
+}
+
+// sum the NPW slots' partial rows (fixed butterfly) and write slot 0's
+template <int VEC, int LPN, int NV>
+__device__ __forceinline__ void spmm_finish(float (&acc)[NV][VEC], int r, float *dst) {
+    const int lane = threadIdx.x & 63;
+    const int slot = lane / LPN, part = lane % LPN;
 #pragma unroll
     for (int off = LPN; off < 64; off <<= 1)
 #pragma unroll
@@ -76,7 +83,6 @@ __global__ __launch_bounds__(256) void k_spmm(const SpChunk *__restrict__ chunks
 #pragma unroll
             for (int v = 0; v < VEC; v++) acc[q][v] += __shfl_xor(acc[q][v], off);
     if (slot != 0) return;
-    float *dst = c.dest < 0 ? P + (int64_t)c.row * r : partial + (int64_t)c.dest * r;
 #pragma unroll
     for (int q = 0; q < NV; q++) {
         const int col0 = (q * LPN + part) * VEC;
@@ -87,15 +93,41 @@ __global__ __launch_bounds__(256) void k_spmm(const SpChunk *__restrict__ chunks
     }
 }
 
+template <int VEC, int LPN, int NV>
+__global__ __launch_bounds__(256) void k_spmm(const SpChunk *__restrict__ chunks, int64_t nchunks,
+                                              const int32_t *__restrict__ colidx,
+                                              const float *__restrict__ vals,
+                                              const float *__restrict__ A, int r,
+                                              float *__restrict__ P, float *__restrict__ partial) {
+    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (w >= nchunks) return;
+    const SpChunk c = chunks[w];
+    float acc[NV][VEC];
+#pragma unroll
+    for (int q = 0; q < NV; q++)
+#pragma unroll
+        for (int v = 0; v < VEC; v++) acc[q][v] = 0.f;
+    spmm_range<VEC, LPN, NV>(c.start, c.end, colidx, vals, A, r, acc);
+    spmm_finish<VEC, LPN, NV>(acc, r,
+                              c.dest < 0 ? P + (int64_t)c.row * r : partial + (int64_t)c.dest * r);
+}
+
 // P[row] = sum of the row's partial slots in chunk order
 __global__ __launch_bounds__(128) void k_spmm_fixup(const SpSplit *__restrict__ splits,
                                                     const float *__restrict__ partial, int r,
                                                     float *__restrict__ P) {
     const SpSplit s = splits[blockIdx.x];
     for (int a = threadIdx.x; a < r; a += 128) {
-        float acc = 0.f;
-        for (int c = 0; c < s.count; c++) acc += partial[(int64_t)(s.first + c) * r + a];
-        P[(int64_t)s.row * r + a] = acc;
+        // eight interleaved sums (loads in flight), combined in a fixed order
+        float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        const float *p = partial + (int64_t)s.first * r + a;
+        int c = 0;
+        for (; c + 8 <= s.count; c += 8)
+#pragma unroll
+            for (int q = 0; q < 8; q++) acc[q] += p[(int64_t)(c + q) * r];
+        for (int q = 0; c < s.count; c++, q++) acc[q] += p[(int64_t)c * r];
+        P[(int64_t)s.row * r + a] =
+            ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
     }
 }
 
@@ -223,44 +255,13 @@ __global__ __launch_bounds__(256) void k_spmm_rows(const int32_t *__restrict__ r
                                                    float *__restrict__ P) {
     const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (w >= nrows) return;
-    const int lane = threadIdx.x & 63;
-    constexpr int NPW = 64 / LPN;
-    const int slot = lane / LPN, part = lane % LPN;
     float acc[NV][VEC];
 #pragma unroll
     for (int q = 0; q < NV; q++)
 #pragma unroll
         for (int v = 0; v < VEC; v++) acc[q][v] = 0.f;
-    const int end = rowptr[w + 1];
-    for (int t = rowptr[w] + slot; t < end; t += NPW) {
-        const int ci = colidx[t];
-        const float cv = vals[t];
-        const float *arow = A + (int64_t)ci * r;
-#pragma unroll
-        for (int q = 0; q < NV; q++) {
-            const int col0 = (q * LPN + part) * VEC;
-            if (col0 < r) {
-#pragma unroll
-                for (int v = 0; v < VEC; v++) acc[q][v] = fmaf(cv, arow[col0 + v], acc[q][v]);
-            }
-        }
-    }
-#pragma unroll
-    for (int off = LPN; off < 64; off <<= 1)
-#pragma unroll
-        for (int q = 0; q < NV; q++)
-#pragma unroll
-            for (int v = 0; v < VEC; v++) acc[q][v] += __shfl_xor(acc[q][v], off);
-    if (slot != 0) return;
-    float *dst = P + w * r;
-#pragma unroll
-    for (int q = 0; q < NV; q++) {
-        const int col0 = (q * LPN + part) * VEC;
-        if (col0 < r) {
-#pragma unroll
-            for (int v = 0; v < VEC; v++) dst[col0 + v] = acc[q][v];
-        }
-    }
+    spmm_range<VEC, LPN, NV>(rowptr[w], rowptr[w + 1], colidx, vals, A, r, acc);
+    spmm_finish<VEC, LPN, NV>(acc, r, P + w * r);
 }
 
 hipError_t launch_spmm_rows(const int32_t *rowptr, int64_t nrows, const int32_t *colidx,

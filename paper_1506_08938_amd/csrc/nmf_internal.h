@@ -23,17 +23,8 @@ int hip_fail(hipError_t e, const char *what);
     } while (0)
 
 // ------------------------------------------------------------------ NQP solve
-// Rescaled problem of Algorithm 3 as the solve kernel reads it.
-struct RescaledHessian {
-    float *Q;    // R x R, row-major, symmetric, unit diagonal (pads and frozen
-                 // coordinates: identity rows/columns)
-    float *dsq;  // R: sqrt(Gamma_ii); 0 marks a frozen or pad coordinate
-    int R;       // padded size (>= r) the solve kernel was built for
-};
-
 struct NqpParams {
-    const float *Q;      // R x R rescaled Hessian
-    const float *dsq;    // R
+    const float *gram;   // r x r Hessian Gamma (rescaled while staging)
     const float *P;      // ncols x ldp: product rows (or h rows)
     float hsign, hadd;   // h = hsign * P + hadd
     float *X;            // ncols x ldx, in: x0 (ignored when cold), out: x
@@ -44,7 +35,7 @@ struct NqpParams {
     int ls_guard;
     int cold;
     int32_t *iters;                    // optional, per column
-    unsigned long long *counter;       // work counter; zeroed by the rescale kernel
+    unsigned long long *counter;       // work counter; must be zero at launch
     unsigned long long *inner_total;   // optional accumulator of iterations
 };
 
@@ -55,9 +46,6 @@ struct NqpVariant {
 NqpVariant nqp_pick(int r);
 int nqp_padded(int r);
 
-// Launches the rescale (Gamma -> Q, dsq; also zeroes the work counter).
-hipError_t launch_rescale(const float *gram, int r, int R, float *Q, float *dsq,
-                          unsigned long long *counter, hipStream_t s);
 // Launches the persistent solve kernel for the given variant.
 hipError_t launch_nqp(const NqpVariant &v, const NqpParams &p, hipStream_t s);
 hipError_t launch_nqp_l1(int E, const NqpParams &p, hipStream_t s);
@@ -87,16 +75,81 @@ hipError_t launch_spmm(const SpmmPlan &pl, const int32_t *colidx, const float *v
 hipError_t launch_spmm_rows(const int32_t *rowptr, int64_t nrows, const int32_t *colidx,
                             const float *vals, const float *A, int r, float *P, hipStream_t s);
 
-size_t gram_scratch_bytes(int r);
+size_t gram_scratch_bytes(int r, int64_t k);
+// Also zeroes *counter (when non-NULL) so that a solve can follow on the stream.
 hipError_t launch_gram(const float *A, int64_t k, int r, float l2, int precision, float *G,
-                       float *scratch, hipStream_t s);
+                       float *scratch, hipStream_t s, unsigned long long *counter = nullptr);
 
 size_t dense_scratch_bytes(int64_t m, int64_t n, int r);
+// split-K decomposition of P (C x r) = X (C x K) A shared by the single and
+// batched products: nsplit slices of kchunk (a multiple of 32) each
+int dense_nsplit(int64_t C, int64_t K);
+int64_t dense_kchunk(int64_t C, int64_t K);
 hipError_t launch_dense_product(const void *V, int bf16, int64_t m, int64_t n, int64_t ld,
                                 int trans, const float *A, int r, float *P, float *scratch,
                                 hipStream_t s);
 hipError_t launch_to_bf16(const float *x, int64_t rows, int64_t cols, int64_t ld, __bf16 *y,
                           hipStream_t s);
+
+// ------------------------------------------------------------------ batched
+// one block's work item: (problem index, chunk / row-block index)
+struct BItem {
+    int32_t prob, idx;
+};
+constexpr int BGRAM_ROWS = 512;  // rows of A per batched Gram work item
+struct BGramProb {
+    const float *A;
+    int64_t k;
+    int r;
+    float l2;
+    float *partial;  // ceil(k / BGRAM_ROWS) partials of NTILE * 1024 floats
+    float *G;        // r x r
+    int nchunks;
+};
+struct BProdProb {
+    const void *V;  // float (m x n, ld) or its BF16 copy (ld = n)
+    int64_t ld;
+    int64_t C, K;   // P is C x r, summed over K
+    const float *A; // K x r
+    int r;
+    float *P;
+    float *part;    // nsplit x C x r split-K partials (when nsplit > 1)
+    int64_t kchunk;
+    int nsplit;
+};
+struct BSolveProb {
+    const float *G;  // r x r
+    const float *P;  // C x r data products
+    float *X;        // C x r solutions (warm start unless cold)
+    int r;
+    float l1;
+    unsigned long long *inner;  // iterations of this problem's columns
+    int32_t *iters;             // optional per-column iteration counts
+    int cold;                   // 1: start from x0 = 0 (X is not read)
+};
+struct BSolveChunk {
+    int32_t prob, c0, c1;
+};
+size_t bgram_partial_floats(int r, int64_t k);
+hipError_t launch_bgram(const BItem *items, int64_t nitems, const BGramProb *probs, int nprobs,
+                        int ntmax, int precision, hipStream_t s);
+// items: (problem, row block * nsplit + slice); reduce items: (problem,
+// block of 4096 entries of P) for problems with nsplit > 1
+hipError_t launch_bdense(const BItem *items, int64_t nitems, const BProdProb *probs, int ntmax,
+                         bool xt, bool bf16, const BItem *red_items, int64_t nred, hipStream_t s);
+hipError_t launch_bnqp(const NqpVariant &v, const BSolveChunk *chunks, int nchunks,
+                       unsigned int *queue, const BSolveProb *probs, int max_inner, double eps,
+                       int ls_guard, hipStream_t s);
+hipError_t launch_bnqp_l1(int E, const BSolveChunk *chunks, int nchunks, unsigned int *queue,
+                          const BSolveProb *probs, int max_inner, double eps, int ls_guard,
+                          hipStream_t s);
+hipError_t launch_bnqp_l2(int E, const BSolveChunk *chunks, int nchunks, unsigned int *queue,
+                          const BSolveProb *probs, int max_inner, double eps, int ls_guard,
+                          hipStream_t s);
+hipError_t launch_bnqp_l4(int E, const BSolveChunk *chunks, int nchunks, unsigned int *queue,
+                          const BSolveProb *probs, int max_inner, double eps, int ls_guard,
+                          hipStream_t s);
+hipError_t launch_zero_u32(unsigned int *p, int n, hipStream_t s);
 
 // ------------------------------------------------------------------ objective
 size_t objective_scratch_bytes(const nmf_matrix *V, int r);
@@ -104,6 +157,22 @@ hipError_t launch_objective(const nmf_matrix *V, int r, const nmf_reg *reg, cons
                             const float *Ht, char *scratch, double *dev_out, hipStream_t s);
 hipError_t launch_kkt(const float *G, int r, const float *P, float hsign, float hadd,
                       const float *X, int64_t c, double *partial, double *dev_out, hipStream_t s);
+
+// ------------------------------------------------------------------ fold-in basis
+}  // namespace nmfi
+struct nmf_basis {
+    float *W = nullptr;  // m x r copy
+    int64_t m = 0;
+    int r = 0;
+    float l1 = 0.f, l2 = 0.f;
+    nmf_opts opt{};
+    nmfi::NqpVariant var{};
+    int R = 0;
+    char *ws = nullptr;  // G, Gram scratch
+    float *G = nullptr;
+};
+namespace nmfi {
+size_t plan_footprint(const nmf_matrix *V, int r, const nmf_opts *opt);
 
 // ------------------------------------------------------------------ misc
 hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t s);

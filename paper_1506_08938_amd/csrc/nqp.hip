@@ -1,42 +1,10 @@
-// Anti-lopsided rescale (Algorithm 3, "Re-scaling variables") and the
-// nnls_solve_batch entry point (Algorithm 3 on a batch of independent NQPs).
+// Kernel-variant choice and the nnls_solve_batch entry point (Algorithm 3 on
+// a batch of independent NQPs sharing one Hessian).
 #include <math.h>
 
 #include "nmf_internal.h"
 
 namespace nmfi {
-
-// One block.  dsq_i = sqrt(Gamma_ii) (0 when Gamma_ii <= 0: frozen; 0 for the
-// pad coordinates r <= i < R).  Q_ij = Gamma_ij / (dsq_i dsq_j), Q_ii = 1, and
-// the row/column of a frozen or pad coordinate is zero off the diagonal.
-// Also zeroes the solve kernel's work counter, so that a solve launched after
-// it on the same stream starts from column 0 (no memset node is needed).
-__global__ __launch_bounds__(256) void k_rescale(const float *__restrict__ gram, int r, int R,
-                                                 float *__restrict__ Q, float *__restrict__ dsq,
-                                                 unsigned long long *counter) {
-    __shared__ float sd[NMF_MAX_RANK];
-    for (int i = threadIdx.x; i < R; i += blockDim.x) {
-        const float d = i < r ? gram[(size_t)i * r + i] : 0.f;
-        sd[i] = d > 0.f ? sqrtf(d) : 0.f;
-        dsq[i] = sd[i];
-    }
-    __syncthreads();
-    for (int t = threadIdx.x; t < R * R; t += blockDim.x) {
-        const int i = t / R, j = t - (t / R) * R;
-        float v;
-        if (i == j) v = 1.f;
-        else if (i >= r || j >= r || sd[i] == 0.f || sd[j] == 0.f) v = 0.f;
-        else v = gram[(size_t)i * r + j] / (sd[i] * sd[j]);
-        Q[t] = v;
-    }
-    if (threadIdx.x == 0 && counter) *counter = 0ull;
-}
-
-hipError_t launch_rescale(const float *gram, int r, int R, float *Q, float *dsq,
-                          unsigned long long *counter, hipStream_t s) {
-    hipLaunchKernelGGL(k_rescale, dim3(1), dim3(256), 0, s, gram, r, R, Q, dsq, counter);
-    return hipGetLastError();
-}
 
 // Kernel variant per rank: one lane per column up to r = 32, two up to 64,
 // four up to 128; E is the smallest instantiated size that covers r.
@@ -99,24 +67,18 @@ extern "C" int nnls_solve_batch(int32_t r, int64_t ncols, const float *gram, con
         if (st) return st;
     }
     const NqpVariant v = nqp_pick(r);
-    const int R = v.E * v.L;
-    // workspace (every part 256-byte aligned): counter, dsq (R), Q (R*R)
-    const size_t qbytes = (size_t)R * R * sizeof(float);
-    char *ws = nullptr;
-    NMF_HIP(hipMallocAsync((void **)&ws, 1024 + qbytes, s));
-    unsigned long long *counter = (unsigned long long *)ws;
-    float *dsq = (float *)(ws + 256);
-    float *Q = (float *)(ws + 1024);
-    hipError_t e = launch_rescale(gram, r, R, Q, dsq, counter, s);
+    unsigned long long *counter = nullptr;
+    NMF_HIP(hipMallocAsync((void **)&counter, 256, s));
+    hipError_t e = launch_zero_u64(counter, 1, s);
     if (e == hipSuccess) {
         NqpParams p{};
-        p.Q = Q; p.dsq = dsq; p.P = h; p.hsign = 1.f; p.hadd = 0.f; p.X = X;
+        p.gram = gram; p.P = h; p.hsign = 1.f; p.hadd = 0.f; p.X = X;
         p.ncols = ncols; p.r = r; p.ldp = r; p.ldx = r;
         p.max_inner = opt->max_inner; p.eps = opt->eps; p.ls_guard = opt->ls_guard ? 1 : 0;
         p.cold = 0; p.iters = iters; p.counter = counter; p.inner_total = nullptr;
         e = launch_nqp(v, p, s);
     }
-    hipError_t e2 = hipFreeAsync(ws, s);
+    hipError_t e2 = hipFreeAsync(counter, s);
     if (e != hipSuccess) return hip_fail(e, "nnls_solve_batch launch");
     if (e2 != hipSuccess) return hip_fail(e2, "hipFreeAsync");
     return NMF_OK;

@@ -129,28 +129,72 @@ __device__ __forceinline__ void matvec(const float *__restrict__ qseg, const flo
 
 __device__ __forceinline__ bool passive(float y, float g) { return y > 0.f || g < 0.f; }
 
-// Occupancy target: about 4E live registers per lane (y, g, the search
-// direction and the product), so ask for as many waves per SIMD as fit.
-template <int E>
-constexpr int nqp_waves_per_eu() {
-    return E <= 12 ? 6 : (E <= 20 ? 4 : (E <= 28 ? 3 : 2));
+// min and max(., 0) as one v_med3_f32 each (no NaN canonicalisation: every
+// operand here is finite)
+__device__ __forceinline__ float min2(float a, float b) {
+    return __builtin_amdgcn_fmed3f(a, b, -__builtin_huge_valf());
+}
+__device__ __forceinline__ float relu(float a) {
+    return __builtin_amdgcn_fmed3f(a, 0.f, __builtin_huge_valf());
 }
 
-template <int E, int L>
-__global__ __launch_bounds__(NQP_BLOCK)
-__attribute__((amdgpu_waves_per_eu(nqp_waves_per_eu<E>(), 8))) void k_nqp(const NqpParams a) {
-    constexpr int R = E * L;
-    constexpr int SQ = ((R + 3) & ~3) + 4;
-    __shared__ float sQ[R * SQ];
-    __shared__ float sD[R];
+// Occupancy target: about 4E live registers per lane (y, g, the search
+// direction and the product), so ask for as many waves per SIMD as fit.
+#ifndef NMF_NQP_WPE
+#define NMF_NQP_WPE 0  // 0: occupancy from the table below
+#endif
+#ifndef NMF_NQP_ONEHOT_LDS
+#define NMF_NQP_ONEHOT_LDS 0  // 0: compare/select (measured faster); 1: y update through the LDS unit vector
+#endif
 
-    for (int t = threadIdx.x; t < R * R; t += NQP_BLOCK) {
-        const int i = t / R, j = t - (t / R) * R;
-        sQ[i * SQ + j] = a.Q[t];
+template <int E>
+constexpr int nqp_waves_per_eu() {
+    return NMF_NQP_WPE ? NMF_NQP_WPE : (E <= 12 ? 6 : (E <= 20 ? 4 : (E <= 28 ? 3 : 2)));
+}
+
+// Where one solve's columns come from and go to.
+struct ColumnIO {
+    const float *P;    // column j's data row: P + j * ldp (h = hsign * P + hadd)
+    float hsign, hadd;
+    float *X;          // column j's start point / solution: X + j * ldx
+    int ldp, ldx;
+    int32_t *iters;    // optional, per column
+    int r;
+    int max_inner;
+    double eps;
+    int ls_guard;
+    int cold;
+};
+
+// Work counters: a global 64-bit counter over [0, n) columns, or a 32-bit LDS
+// counter over the columns of one chunk.
+struct GlobalFetch {
+    unsigned long long *ctr;
+    int64_t n;
+    __device__ __forceinline__ unsigned long long take(int cnt) {
+        return atomicAdd(ctr, (unsigned long long)cnt);
     }
-    for (int t = threadIdx.x; t < R; t += NQP_BLOCK) sD[t] = a.dsq[t];
-    __syncthreads();
+};
+struct LdsFetch {
+    unsigned int *ctr;
+    int64_t n;
+    __device__ __forceinline__ unsigned long long take(int cnt) {
+        return (unsigned long long)atomicAdd(ctr, (unsigned int)cnt);
+    }
+};
 
+// One wave's share of a batch of NQPs sharing the rescaled Hessian sQ (LDS,
+// R x SQ) and its sqrt-diagonal sD (LDS): every group of L lanes solves
+// columns taken from `fetch` until none are left.  Adds the iterations of the
+// columns it finished (counted once per group) to my_inner.
+// sZ (LDS, 2R floats) holds a single 1 at index R: sZ + R + base - p is this
+// lane's segment of the unit vector e_p, so the coordinate-descent update of y
+// is one FMA per entry, fma(-m, 1, y) = y - m at p and y elsewhere.
+template <int E, int L, int SQ, class Fetch>
+__device__ __forceinline__ void nqp_columns(const float *__restrict__ sQ,
+                                            const float *__restrict__ sD,
+                                            const float *__restrict__ sZ, const ColumnIO &a,
+                                            Fetch &fetch, unsigned long long &my_inner) {
     const int lane = threadIdx.x & 63;
     const int sub = lane & (L - 1);
     const int base = sub * E;
@@ -165,7 +209,6 @@ __attribute__((amdgpu_waves_per_eu(nqp_waves_per_eu<E>(), 8))) void k_nqp(const 
     int64_t col = 0;
     double n0 = 0.0;
     int k = 0;
-    unsigned long long my_inner = 0;
 
     for (;;) {
         // ------------------------------------------------ refill finished groups
@@ -174,17 +217,17 @@ __attribute__((amdgpu_waves_per_eu(nqp_waves_per_eu<E>(), 8))) void k_nqp(const 
             if (needmask) {
                 const int cnt = __popcll(needmask);
                 unsigned long long b0 = 0;
-                if (lane == 0) b0 = atomicAdd(a.counter, (unsigned long long)cnt);
+                if (lane == 0) b0 = fetch.take(cnt);
                 const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)(b0 & 0xffffffffull));
                 const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b0 >> 32));
                 b0 = ((unsigned long long)hi << 32) | lo;
-                if (b0 + (unsigned long long)cnt >= (unsigned long long)a.ncols) exhausted = true;
+                if (b0 + (unsigned long long)cnt >= (unsigned long long)fetch.n) exhausted = true;
                 const int leader = lane - sub;
                 const int rank = __popcll(needmask & ((1ull << leader) - 1ull));
                 bool fresh = false;
                 if (!active) {
                     const unsigned long long c = b0 + (unsigned long long)rank;
-                    if (c < (unsigned long long)a.ncols) { col = (int64_t)c; fresh = true; }
+                    if (c < (unsigned long long)fetch.n) { col = (int64_t)c; fresh = true; }
                 }
                 if (fresh) {
                     // y0 = x0 * sqrt(diag), q = h / sqrt(diag), g0 = Q y0 + q
@@ -239,7 +282,7 @@ __attribute__((amdgpu_waves_per_eu(nqp_waves_per_eu<E>(), 8))) void k_nqp(const 
                 if (den > 0.f) {
                     const float alpha = s / den;
 #pragma unroll
-                    for (int e = 0; e < E; e++) gb[e] = fmaxf(0.f, fmaf(-alpha, gb[e], y[e])) - y[e];
+                    for (int e = 0; e < E; e++) gb[e] = relu(fmaf(-alpha, gb[e], y[e])) - y[e];
                     matvec<E, L, SQ>(qseg, gb, u);
                     bool accept = true;
                     if (a.ls_guard) {
@@ -256,17 +299,31 @@ __attribute__((amdgpu_waves_per_eu(nqp_waves_per_eu<E>(), 8))) void k_nqp(const 
             }
             // ------------------------------------------------ r greedy CD steps
             for (int t = 0; t < r; t++) {
-                float best = -1.f, bm = 0.f;
-                int bi = 0;
+                // best step and decrease of every own coordinate (independent)
+                float Dv[E], mv[E];
+                int iv[E];
 #pragma unroll
                 for (int e = 0; e < E; e++) {
-                    const float m = fminf(y[e], g[e]);        // -(best step)
-                    const float D = m * fmaf(2.f, g[e], -m);  // 2 x decrease
-                    const bool c = D > best;
-                    best = c ? D : best;
-                    bi = c ? e : bi;
-                    bm = c ? m : bm;
+                    const float m = min2(y[e], g[e]);              // -(best step)
+                    mv[e] = m;
+                    Dv[e] = m * fmaf(2.f, g[e], -m);               // 2 x decrease
+                    iv[e] = e;
                 }
+                // argmax as a tree (depth log2 E instead of a chain of E): the
+                // right operand holds higher indices and wins only when
+                // strictly larger, so ties keep the lowest index
+#pragma unroll
+                for (int w = 1; w < E; w <<= 1) {
+#pragma unroll
+                    for (int e = 0; e + w < E; e += 2 * w) {
+                        const bool c = Dv[e + w] > Dv[e];
+                        Dv[e] = c ? Dv[e + w] : Dv[e];
+                        mv[e] = c ? mv[e + w] : mv[e];
+                        iv[e] = c ? iv[e + w] : iv[e];
+                    }
+                }
+                float best = Dv[0], bm = mv[0];
+                int bi = iv[0];
                 bi += base;
                 grp_argmax<L>(best, bi, bm);
                 const bool go = best > 0.f;
@@ -274,10 +331,17 @@ __attribute__((amdgpu_waves_per_eu(nqp_waves_per_eu<E>(), 8))) void k_nqp(const 
                 lds_reload_fence();
                 if (go) {
                     const float *row = qseg + bi * SQ;
+                    const float *onehot = sZ + (E * L) + base - bi;
 #pragma unroll
                     for (int e = 0; e < E; e++) g[e] = fmaf(-bm, row[e], g[e]);
+#if NMF_NQP_ONEHOT_LDS
+#pragma unroll
+                    for (int e = 0; e < E; e++) y[e] = fmaf(-bm, onehot[e], y[e]);
+#else
+                    (void)onehot;
 #pragma unroll
                     for (int e = 0; e < E; e++) y[e] = (base + e == bi) ? y[e] - bm : y[e];
+#endif
                 }
             }
             // ------------------------------------------------ stopping rule
@@ -307,12 +371,116 @@ __attribute__((amdgpu_waves_per_eu(nqp_waves_per_eu<E>(), 8))) void k_nqp(const 
             }
         }
     }
-    if (a.inner_total) {
-        // wave total of finished columns' iterations, one atomic per wave
-        unsigned long long v = my_inner;
-        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-        if (lane == 0 && v) atomicAdd(a.inner_total, v);
+}
+
+template <int R>
+constexpr int nqp_stride() {
+    return ((R + 3) & ~3) + 4;
+}
+
+// Anti-lopsided rescale (Algorithm 3, "Re-scaling variables") while staging
+// into LDS: sD[i] = sqrt(Gamma_ii) (0 when Gamma_ii <= 0, a frozen coordinate,
+// and for the pads r <= i < R); sQ[i][j] = Gamma_ij / (sD[i] sD[j]) with a
+// unit diagonal, zero rows/columns off the diagonal for frozen or pad
+// coordinates.  Every block forms the same Q from the same Gamma.
+template <int R, int SQ>
+__device__ __forceinline__ void stage_q(const float *__restrict__ gram, int r, float *sQ,
+                                        float *sD, float *sZ) {
+    for (int t = threadIdx.x; t < 2 * R; t += NQP_BLOCK) sZ[t] = t == R ? 1.f : 0.f;
+    for (int i = threadIdx.x; i < R; i += NQP_BLOCK) {
+        const float d = i < r ? gram[(size_t)i * r + i] : 0.f;
+        sD[i] = d > 0.f ? sqrtf(d) : 0.f;
     }
+    __syncthreads();
+    for (int t = threadIdx.x; t < R * R; t += NQP_BLOCK) {
+        const int i = t / R, j = t - (t / R) * R;
+        float v;
+        if (i == j) v = 1.f;
+        else if (i >= r || j >= r || sD[i] == 0.f || sD[j] == 0.f) v = 0.f;
+        else v = gram[(size_t)i * r + j] / (sD[i] * sD[j]);
+        sQ[i * SQ + j] = v;
+    }
+}
+
+__device__ __forceinline__ void flush_inner(unsigned long long v, unsigned long long *total) {
+    if (!total) return;
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+    if ((threadIdx.x & 63) == 0 && v) atomicAdd(total, v);
+}
+
+template <int E, int L>
+__global__ __launch_bounds__(NQP_BLOCK)
+__attribute__((amdgpu_waves_per_eu(nqp_waves_per_eu<E>(), 8))) void k_nqp(const NqpParams a) {
+    constexpr int R = E * L;
+    constexpr int SQ = nqp_stride<R>();
+    __shared__ float sQ[R * SQ];
+    __shared__ float sD[R];
+    __shared__ float sZ[2 * R];
+    stage_q<R, SQ>(a.gram, a.r, sQ, sD, sZ);
+    __syncthreads();
+    ColumnIO io{a.P, a.hsign, a.hadd, a.X, a.ldp, a.ldx, a.iters, a.r, a.max_inner, a.eps,
+                a.ls_guard, a.cold};
+    GlobalFetch f{a.counter, a.ncols};
+    unsigned long long my_inner = 0;
+    nqp_columns<E, L, SQ>(sQ, sD, sZ, io, f, my_inner);
+    flush_inner(my_inner, a.inner_total);
+}
+
+// Many problems at once (the batched fit): a block takes chunks (problem,
+// columns [c0, c1)) from a queue, stages that problem's rescaled Hessian and
+// solves the chunk's columns; its lane groups refill from an LDS counter.
+// All problems of one launch share the kernel variant (E, L).
+template <int E, int L>
+__global__ __launch_bounds__(NQP_BLOCK)
+__attribute__((amdgpu_waves_per_eu(nqp_waves_per_eu<E>(), 8))) void k_bnqp(
+    const BSolveChunk *__restrict__ chunks, int nchunks, unsigned int *queue,
+    const BSolveProb *__restrict__ probs, int max_inner, double eps, int ls_guard) {
+    constexpr int R = E * L;
+    constexpr int SQ = nqp_stride<R>();
+    __shared__ float sQ[R * SQ];
+    __shared__ float sD[R];
+    __shared__ float sZ[2 * R];
+    __shared__ unsigned int s_task, s_ctr;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            s_task = atomicAdd(queue, 1u);
+            s_ctr = 0u;
+        }
+        __syncthreads();
+        const unsigned int t = s_task;
+        if (t >= (unsigned int)nchunks) break;
+        const BSolveChunk ch = chunks[t];
+        const BSolveProb P = probs[ch.prob];
+        stage_q<R, SQ>(P.G, P.r, sQ, sD, sZ);
+        __syncthreads();
+        ColumnIO io{P.P + (int64_t)ch.c0 * P.r, -1.f, P.l1, P.X + (int64_t)ch.c0 * P.r, P.r, P.r,
+                    P.iters ? P.iters + ch.c0 : nullptr, P.r, max_inner, eps, ls_guard, P.cold};
+        LdsFetch f{&s_ctr, (int64_t)(ch.c1 - ch.c0)};
+        unsigned long long my_inner = 0;
+        nqp_columns<E, L, SQ>(sQ, sD, sZ, io, f, my_inner);
+        flush_inner(my_inner, P.inner);
+        __syncthreads();
+    }
+}
+
+template <int E, int L>
+hipError_t launch_bnqp_t(const BSolveChunk *chunks, int nchunks, unsigned int *queue,
+                         const BSolveProb *probs, int max_inner, double eps, int ls_guard,
+                         hipStream_t s) {
+    if (nchunks <= 0) return hipSuccess;
+    static int per_cu = -1;
+    if (per_cu < 0) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bnqp<E, L>, NQP_BLOCK, 0) !=
+                hipSuccess || nb < 1)
+            nb = 1;
+        per_cu = nb;
+    }
+    const int64_t cap = (int64_t)per_cu * device_cu_count();
+    const int grid = (int)(nchunks < cap ? nchunks : cap);
+    hipLaunchKernelGGL((k_bnqp<E, L>), dim3(grid), dim3(NQP_BLOCK), 0, s, chunks, nchunks, queue,
+                       probs, max_inner, eps, ls_guard);
+    return hipGetLastError();
 }
 
 template <int E, int L>

@@ -22,7 +22,9 @@ MAX_RANK = 128
 EXPORTS = [
     "nmf_default_opts", "nmf_last_error", "nnls_solve_batch", "nmf_gram", "nmf_product",
     "nmf_plan_create", "nmf_plan_run", "nmf_plan_destroy", "nmf_plan_profile", "nmf_plan_timers",
-    "nmf_fit", "nmf_objective",
+    "nmf_fit", "nmf_objective", "nmf_fit_batched",
+    "nmf_server_create", "nmf_server_submit", "nmf_server_poll", "nmf_server_wait",
+    "nmf_server_stats", "nmf_server_destroy",
     "nmf_basis_create", "nmf_foldin", "nmf_basis_destroy",
 ]
 
@@ -55,6 +57,20 @@ class NmfStats(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class NmfProblem(ctypes.Structure):
+    _fields_ = [("V", NmfMatrix), ("r", ctypes.c_int32), ("reg", NmfReg),
+                ("W", ctypes.c_void_p), ("Ht", ctypes.c_void_p)]
+
+
+NMF_REQ_FOLDIN, NMF_REQ_FIT = 0, 1
+
+
+class NmfRequest(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("V", NmfMatrix), ("out", ctypes.c_void_p),
+                ("iters", ctypes.c_void_p), ("r", ctypes.c_int32), ("reg", NmfReg),
+                ("fit_opts", NmfOpts), ("W", ctypes.c_void_p), ("Ht", ctypes.c_void_p)]
 
 
 class NmfError(RuntimeError):
@@ -100,6 +116,19 @@ def lib():
         L.nmf_objective.argtypes = [ctypes.POINTER(NmfMatrix), ctypes.c_int32,
                                     ctypes.POINTER(NmfReg), _vp, _vp, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_double), _vp]
+        L.nmf_fit_batched.argtypes = [ctypes.c_int32, ctypes.POINTER(NmfProblem),
+                                      ctypes.POINTER(NmfOpts), ctypes.POINTER(NmfStats), _vp]
+        L.nmf_server_create.argtypes = [_vp, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int64,
+                                        ctypes.POINTER(_vp)]
+        L.nmf_server_submit.argtypes = [_vp, ctypes.POINTER(NmfRequest),
+                                        ctypes.POINTER(ctypes.c_uint64)]
+        L.nmf_server_poll.argtypes = [_vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32),
+                                      ctypes.POINTER(ctypes.c_double)]
+        L.nmf_server_wait.argtypes = [_vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)]
+        L.nmf_server_stats.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+        L.nmf_server_destroy.argtypes = [_vp]
+        L.nmf_server_destroy.restype = None
         L.nmf_basis_create.argtypes = [_vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_float,
                                        ctypes.c_float, ctypes.POINTER(NmfOpts),
                                        ctypes.POINTER(_vp), _vp]
@@ -336,6 +365,118 @@ class Basis:
         if self.h:
             lib().nmf_basis_destroy(self.h)
             self.h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fit_batched(problems, opt: NmfOpts, want_stats=True):
+    """nmf_fit_batched.  problems: list of dicts with V (device float32 m x n),
+    r, reg (NmfReg), W (m x r) and Ht (n x r) device tensors, updated in place.
+    Returns the per-problem statistics."""
+    torch = _torch()
+    arr = (NmfProblem * len(problems))()
+    keep = []
+    for i, pb in enumerate(problems):
+        V = pb["V"]
+        _dev(V, torch.float32, "V")
+        m, n = V.shape
+        r = pb["r"]
+        _dev(pb["W"], torch.float32, "W", (m, r))
+        _dev(pb["Ht"], torch.float32, "Ht", (n, r))
+        d = DeviceMatrix(V)
+        keep.append(d)
+        arr[i].V = d.m
+        arr[i].r = r
+        arr[i].reg = pb["reg"]
+        arr[i].W = pb["W"].data_ptr()
+        arr[i].Ht = pb["Ht"].data_ptr()
+    st = (NmfStats * len(problems))() if want_stats else None
+    check(lib().nmf_fit_batched(len(problems), arr, ctypes.byref(opt), st, stream_ptr()))
+    return [x.as_dict() for x in st] if want_stats else None
+
+
+def sparse_request(csr_t, m):
+    """DeviceMatrix for new columns given as CSR of their transpose (c x m):
+    the t_* arrays of an m x c matrix."""
+    c = csr_t.shape[0]
+    d = DeviceMatrix(csr_t, with_transpose=False)
+    mm = d.m
+    mm.t_rowptr, mm.t_colidx, mm.t_vals = mm.rowptr, mm.colidx, mm.vals
+    mm.rows, mm.cols = m, c
+    return d
+
+
+class Server:
+    """nmf_server_*: continuously batched fold-in requests and small fits."""
+
+    def __init__(self, basis: Basis, hbm_budget=1 << 30, max_slots=2, max_batch_cols=16384):
+        self.basis = basis
+        self.h = _vp()
+        self.refs = {}
+        check(lib().nmf_server_create(basis.h, int(hbm_budget), int(max_slots),
+                                      int(max_batch_cols), ctypes.byref(self.h)))
+
+    def _submit(self, req, refs):
+        t = ctypes.c_uint64()
+        check(lib().nmf_server_submit(self.h, ctypes.byref(req), ctypes.byref(t)))
+        self.refs[t.value] = refs
+        return t.value
+
+    def submit_foldin(self, Vnew: DeviceMatrix, out, iters=None):
+        torch = _torch()
+        _dev(out, torch.float32, "out", (Vnew.m.cols, self.basis.r))
+        _dev(iters, torch.int32, "iters", (Vnew.m.cols,))
+        q = NmfRequest()
+        q.kind = NMF_REQ_FOLDIN
+        q.V = Vnew.m
+        q.out = out.data_ptr()
+        q.iters = _ptr(iters)
+        return self._submit(q, (Vnew, out, iters))
+
+    def submit_fit(self, V, r, regw: NmfReg, opt: NmfOpts, W, Ht):
+        torch = _torch()
+        d = DeviceMatrix(V)
+        m, n = V.shape
+        _dev(W, torch.float32, "W", (m, r))
+        _dev(Ht, torch.float32, "Ht", (n, r))
+        q = NmfRequest()
+        q.kind = NMF_REQ_FIT
+        q.V = d.m
+        q.r = r
+        q.reg = regw
+        q.fit_opts = opt
+        q.W = W.data_ptr()
+        q.Ht = Ht.data_ptr()
+        return self._submit(q, (d, W, Ht))
+
+    def poll(self, ticket):
+        done = ctypes.c_int32(); lat = ctypes.c_double()
+        check(lib().nmf_server_poll(self.h, ticket, ctypes.byref(done), ctypes.byref(lat)))
+        return bool(done.value), lat.value
+
+    def wait(self, ticket=0):
+        lat = ctypes.c_double()
+        check(lib().nmf_server_wait(self.h, ticket, ctypes.byref(lat)))
+        if ticket:
+            self.refs.pop(ticket, None)
+            return lat.value
+        self.refs.clear()
+        return None
+
+    def stats(self):
+        a = ctypes.c_int64(); b = ctypes.c_int64(); c = ctypes.c_int64()
+        check(lib().nmf_server_stats(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return {"completed": a.value, "columns": b.value, "batches": c.value}
+
+    def close(self):
+        if self.h:
+            lib().nmf_server_destroy(self.h)
+            self.h = _vp()
+            self.refs.clear()
 
     def __del__(self):
         try:

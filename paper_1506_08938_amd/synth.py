@@ -107,10 +107,10 @@ def zipf_rows(m, ncols, per_row, s, seed, batch=20000):
     cdf = np.cumsum(pk); cdf /= cdf[-1]
     perm = g.permutation(ncols).astype(np.int32)
     out = np.empty((m, per_row), dtype=np.int32)
-    draws = max(2 * per_row, per_row + 64)
     for r0 in range(0, m, batch):
         rows = np.arange(r0, min(m, r0 + batch))
         todo = rows
+        draws = max(2 * per_row, per_row + 64)
         while todo.size:
             u = g.random((todo.size, draws))
             d = np.searchsorted(cdf, u, side="right").astype(np.int32)

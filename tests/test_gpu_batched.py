@@ -1,0 +1,90 @@
+"""nmf_fit_batched (many uneven problems per launch, one hipGraph) on the GPU:
+every problem's result equals its own nmf_fit run (the same kernels' per-
+problem arithmetic, so bitwise), and one outer iteration agrees with the FP64
+oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1506_08938_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def T(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def H(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy().astype(np.float64)
+
+
+def problems(count, first_seed=0):
+    probs = synth.workload4(count=max(count, 1024), first=count)
+    return probs
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batched_equals_solo_fits(precision):
+    from paper_1506_08938_amd import native as nat
+    probs = problems(24)
+    # make the regularisation differ per problem
+    for i, p in enumerate(probs):
+        p["reg"] = (0.01 * (i % 2), 0.02 * (i % 3 == 0), 0.05 * (i % 4 == 1), 0.01 * (i % 5 == 2))
+    opt = nat.opts(max_outer=3, precision=precision)
+    batch = [dict(V=T(p["V"]), r=p["r"], reg=nat.reg(*p["reg"]), W=T(p["W0"]), Ht=T(p["Ht0"]))
+             for p in probs]
+    stats = nat.fit_batched(batch, opt)
+    for i, p in enumerate(probs):
+        W = T(p["W0"]); Ht = T(p["Ht0"])
+        Vd = nat.DeviceMatrix(T(p["V"]))
+        _, st = nat.fit(Vd, p["r"], nat.reg(*p["reg"]), opt, W, Ht, want_trace=False)
+        assert np.array_equal(H(batch[i]["W"]), H(W)), i
+        assert np.array_equal(H(batch[i]["Ht"]), H(Ht)), i
+        assert stats[i]["inner_total"] == st["inner_total"]
+        assert stats[i]["loss"] == pytest.approx(st["loss"], rel=1e-12)
+
+
+def test_batched_one_step_matches_oracle():
+    from paper_1506_08938_amd import native as nat
+    probs = problems(12)
+    FIX = dict(max_inner=10, eps=0.0)
+    # common converging state from the oracle
+    states = []
+    for p in probs:
+        o = oracle.nmf_fit(p["V"], p["r"], p["reg"], p["W0"], p["Ht0"], T=5, want_trace=False, **FIX)
+        states.append((o["W"].astype(np.float32), o["Ht"].astype(np.float32)))
+    batch = [dict(V=T(p["V"]), r=p["r"], reg=nat.reg(*p["reg"]), W=T(w), Ht=T(h))
+             for p, (w, h) in zip(probs, states)]
+    nat.fit_batched(batch, nat.opts(max_outer=1, **FIX), want_stats=False)
+    # These problems are exactly low rank plus 1% noise, so after a few
+    # iterations J is a small fraction of J(0) = ||V||^2 / 2 and FP32 rounding
+    # of the products (relative 1e-7 of ||V||^2) shows up amplified in J / J.
+    # The bound is on the error relative to J(0); J / J is printed.
+    worst = worst_rel = 0.0
+    for p, (w, h), b in zip(probs, states, batch):
+        o = oracle.nmf_fit(p["V"], p["r"], p["reg"], w, h, T=1, want_trace=False, **FIX)
+        Jg = oracle.objective(p["V"], H(b["W"]), H(b["Ht"]), p["reg"])
+        Jo = oracle.objective(p["V"], o["W"], o["Ht"], p["reg"])
+        J0 = 0.5 * float(np.sum(np.asarray(p["V"], dtype=np.float64) ** 2))
+        worst = max(worst, abs(Jg - Jo) / J0)
+        worst_rel = max(worst_rel, abs(Jg - Jo) / Jo)
+    print(f"batched one step from oracle states: worst |dJ|/J(0) {worst:.2e}, |dJ|/J {worst_rel:.2e}")
+    assert worst < 1e-6
+
+
+def test_batched_edge_cases():
+    from paper_1506_08938_amd import native as nat
+    g = np.random.default_rng(3)
+    shapes = [(1, 1, 1), (1, 70, 3), (65, 1, 2), (64, 64, 64), (130, 97, 33)]
+    batch = []
+    for m, n, r in shapes:
+        V = g.random((m, n)).astype(np.float32)
+        batch.append(dict(V=T(V), r=r, reg=nat.reg(), W=T(g.random((m, r))), Ht=T(g.random((n, r)))))
+    st = nat.fit_batched(batch, nat.opts(max_outer=2))
+    for s, (m, n, r) in zip(st, shapes):
+        assert np.isfinite(s["loss"]) and s["inner_total"] >= 2 * (m + n)
+    assert nat.fit_batched([], nat.opts()) == []

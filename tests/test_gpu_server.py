@@ -1,0 +1,100 @@
+"""Serving (continuously batched fold-in requests and small fits) on the GPU:
+a request's result is the same alone and in a mix of other requests
+(bitwise: a column's arithmetic does not depend on its batch), equals the
+direct nmf_foldin / nmf_fit result, and matches the FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1506_08938_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def T(a, dt=np.float32):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).cuda()
+
+
+def H(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy().astype(np.float64)
+
+
+@pytest.fixture(scope="module")
+def basis():
+    from paper_1506_08938_amd import native as nat
+    m, r = 4000, 48
+    W = np.random.default_rng(5).gamma(2.0, 0.5, (m, r)).astype(np.float32)
+    B = nat.Basis(T(W), l1=0.05, l2=0.0, opt=nat.opts(max_inner=100, eps=1e-3))
+    yield B, W
+    B.close()
+
+
+def test_alone_equals_mix_equals_direct(basis):
+    import torch
+    from paper_1506_08938_amd import native as nat
+    B, W = basis
+    m, r = W.shape
+    req = synth.foldin_columns(m, 300, 60, seed=1)
+    R = nat.sparse_request(req, m)
+    # direct call
+    direct = H(B.foldin(R))
+    # alone through the server
+    S = nat.Server(B, hbm_budget=1 << 30, max_slots=2, max_batch_cols=4096)
+    out_alone = torch.empty((300, r), device="cuda")
+    S.wait(S.submit_foldin(R, out_alone))
+    # in a mix: many requests of other sizes (sparse and dense), a fit, and R again
+    mix_out = []
+    tickets = []
+    sizes = synth.request_sizes(40, seed=9, cmax=2000)
+    for i, c in enumerate(sizes):
+        q = synth.foldin_columns(m, int(c), 60, seed=100 + i)
+        if i % 7 == 3:
+            Rq = nat.DeviceMatrix(T(q.toarray().T))  # dense request
+        else:
+            Rq = nat.sparse_request(q, m)
+        o = torch.empty((int(c), r), device="cuda")
+        tickets.append(S.submit_foldin(Rq, o))
+        if i == 20:
+            out_mix = torch.empty((300, r), device="cuda")
+            t_r = S.submit_foldin(R, out_mix)
+            fitp = synth.workload4(count=1024, first=1)[0]
+            Wf, Hf = T(fitp["W0"]), T(fitp["Ht0"])
+            t_fit = S.submit_fit(T(fitp["V"]), fitp["r"], nat.reg(), nat.opts(max_outer=3), Wf, Hf)
+    S.wait()
+    assert np.array_equal(H(out_alone), direct)
+    assert np.array_equal(H(out_mix), direct)
+    # the fit request equals nmf_fit
+    W2, H2 = T(fitp["W0"]), T(fitp["Ht0"])
+    nat.fit(nat.DeviceMatrix(T(fitp["V"])), fitp["r"], nat.reg(), nat.opts(max_outer=3), W2, H2,
+            want_trace=False)
+    assert np.array_equal(H(Wf), H(W2)) and np.array_equal(H(Hf), H(H2))
+    st = S.stats()
+    assert st["completed"] == 43 and st["batches"] <= 43
+    S.close()
+    # and the fold-in matches the FP64 oracle (cold start, same stopping rule)
+    G = oracle.gram(W, 0.0)
+    P = oracle.product_csr(req, W, 1)
+    xo, _ = oracle.nqp_batch(G.astype(np.float32), (-P + np.float32(0.05)).astype(np.float32),
+                             np.zeros((300, r)), max_inner=100, eps=1e-3)
+    e = np.linalg.norm(direct - xo, axis=1) / np.maximum(np.linalg.norm(xo, axis=1), 1e-30)
+    assert np.median(e) < 1e-3
+
+
+def test_budget_refusal_and_latency(basis):
+    import torch
+    from paper_1506_08938_amd import native as nat
+    B, W = basis
+    m, r = W.shape
+    S = nat.Server(B, hbm_budget=200000, max_slots=1, max_batch_cols=1024)
+    small = nat.sparse_request(synth.foldin_columns(m, 50, 20, seed=2), m)
+    big = nat.sparse_request(synth.foldin_columns(m, 3000, 20, seed=3), m)
+    o = torch.empty((50, r), device="cuda")
+    lat = S.wait(S.submit_foldin(small, o))
+    assert lat > 0
+    with pytest.raises(nat.NmfError) as ei:
+        S.submit_foldin(big, torch.empty((3000, r), device="cuda"))
+    assert ei.value.status == nat.NMF_E_BUSY
+    S.close()
