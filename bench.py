@@ -17,7 +17,16 @@ the FP64 oracle timed on the host cores for one outer iteration of the same
 workload from the same start point (its first --cpu-iters outer
 iterations).
 
+The "serving" entry covers the fold-in side of the metric: a basis W
+(100000 x 128) fitted on the device to Gamma-factor data stays resident;
+fold-in requests of c ~ logU[1, 8192] sparse columns (0.5% density) and 5%
+small full fits go through nmf_server_*.  First every request is submitted at
+once (saturated: fold-in columns solved per second), then the same mix
+arrives as a Poisson stream at --serve-load times the saturated request rate
+and the per-request latencies (submission to completion) give p50/p99.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--cpu-iters T]
+                       [--no-serve] [--serve-requests N] [--serve-load F]
        python bench.py --calibrate-copy   (1 GiB device copy, for counter scaling)
 """
 import argparse
@@ -45,6 +54,97 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def serving_leg(native, synth, torch, n_req, load, seed=5005):
+    """Saturated throughput and Poisson-arrival latency of nmf_server_*."""
+    import numpy as np
+    t_setup = time.perf_counter()
+    wb = synth.workload5_basis()
+    m, r = wb["V"].shape[0], wb["r"]
+    Vb = native.DeviceMatrix(torch.from_numpy(wb["V"]).cuda())
+    W = torch.from_numpy(wb["W0"]).cuda()
+    Ht = torch.from_numpy(wb["Ht0"]).cuda()
+    native.fit(Vb, r, native.reg(), native.opts(max_outer=10), W, Ht, want_trace=False)
+    del Vb, Ht
+    basis = native.Basis(W, l1=0.05, l2=0.0, opt=native.opts(max_inner=100, eps=1e-3))
+    # a pool of distinct requests, reused by the arrivals (each arrival has its own output)
+    n_pool = 96
+    sizes = synth.request_sizes(n_pool, seed, cmax=8192)
+    pool = [native.sparse_request(synth.foldin_columns_many(m, int(c), 500, seed + 1 + i), m)
+            for i, c in enumerate(sizes)]
+    fits = synth.workload5_fits(8)
+    fit_V = [torch.from_numpy(f["V"]).cuda() for f in fits]
+    g = synth.rng(seed + 999)
+    is_fit = g.random(n_req) < 0.05
+    pick = g.integers(0, n_pool, n_req)
+    fpick = g.integers(0, len(fits), n_req)
+    fit_opt = native.opts(max_outer=30)
+
+    def make_outputs():
+        outs = []
+        for i in range(n_req):
+            if is_fit[i]:
+                f = fits[fpick[i]]
+                outs.append((torch.from_numpy(f["W0"]).cuda(), torch.from_numpy(f["Ht0"]).cuda()))
+            else:
+                outs.append(torch.empty((int(sizes[pick[i]]), r), device="cuda"))
+        torch.cuda.synchronize()
+        return outs
+
+    def submit(S, i, outs):
+        if is_fit[i]:
+            f = fits[fpick[i]]
+            return S.submit_fit(fit_V[fpick[i]], f["r"], native.reg(), fit_opt, *outs[i])
+        return S.submit_foldin(pool[pick[i]], outs[i])
+
+    def run(arrivals):
+        outs = make_outputs()
+        S = native.Server(basis, hbm_budget=8 << 30, max_slots=4, max_batch_cols=16384)
+        tickets = []
+        t0 = time.perf_counter()
+        for i in range(n_req):
+            if arrivals is not None:
+                while time.perf_counter() - t0 < arrivals[i]:
+                    pass
+            tickets.append(submit(S, i, outs))
+        S.wait()
+        elapsed = time.perf_counter() - t0
+        lat = np.array([S.poll(t)[1] for t in tickets])
+        st = S.stats()
+        S.close()
+        return elapsed, lat, st
+
+    cols = int(sum(int(sizes[pick[i]]) for i in range(n_req) if not is_fit[i]))
+    log(f"[bench] serving set up in {time.perf_counter() - t_setup:.1f}s; {n_req} requests, "
+        f"{cols} fold-in columns, {int(is_fit.sum())} fits")
+    run(None)  # warm-up pass
+    el_sat, lat_sat, st_sat = run(None)
+    rate = load * n_req / el_sat
+    log(f"[bench] serving saturated {el_sat * 1e3:.1f} ms; Poisson arrivals at {rate:.0f} req/s")
+    arrivals = synth.poisson_arrivals(n_req, rate, seed + 7)
+    el, lat, st = run(arrivals)
+    fold = lat[~is_fit]
+    fitl = lat[is_fit]
+    basis.close()
+    return {
+        "workload": "resident basis W 100000x128 (10 outer iterations fitted on the device to "
+                    "Gamma(2,0.5)-factor data), L1=0.05, eps=1e-3; fold-in requests of "
+                    "c~logU[1,8192] columns at 0.5% density, values log(1+Poisson(3)); 5% small "
+                    "full fits (m,n~logU[64,2048], r~U{4..32}, 30 outer iterations); 4 slots",
+        "requests": n_req,
+        "fold_in_columns": cols,
+        "saturated_solves_per_s": cols / el_sat,
+        "saturated_ms": el_sat * 1e3,
+        "saturated_batches": st_sat["batches"],
+        "arrival_rate_req_per_s": rate,
+        "load": load,
+        "poisson_solves_per_s": cols / el,
+        "fold_in_p50_ms": float(np.percentile(fold, 50)),
+        "fold_in_p99_ms": float(np.percentile(fold, 99)),
+        "fit_p50_ms": float(np.percentile(fitl, 50)) if fitl.size else None,
+        "poisson_batches": st["batches"],
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -53,6 +153,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=8,
                     help="outer iterations of the CPU-oracle sample")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-load", type=float, default=0.5,
+                    help="Poisson arrival rate as a fraction of the saturated request rate")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 1 GiB device buffer (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -155,6 +259,10 @@ def main():
         "loss_after": st["loss"],
     }
 
+    plan.close()
+    if not args.no_serve:
+        out["serving"] = serving_leg(native, synth, torch, args.serve_requests, args.serve_load)
+
     if not args.no_cpu:
         import oracle
         cores = oracle.num_threads()
@@ -176,7 +284,6 @@ def main():
         }
         log(f"[bench] CPU oracle {tcpu:.1f}s")
     print(json.dumps(out), flush=True)
-    plan.close()
 
 
 if __name__ == "__main__":

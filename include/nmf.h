@@ -98,7 +98,11 @@ typedef struct {
  * NMF_FP32 or NMF_BF16 for the Gram and data products (the solve is always
  * float32).  objective_every: compute the loss every s outer iterations
  * (0 = only when a trace or stats are requested, at the end).  check_finite:
- * scan inputs for NaN/Inf (and V for negatives) before running. */
+ * scan inputs for NaN/Inf (and V for negatives) before running.  lanes:
+ * lanes of a wavefront that cooperate on one column in the solve kernel
+ * (1, 2, 4, 8 or 16; 0 = chosen from r and the launch's column count: few
+ * columns get wider groups).  It is a layout choice: results for different
+ * lanes agree to rounding, and are bitwise reproducible for a fixed choice. */
 typedef struct {
     int32_t max_outer;
     int32_t max_inner;
@@ -107,6 +111,7 @@ typedef struct {
     int32_t precision;
     int32_t objective_every;
     int32_t check_finite;
+    int32_t lanes;
 } nmf_opts;
 
 /* Statistics of a fit.  loss = 0.5||V - W H||^2, objective = J above (both
@@ -120,7 +125,7 @@ typedef struct {
 } nmf_stats;
 
 /* Fills *o with the defaults: max_outer 50, max_inner 100, eps 1e-3,
- * ls_guard 1, NMF_FP32, objective_every 0, check_finite 0. */
+ * ls_guard 1, NMF_FP32, objective_every 0, check_finite 0, lanes 0. */
 NMF_API void nmf_default_opts(nmf_opts *o);
 
 /* Message describing the calling thread's last non-OK status. */
@@ -137,6 +142,14 @@ NMF_API const char *nmf_last_error(void);
  * All device pointers; X must not alias gram or h. */
 NMF_API int nnls_solve_batch(int32_t r, int64_t ncols, const float *gram, const float *h, float *X,
                      const nmf_opts *opt, int32_t *iters, void *stream);
+
+/* The solve kernel's layout for rank r and a launch of ncols columns: *L
+ * lanes per column, *E coordinates per lane (E * L >= r, the padded rank).
+ * lanes as in nmf_opts.  Host-only; NMF_E_INVAL when lanes cannot hold r.
+ * nmf_fit uses (r, n, lanes) for its H-update and (r, m, lanes) for its
+ * W-update; nmf_fit_batched the total columns of all problems of a half-
+ * iteration; a fold-in basis (r, 8192, lanes). */
+NMF_API int nnls_layout(int32_t r, int64_t ncols, int32_t lanes, int32_t *E, int32_t *L);
 
 /* ---------------------------------------------------------------- building blocks
  * One step of a half-iteration each (Algorithm 2; Section 4.2 costs them at
@@ -265,10 +278,13 @@ NMF_API int nmf_server_create(const nmf_basis *B, size_t hbm_budget, int32_t max
                               int64_t max_batch_cols, nmf_server **out);
 /* Queues a request; NMF_E_BUSY iff its footprint exceeds the whole budget. */
 NMF_API int nmf_server_submit(nmf_server *s, const nmf_request *req, uint64_t *ticket);
-/* *done = 1 once finished; latency_ms (optional) = completion - submission.
- * Returns the request's status once done. */
+/* *done = 1 once finished; latency_ms (optional) = completion - submission
+ * (host clock; completion is when the request's stream has drained).
+ * Returns the request's status once done.  A request reported done by poll
+ * or by wait(ticket) is forgotten: its ticket is unknown afterwards. */
 NMF_API int nmf_server_poll(nmf_server *s, uint64_t ticket, int32_t *done, double *latency_ms);
-/* Blocks until the request (ticket 0: every request submitted so far) is done. */
+/* Blocks until the request (ticket 0: every request submitted so far; those
+ * records stay until polled) is done. */
 NMF_API int nmf_server_wait(nmf_server *s, uint64_t ticket, double *latency_ms);
 NMF_API int nmf_server_stats(nmf_server *s, int64_t *completed, int64_t *columns, int64_t *batches);
 /* Finishes the queued work, stops the workers and frees the server. */

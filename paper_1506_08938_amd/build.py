@@ -54,6 +54,12 @@ def _compile(src: str, incremental: bool) -> str:
 
 
 def build(incremental: bool = False, jobs: int | None = None) -> str:
+    sys.path.insert(0, PKG)
+    try:
+        import variants
+    finally:
+        sys.path.pop(0)
+    variants.generate()  # per-L solve instantiations and their table
     os.makedirs(BUILD, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
     jobs = jobs or min(len(srcs), max(1, min(16, os.cpu_count() or 4)))

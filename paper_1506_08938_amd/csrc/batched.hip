@@ -65,6 +65,8 @@ extern "C" int nmf_fit_batched(int32_t count, const nmf_problem *probs, const nm
         if (q.V.rows < 1 || q.V.cols < 1 || !q.V.dense || q.V.ld < q.V.cols)
             return fail(NMF_E_INVAL, "problem %d: bad dense V", p);
         if (q.r < 1 || q.r > NMF_MAX_RANK) return fail(NMF_E_INVAL, "problem %d: r out of range", p);
+        if (opt->lanes && !nqp_lanes_ok(q.r, opt->lanes))
+            return fail(NMF_E_INVAL, "problem %d: lanes = %d cannot hold rank %d", p, opt->lanes, q.r);
         if (!q.W || !q.Ht) return fail(NMF_E_INVAL, "problem %d: W and Ht must be non-NULL", p);
         const float rg[4] = {q.reg.l1_w, q.reg.l2_w, q.reg.l1_h, q.reg.l2_h};
         for (float v : rg)
@@ -101,7 +103,16 @@ extern "C" int nmf_fit_batched(int32_t count, const nmf_problem *probs, const nm
     HalfLists hl[2];  // 0: H-update (A = W, data V'), 1: W-update (A = Ht, data V)
     char *base = nullptr;  // set after allocation; lists hold offsets until then
     auto dptr = [&](size_t o) { return (void *)(base + o); };
-    NMF_HIP(hipMalloc((void **)&base, data_bytes + 256));
+    {
+        const hipError_t e0 = hipMalloc((void **)&base, data_bytes + 256);
+        if (e0 != hipSuccess)
+            return fail(NMF_E_DEVICE, "batched buffers (%zu bytes): %s", data_bytes + 256, hipGetErrorString(e0));
+    }
+    int64_t ctot[2] = {0, 0};  // columns solved per half-iteration, all problems
+    for (int p = 0; p < count; p++) {
+        ctot[0] += probs[p].V.cols;
+        ctot[1] += probs[p].V.rows;
+    }
     for (int h = 0; h < 2; h++) {
         for (int p = 0; p < count; p++) {
             const nmf_problem &q = probs[p];
@@ -128,8 +139,9 @@ extern "C" int nmf_fit_batched(int32_t count, const nmf_problem *probs, const nm
                           r, H ? q.reg.l1_h : q.reg.l1_w, (unsigned long long *)dptr(slot[p].inner),
                           nullptr, 0};
             hl[h].solve.push_back(sv);
-            const NqpVariant v = nqp_pick(r);
-            const int chunk = 4 * (64 / v.L) * 4;  // four trips of every lane group of a block
+            // the layout is chosen for the whole launch's column count
+            const NqpVariant v = nqp_pick(r, ctot[h], opt->lanes);
+            const int chunk = bnqp_chunk_cols(v.L);
             auto &lst = hl[h].chunks[{v.E, v.L}];
             for (int64_t c0 = 0; c0 < C; c0 += chunk)
                 lst.push_back({p, (int32_t)c0, (int32_t)std::min<int64_t>(C, c0 + chunk)});
@@ -257,6 +269,8 @@ hipError_t launch_bnqp(const NqpVariant &v, const BSolveChunk *chunks, int nchun
     case 1: return launch_bnqp_l1(v.E, chunks, nchunks, queue, probs, max_inner, eps, ls_guard, s);
     case 2: return launch_bnqp_l2(v.E, chunks, nchunks, queue, probs, max_inner, eps, ls_guard, s);
     case 4: return launch_bnqp_l4(v.E, chunks, nchunks, queue, probs, max_inner, eps, ls_guard, s);
+    case 8: return launch_bnqp_l8(v.E, chunks, nchunks, queue, probs, max_inner, eps, ls_guard, s);
+    case 16: return launch_bnqp_l16(v.E, chunks, nchunks, queue, probs, max_inner, eps, ls_guard, s);
     default: return hipErrorInvalidValue;
     }
 }

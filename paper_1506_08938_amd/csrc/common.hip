@@ -50,6 +50,7 @@ extern "C" void nmf_default_opts(nmf_opts *o) {
     o->precision = NMF_FP32;
     o->objective_every = 0;
     o->check_finite = 0;
+    o->lanes = 0;
 }
 
 namespace nmfi {

@@ -191,8 +191,7 @@ struct nmf_plan {
     int r = 0;
     nmf_reg reg{};
     nmf_opts opt{};
-    NqpVariant var{};
-    int R = 0;
+    NqpVariant var_h{}, var_w{};  // solve layouts of the H-update (n columns) and W-update (m)
     // CSR
     int32_t *t_rowptr = nullptr, *t_colidx = nullptr;
     float *t_vals = nullptr;
@@ -256,8 +255,12 @@ extern "C" int nmf_plan_create(const nmf_matrix *V, int32_t r, const nmf_reg *re
     }
     nmf_plan *p = new nmf_plan();
     p->V = *V; p->m = V->rows; p->n = V->cols; p->r = r; p->reg = *reg; p->opt = *opt;
-    p->var = nqp_pick(r);
-    p->R = p->var.E * p->var.L;
+    p->var_h = nqp_pick(r, p->n, opt->lanes);
+    p->var_w = nqp_pick(r, p->m, opt->lanes);
+    if (!p->var_h.E || !p->var_w.E) {
+        delete p;
+        return fail(NMF_E_INVAL, "lanes = %d cannot hold rank %d", opt->lanes, r);
+    }
     int st = NMF_OK;
     if (V->kind == NMF_CSR) {
         if (!V->t_rowptr) {
@@ -430,7 +433,7 @@ static hipError_t half_update(nmf_plan *p, bool h_update, const float *A, float 
     q.max_inner = p->opt.max_inner; q.eps = p->opt.eps; q.ls_guard = p->opt.ls_guard ? 1 : 0;
     q.cold = 0; q.iters = nullptr; q.counter = p->counter; q.inner_total = p->inner_total;
     PhaseMark pm(p, NMF_PHASE_SOLVE, s);
-    return launch_nqp(p->var, q, s);
+    return launch_nqp(h_update ? p->var_h : p->var_w, q, s);
 }
 
 static int objective_now(nmf_plan *p, const float *W, const float *Ht, double out[2], hipStream_t s) {
@@ -530,6 +533,9 @@ extern "C" int nmf_objective(const nmf_matrix *V, int32_t r, const nmf_reg *reg,
 }
 
 // ============================================================ fold-in
+// Column count the fold-in solve layout is chosen for.
+constexpr int64_t kFoldinLayoutCols = 8192;
+
 extern "C" int nmf_basis_create(const float *W, int64_t m, int32_t r, float l1, float l2,
                                 const nmf_opts *opt, nmf_basis **out, void *stream) {
     if (!out) return fail(NMF_E_INVAL, "out is NULL");
@@ -541,10 +547,14 @@ extern "C" int nmf_basis_create(const float *W, int64_t m, int32_t r, float l1, 
         return fail(NMF_E_INVAL, "l1 and l2 must be finite and >= 0");
     if (int st = validate_opts(opt)) return st;
     hipStream_t s = (hipStream_t)stream;
+    // One solve layout for every fold-in of this basis (so a column's result
+    // never depends on the request or batch it arrives in), chosen for
+    // batches of a few thousand columns unless opt->lanes forces it.
+    const NqpVariant var = nqp_pick(r, kFoldinLayoutCols, opt->lanes);
+    if (!var.E) return fail(NMF_E_INVAL, "lanes = %d cannot hold rank %d", opt->lanes, r);
     nmf_basis *b = new nmf_basis();
     b->m = m; b->r = r; b->l1 = l1; b->l2 = l2; b->opt = *opt;
-    b->var = nqp_pick(r);
-    b->R = b->var.E * b->var.L;
+    b->var = var;
     const size_t oG = 0, oS = al256((size_t)r * r * 4), total = oS + al256(gram_scratch_bytes(r, m));
     hipError_t e = hipMalloc((void **)&b->W, (size_t)m * r * sizeof(float));
     if (e == hipSuccess) e = hipMalloc((void **)&b->ws, total);

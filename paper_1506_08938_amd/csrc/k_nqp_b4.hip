@@ -1,4 +1,5 @@
-// Batched solve-kernel instantiations with 4 lane(s) per column (see nqp_kernel.h).
+// Batched solve-kernel instantiations with 4 lane(s) per column
+// (nqp_kernel.h).  Written by variants.py.
 #include "nqp_kernel.h"
 
 namespace nmfi {
@@ -7,6 +8,13 @@ hipError_t launch_bnqp_l4(int E, const BSolveChunk *chunks, int nchunks, unsigne
                           const BSolveProb *probs, int max_inner, double eps, int ls_guard,
                           hipStream_t s) {
     switch (E) {
+    case 1: return launch_bnqp_t<1, 4>(chunks, nchunks, queue, probs, max_inner, eps, ls_guard, s);
+    case 2: return launch_bnqp_t<2, 4>(chunks, nchunks, queue, probs, max_inner, eps, ls_guard, s);
+    case 4: return launch_bnqp_t<4, 4>(chunks, nchunks, queue, probs, max_inner, eps, ls_guard, s);
+    case 6: return launch_bnqp_t<6, 4>(chunks, nchunks, queue, probs, max_inner, eps, ls_guard, s);
+    case 8: return launch_bnqp_t<8, 4>(chunks, nchunks, queue, probs, max_inner, eps, ls_guard, s);
+    case 12: return launch_bnqp_t<12, 4>(chunks, nchunks, queue, probs, max_inner, eps, ls_guard, s);
+    case 16: return launch_bnqp_t<16, 4>(chunks, nchunks, queue, probs, max_inner, eps, ls_guard, s);
     case 18: return launch_bnqp_t<18, 4>(chunks, nchunks, queue, probs, max_inner, eps, ls_guard, s);
     case 20: return launch_bnqp_t<20, 4>(chunks, nchunks, queue, probs, max_inner, eps, ls_guard, s);
     case 22: return launch_bnqp_t<22, 4>(chunks, nchunks, queue, probs, max_inner, eps, ls_guard, s);

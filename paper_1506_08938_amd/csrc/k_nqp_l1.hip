@@ -1,4 +1,5 @@
-// Solve-kernel instantiations with 1 lane(s) per column (see nqp_kernel.h).
+// Solve-kernel instantiations with 1 lane(s) per column (nqp_kernel.h).
+// Written by variants.py.
 #include "nqp_kernel.h"
 
 namespace nmfi {

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "nmf.h"
+#include "nqp_variants.h"
 
 namespace nmfi {
 
@@ -39,18 +40,19 @@ struct NqpParams {
     unsigned long long *inner_total;   // optional accumulator of iterations
 };
 
-// Kernel variant (entries per lane E, lanes per column L) for rank r.
+// Kernel variant (entries per lane E, lanes per column L).
 struct NqpVariant {
     int E, L;
 };
-NqpVariant nqp_pick(int r);
-int nqp_padded(int r);
+// Lanes per column for rank r and a launch of ncols columns: `lanes` > 0
+// forces L (E = 0 when L cannot hold r); 0 picks the throughput layout for r
+// and widens it while the launch would leave the chip short of lanes.
+NqpVariant nqp_pick(int r, int64_t ncols, int lanes);
+// Lanes-per-column values a launch can use for rank r (nonzero E).
+bool nqp_lanes_ok(int r, int lanes);
 
 // Launches the persistent solve kernel for the given variant.
 hipError_t launch_nqp(const NqpVariant &v, const NqpParams &p, hipStream_t s);
-hipError_t launch_nqp_l1(int E, const NqpParams &p, hipStream_t s);
-hipError_t launch_nqp_l2(int E, const NqpParams &p, hipStream_t s);
-hipError_t launch_nqp_l4(int E, const NqpParams &p, hipStream_t s);
 
 // ------------------------------------------------------------------ products
 constexpr int SPMM_CHUNK = 512;  // stored entries per SpMM work item
@@ -140,15 +142,9 @@ hipError_t launch_bdense(const BItem *items, int64_t nitems, const BProdProb *pr
 hipError_t launch_bnqp(const NqpVariant &v, const BSolveChunk *chunks, int nchunks,
                        unsigned int *queue, const BSolveProb *probs, int max_inner, double eps,
                        int ls_guard, hipStream_t s);
-hipError_t launch_bnqp_l1(int E, const BSolveChunk *chunks, int nchunks, unsigned int *queue,
-                          const BSolveProb *probs, int max_inner, double eps, int ls_guard,
-                          hipStream_t s);
-hipError_t launch_bnqp_l2(int E, const BSolveChunk *chunks, int nchunks, unsigned int *queue,
-                          const BSolveProb *probs, int max_inner, double eps, int ls_guard,
-                          hipStream_t s);
-hipError_t launch_bnqp_l4(int E, const BSolveChunk *chunks, int nchunks, unsigned int *queue,
-                          const BSolveProb *probs, int max_inner, double eps, int ls_guard,
-                          hipStream_t s);
+// columns per chunk of a batched solve launch: four trips of every lane
+// group of a block
+inline int bnqp_chunk_cols(int L) { return 4 * (64 / L) * 4; }
 hipError_t launch_zero_u32(unsigned int *p, int n, hipStream_t s);
 
 // ------------------------------------------------------------------ objective
@@ -167,7 +163,6 @@ struct nmf_basis {
     float l1 = 0.f, l2 = 0.f;
     nmf_opts opt{};
     nmfi::NqpVariant var{};
-    int R = 0;
     char *ws = nullptr;  // G, Gram scratch
     float *G = nullptr;
 };

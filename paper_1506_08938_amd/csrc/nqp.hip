@@ -6,26 +6,40 @@
 
 namespace nmfi {
 
-// Kernel variant per rank: one lane per column up to r = 32, two up to 64,
-// four up to 128; E is the smallest instantiated size that covers r.
-static const int kE1[] = {1, 2, 4, 6, 8, 12, 16, 20, 24, 28, 32};
-static const int kE2[] = {20, 24, 28, 32};
-static const int kE4[] = {18, 20, 22, 24, 25, 26, 28, 30, 32};
-
-NqpVariant nqp_pick(int r) {
-    if (r <= 32) {
-        for (int e : kE1) if (e >= r) return {e, 1};
-    } else if (r <= 64) {
-        for (int e : kE2) if (2 * e >= r) return {e, 2};
-    } else {
-        for (int e : kE4) if (4 * e >= r) return {e, 4};
-    }
-    return {0, 0};
+// E for L lanes per column: the smallest compiled E with E * L >= r, else 0.
+static int pick_e(int L, int r) {
+    int n = 0;
+    const int *t = nqp_e_table(L, &n);
+    for (int i = 0; i < n; i++)
+        if (t[i] * L >= r) return t[i];
+    return 0;
 }
 
-int nqp_padded(int r) {
-    NqpVariant v = nqp_pick(r);
-    return v.E * v.L;
+bool nqp_lanes_ok(int r, int lanes) { return pick_e(lanes, r) != 0; }
+
+// Lanes a launch should keep busy before widening stops paying: two waves on
+// each SIMD of a 256-CU chip.  A fixed constant (not the device's CU count),
+// so that the choice, and with it the rounding of every result, is the same
+// on every device.
+constexpr int64_t kLaneTarget = 256LL * 4 * 64 * 2;
+
+NqpVariant nqp_pick(int r, int64_t ncols, int lanes) {
+    if (lanes > 0) {
+        const int e = pick_e(lanes, r);
+        return {e, e ? lanes : 0};
+    }
+    // throughput layout: one lane per column up to r = 32, two up to 64, four
+    // up to 128 (E <= 32 registers-worth of coordinates per lane)
+    int L = r <= 32 ? 1 : (r <= 64 ? 2 : 4);
+    // few columns: widen the lane groups (shorter per-column critical path)
+    // while the launch stays under the lane target, each lane keeps more than
+    // one real coordinate and the padded rank grows by at most a quarter
+    while (L < 16 && ncols * L < kLaneTarget && (r + L - 1) / L > 1) {
+        const int e2 = pick_e(2 * L, r);
+        if (!e2 || 4 * (e2 * 2 * L) > 5 * (pick_e(L, r) * L)) break;
+        L *= 2;
+    }
+    return {pick_e(L, r), L};
 }
 
 hipError_t launch_nqp(const NqpVariant &v, const NqpParams &p, hipStream_t s) {
@@ -33,6 +47,8 @@ hipError_t launch_nqp(const NqpVariant &v, const NqpParams &p, hipStream_t s) {
     case 1: return launch_nqp_l1(v.E, p, s);
     case 2: return launch_nqp_l2(v.E, p, s);
     case 4: return launch_nqp_l4(v.E, p, s);
+    case 8: return launch_nqp_l8(v.E, p, s);
+    case 16: return launch_nqp_l16(v.E, p, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -44,12 +60,27 @@ int validate_opts(const nmf_opts *o) {
         return fail(NMF_E_INVAL, "eps must be finite and >= 0");
     if (o->precision != NMF_FP32 && o->precision != NMF_BF16)
         return fail(NMF_E_INVAL, "precision must be NMF_FP32 or NMF_BF16");
+    if (o->lanes != 0 && o->lanes != 1 && o->lanes != 2 && o->lanes != 4 && o->lanes != 8 && o->lanes != 16)
+        return fail(NMF_E_INVAL, "lanes must be 0, 1, 2, 4, 8 or 16 (got %d)", o->lanes);
     return NMF_OK;
 }
 
 }  // namespace nmfi
 
 using namespace nmfi;
+
+extern "C" int nnls_layout(int32_t r, int64_t ncols, int32_t lanes, int32_t *E, int32_t *L) {
+    if (!E || !L) return fail(NMF_E_INVAL, "E and L must be non-NULL");
+    if (r < 1 || r > NMF_MAX_RANK) return fail(NMF_E_INVAL, "r must be in [1, %d] (got %d)", NMF_MAX_RANK, r);
+    if (ncols < 0) return fail(NMF_E_INVAL, "ncols must be >= 0");
+    if (lanes != 0 && lanes != 1 && lanes != 2 && lanes != 4 && lanes != 8 && lanes != 16)
+        return fail(NMF_E_INVAL, "lanes must be 0, 1, 2, 4, 8 or 16 (got %d)", lanes);
+    const NqpVariant v = nqp_pick(r, ncols, lanes);
+    if (!v.E) return fail(NMF_E_INVAL, "lanes = %d cannot hold rank %d", lanes, r);
+    *E = v.E;
+    *L = v.L;
+    return NMF_OK;
+}
 
 extern "C" int nnls_solve_batch(int32_t r, int64_t ncols, const float *gram, const float *h,
                                 float *X, const nmf_opts *opt, int32_t *iters, void *stream) {
@@ -66,7 +97,8 @@ extern "C" int nnls_solve_batch(int32_t r, int64_t ncols, const float *gram, con
         if (!st) st = check_values(X, ncols * r, 1, s);
         if (st) return st;
     }
-    const NqpVariant v = nqp_pick(r);
+    const NqpVariant v = nqp_pick(r, ncols, opt->lanes);
+    if (!v.E) return fail(NMF_E_INVAL, "lanes = %d cannot hold rank %d", opt->lanes, r);
     unsigned long long *counter = nullptr;
     NMF_HIP(hipMallocAsync((void **)&counter, 256, s));
     hipError_t e = launch_zero_u64(counter, 1, s);

@@ -1,9 +1,9 @@
 // Algorithm 3 (Fast Combinational Algorithm for NQP, Section 3.4) as a
 // persistent gfx950 kernel.
 //
-// Mapping.  L lanes (1, 2 or 4, always inside one DPP quad) cooperate on one
-// column; lane `sub` of the group owns the E contiguous coordinates
-// [sub*E, sub*E + E) of the padded rank R = E*L.  The rescaled Hessian Q
+// Mapping.  L lanes (1, 2, 4, 8 or 16: a DPP quad, half-row or row)
+// cooperate on one column; lane `sub` of the group owns the E contiguous
+// coordinates [sub*E, sub*E + E) of the padded rank R = E*L.  The rescaled Hessian Q
 // (unit diagonal) sits in LDS, row-major with stride SQ; because Q is
 // symmetric, both the matrix-vector products and the coordinate-descent
 // gradient update read one row segment per lane: Q[j][sub*E .. sub*E+E).
@@ -54,6 +54,13 @@ __device__ __forceinline__ double dppd(double v) {
 // quad_perm selectors: xor 1 = [1,0,3,2], xor 2 = [2,3,0,1]
 constexpr int DPP_XOR1 = 1 | (0 << 2) | (3 << 4) | (2 << 6);
 constexpr int DPP_XOR2 = 2 | (3 << 2) | (0 << 4) | (1 << 6);
+// lane i of each 8-lane half-row reads lane 7 - i; of each 16-lane row, 15 - i.
+// Once every quad (half-row) agrees on a value these pair it with the other
+// quad (half-row) of the group, so each stage is a butterfly step.
+constexpr int DPP_HALF_MIRROR = 0x141;
+constexpr int DPP_MIRROR = 0x140;
+// lane S of each 16-lane row, broadcast to the row
+constexpr int DPP_ROW_BCAST0 = 0x150;
 
 // broadcast the value of group member S to every lane of its group
 template <int L, int S>
@@ -62,8 +69,16 @@ __device__ __forceinline__ float grp_bcast(float v) {
         return v;
     } else if constexpr (L == 2) {
         return dppf<S | (S << 2) | ((2 + S) << 4) | ((2 + S) << 6)>(v);
-    } else {
+    } else if constexpr (L == 4) {
         return dppf<S * 0x55>(v);
+    } else if constexpr (L == 8) {
+        // member S of the lower and of the upper half-row; keep the own half's
+        const float lo = dppf<DPP_ROW_BCAST0 + S>(v);
+        const float hi = dppf<DPP_ROW_BCAST0 + 8 + S>(v);
+        return (threadIdx.x & 8) ? hi : lo;
+    } else {
+        static_assert(L == 16, "lanes per column: 1, 2, 4, 8 or 16");
+        return dppf<DPP_ROW_BCAST0 + S>(v);
     }
 }
 
@@ -71,12 +86,16 @@ template <int L>
 __device__ __forceinline__ float grp_sum(float v) {
     if constexpr (L >= 2) v += dppf<DPP_XOR1>(v);
     if constexpr (L >= 4) v += dppf<DPP_XOR2>(v);
+    if constexpr (L >= 8) v += dppf<DPP_HALF_MIRROR>(v);
+    if constexpr (L >= 16) v += dppf<DPP_MIRROR>(v);
     return v;
 }
 template <int L>
 __device__ __forceinline__ double grp_sum_d(double v) {
     if constexpr (L >= 2) v += dppd<DPP_XOR1>(v);
     if constexpr (L >= 4) v += dppd<DPP_XOR2>(v);
+    if constexpr (L >= 8) v += dppd<DPP_HALF_MIRROR>(v);
+    if constexpr (L >= 16) v += dppd<DPP_MIRROR>(v);
     return v;
 }
 
@@ -95,6 +114,8 @@ template <int L>
 __device__ __forceinline__ void grp_argmax(float &best, int &idx, float &m) {
     if constexpr (L >= 2) argmax_step<DPP_XOR1>(best, idx, m);
     if constexpr (L >= 4) argmax_step<DPP_XOR2>(best, idx, m);
+    if constexpr (L >= 8) argmax_step<DPP_HALF_MIRROR>(best, idx, m);
+    if constexpr (L >= 16) argmax_step<DPP_MIRROR>(best, idx, m);
 }
 
 // out[e] = sum_j Q[sub*E + e][j] v_j for this lane's E rows; v is spread over
@@ -147,9 +168,26 @@ __device__ __forceinline__ float relu(float a) {
 #define NMF_NQP_ONEHOT_LDS 0  // 0: compare/select (measured faster); 1: y update through the LDS unit vector
 #endif
 
-template <int E>
+template <int R>
+constexpr int nqp_stride() {
+    return ((R + 3) & ~3) + 4;
+}
+
+// LDS of one block: Q (R x SQ), sqrt-diagonal (R), unit-vector window (2R),
+// and a few counters
+template <int R>
+constexpr int nqp_lds_bytes() {
+    return (R * nqp_stride<R>() + 3 * R) * 4 + 64;
+}
+
+// Waves per SIMD: the register table, capped by how many blocks the 160 KB
+// of LDS of a CU holds (each block puts one wave on each of the 4 SIMDs).
+// Asking for more than LDS allows makes the compiler drop the register cap.
+template <int E, int L>
 constexpr int nqp_waves_per_eu() {
-    return NMF_NQP_WPE ? NMF_NQP_WPE : (E <= 12 ? 6 : (E <= 20 ? 4 : (E <= 28 ? 3 : 2)));
+    constexpr int by_regs = NMF_NQP_WPE ? NMF_NQP_WPE : (E <= 12 ? 6 : (E <= 20 ? 4 : (E <= 28 ? 3 : 2)));
+    constexpr int by_lds = (160 * 1024) / nqp_lds_bytes<E * L>();
+    return by_regs < by_lds ? by_regs : (by_lds > 0 ? by_lds : 1);
 }
 
 // Where one solve's columns come from and go to.
@@ -373,11 +411,6 @@ __device__ __forceinline__ void nqp_columns(const float *__restrict__ sQ,
     }
 }
 
-template <int R>
-constexpr int nqp_stride() {
-    return ((R + 3) & ~3) + 4;
-}
-
 // Anti-lopsided rescale (Algorithm 3, "Re-scaling variables") while staging
 // into LDS: sD[i] = sqrt(Gamma_ii) (0 when Gamma_ii <= 0, a frozen coordinate,
 // and for the pads r <= i < R); sQ[i][j] = Gamma_ij / (sD[i] sD[j]) with a
@@ -410,7 +443,7 @@ __device__ __forceinline__ void flush_inner(unsigned long long v, unsigned long 
 
 template <int E, int L>
 __global__ __launch_bounds__(NQP_BLOCK)
-__attribute__((amdgpu_waves_per_eu(nqp_waves_per_eu<E>(), 8))) void k_nqp(const NqpParams a) {
+__attribute__((amdgpu_waves_per_eu(nqp_waves_per_eu<E, L>(), 8))) void k_nqp(const NqpParams a) {
     constexpr int R = E * L;
     constexpr int SQ = nqp_stride<R>();
     __shared__ float sQ[R * SQ];
@@ -432,7 +465,7 @@ __attribute__((amdgpu_waves_per_eu(nqp_waves_per_eu<E>(), 8))) void k_nqp(const 
 // All problems of one launch share the kernel variant (E, L).
 template <int E, int L>
 __global__ __launch_bounds__(NQP_BLOCK)
-__attribute__((amdgpu_waves_per_eu(nqp_waves_per_eu<E>(), 8))) void k_bnqp(
+__attribute__((amdgpu_waves_per_eu(nqp_waves_per_eu<E, L>(), 8))) void k_bnqp(
     const BSolveChunk *__restrict__ chunks, int nchunks, unsigned int *queue,
     const BSolveProb *__restrict__ probs, int max_inner, double eps, int ls_guard) {
     constexpr int R = E * L;

@@ -60,7 +60,7 @@ struct nmf_server {
     uint64_t next_ticket = 1;
     bool stop = false;
     std::vector<std::thread> workers;
-    int64_t batches = 0, completed = 0, columns = 0;
+    int64_t batches = 0, completed = 0, columns = 0, submitted = 0;
 };
 
 namespace {
@@ -83,7 +83,7 @@ int run_foldin_batch(nmf_server *S, std::vector<std::shared_ptr<Req>> &batch, hi
     }
     std::vector<BSolveProb> probs;
     std::vector<BSolveChunk> chunks;
-    const int chunk = 4 * (64 / B->var.L) * 4;
+    const int chunk = bnqp_chunk_cols(B->var.L);
     int64_t off = 0;
     for (size_t j = 0; j < batch.size(); j++) {
         const nmf_request &q = batch[j]->q;
@@ -240,6 +240,7 @@ extern "C" int nmf_server_submit(nmf_server *S, const nmf_request *q, uint64_t *
         R->t_submit = now_s();
         S->queue.push_back(R);
         S->reqs[R->ticket] = R;
+        S->submitted++;
         *ticket = R->ticket;
     }
     S->cv_work.notify_all();
@@ -254,14 +255,17 @@ extern "C" int nmf_server_poll(nmf_server *S, uint64_t ticket, int32_t *done, do
     const Req &R = *it->second;
     *done = R.state == 2;
     if (latency_ms) *latency_ms = R.state == 2 ? (R.t_done - R.t_submit) * 1e3 : NAN;
-    return R.state == 2 ? R.status : NMF_OK;
+    if (R.state != 2) return NMF_OK;
+    const int st = R.status;
+    S->reqs.erase(it);  // reported done: the record is released
+    return st;
 }
 
 extern "C" int nmf_server_wait(nmf_server *S, uint64_t ticket, double *latency_ms) {
     if (!S) return fail(NMF_E_INVAL, "server is NULL");
     std::unique_lock<std::mutex> lk(S->mu);
     if (ticket == 0) {  // every submitted request
-        S->cv_done.wait(lk, [&] { return S->completed == (int64_t)S->reqs.size(); });
+        S->cv_done.wait(lk, [&] { return S->completed == S->submitted; });
         return NMF_OK;
     }
     auto it = S->reqs.find(ticket);
@@ -269,6 +273,7 @@ extern "C" int nmf_server_wait(nmf_server *S, uint64_t ticket, double *latency_m
     auto R = it->second;
     S->cv_done.wait(lk, [&] { return R->state == 2; });
     if (latency_ms) *latency_ms = (R->t_done - R->t_submit) * 1e3;
+    S->reqs.erase(ticket);  // reported done: the record is released
     return R->status;
 }
 

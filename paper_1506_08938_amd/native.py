@@ -20,7 +20,8 @@ MAX_RANK = 128
 
 # every entry point include/nmf.h declares
 EXPORTS = [
-    "nmf_default_opts", "nmf_last_error", "nnls_solve_batch", "nmf_gram", "nmf_product",
+    "nmf_default_opts", "nmf_last_error", "nnls_solve_batch", "nnls_layout", "nmf_gram",
+    "nmf_product",
     "nmf_plan_create", "nmf_plan_run", "nmf_plan_destroy", "nmf_plan_profile", "nmf_plan_timers",
     "nmf_fit", "nmf_objective", "nmf_fit_batched",
     "nmf_server_create", "nmf_server_submit", "nmf_server_poll", "nmf_server_wait",
@@ -47,7 +48,7 @@ class NmfOpts(ctypes.Structure):
     _fields_ = [("max_outer", ctypes.c_int32), ("max_inner", ctypes.c_int32),
                 ("eps", ctypes.c_double), ("ls_guard", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("objective_every", ctypes.c_int32),
-                ("check_finite", ctypes.c_int32)]
+                ("check_finite", ctypes.c_int32), ("lanes", ctypes.c_int32)]
 
 
 class NmfStats(ctypes.Structure):
@@ -90,12 +91,20 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_1506_08938_amd.build` (hipcc, gfx950)")
+        # torch loads its own copy of the HIP runtime (by an unversioned
+        # name).  Importing it first lets this library's libamdhip64.so.7
+        # dependency resolve to that same copy: one runtime per process, so
+        # device pointers and streams are shared.  Loaded the other way round,
+        # the process would hold two runtimes and one of them sees no GPU.
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         L.nmf_last_error.restype = ctypes.c_char_p
         L.nmf_default_opts.argtypes = [ctypes.POINTER(NmfOpts)]
         L.nmf_default_opts.restype = None
         L.nnls_solve_batch.argtypes = [ctypes.c_int32, ctypes.c_int64, _vp, _vp, _vp,
                                        ctypes.POINTER(NmfOpts), _vp, _vp]
+        L.nnls_layout.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
+                                  ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
         L.nmf_gram.argtypes = [_vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_float, ctypes.c_int32,
                                _vp, _vp]
         L.nmf_product.argtypes = [ctypes.POINTER(NmfMatrix), ctypes.c_int32, ctypes.c_int32, _vp,
@@ -201,6 +210,13 @@ def nnls_solve_batch(gram, h, X, opt: NmfOpts | None = None, iters=None):
     check(lib().nnls_solve_batch(r, ncols, _ptr(gram), _ptr(h), _ptr(X), ctypes.byref(opt),
                                  _ptr(iters), stream_ptr()))
     return X
+
+
+def layout(r, ncols, lanes=0):
+    """nnls_layout: (E, L) of the solve kernel for rank r and ncols columns."""
+    E = ctypes.c_int32(); L = ctypes.c_int32()
+    check(lib().nnls_layout(int(r), int(ncols), int(lanes), ctypes.byref(E), ctypes.byref(L)))
+    return E.value, L.value
 
 
 class DeviceMatrix:
@@ -456,6 +472,8 @@ class Server:
     def poll(self, ticket):
         done = ctypes.c_int32(); lat = ctypes.c_double()
         check(lib().nmf_server_poll(self.h, ticket, ctypes.byref(done), ctypes.byref(lat)))
+        if done.value:
+            self.refs.pop(ticket, None)
         return bool(done.value), lat.value
 
     def wait(self, ticket=0):

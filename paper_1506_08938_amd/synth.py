@@ -25,9 +25,12 @@ Workloads (V is m x n; W m x r and Ht n x r are the factors):
   4 batched         many small dense problems, m ~ logU[64, 4096], n ~
                     logU[64, 2048], r ~ U{4..64}, V = W0 H0 + |N(0, 0.01)|,
                     W0, H0 ~ U[0,1] with inner dimension r.
-  5 serving         fold-in requests of c ~ logU[1, 8192] sparse columns over
-                    100000 rows, 500 distinct uniform rows per column, values
-                    as workload 3.
+  5 serving         a resident basis (100000 x 128) fitted to V = W0 H0 +
+                    |N(0, 0.05)| with Gamma(2, 0.5) factors; fold-in requests
+                    of c ~ logU[1, 8192] sparse columns over its 100000 rows,
+                    0.5% density (500 uniform rows per column, duplicates
+                    dropped), values as workload 3; 5% of the requests are
+                    small full fits (m, n ~ logU[64, 2048], r ~ U{4..32}).
 """
 from __future__ import annotations
 
@@ -194,6 +197,51 @@ def foldin_columns(m, c, per_col, seed):
     vals = log_poisson_values(c * per_col, seed + 13)
     indptr = np.arange(0, (c + 1) * per_col, per_col, dtype=np.int32)
     return sp.csr_matrix((vals, idx.reshape(-1), indptr), shape=(c, m))
+
+
+def foldin_columns_many(m, c, per_col, seed):
+    """Large requests quickly: per_col rows per column drawn uniformly with
+    replacement and de-duplicated (a column keeps per_col minus its few
+    collisions), values as workload 3.  CSR of the request's transpose."""
+    g = rng(seed)
+    idx = np.sort(g.integers(0, m, (c, per_col), dtype=np.int32), axis=1)
+    keep = np.ones((c, per_col), dtype=bool)
+    keep[:, 1:] = idx[:, 1:] != idx[:, :-1]
+    counts = keep.sum(axis=1)
+    indptr = np.zeros(c + 1, dtype=np.int32)
+    np.cumsum(counts, out=indptr[1:])
+    cols = idx[keep]
+    vals = log_poisson_values(cols.size, seed + 13)
+    return sp.csr_matrix((vals, cols, indptr), shape=(c, m))
+
+
+def workload5_basis(m=100000, nb=1024, r=128):
+    """Data and start point of the prior fit that yields the resident basis:
+    V (m x nb) = W0 H0 + |N(0, 0.05)|, Gamma(2, 0.5) factors of inner
+    dimension r."""
+    V = dense_lowrank(m, nb, r, DATA_SEED + 5, "gamma", 0.05)
+    W, Ht = start_point(m, nb, r, INIT_SEED + 5)
+    return dict(V=V, r=r, W0=W, Ht0=Ht)
+
+
+def workload5_fits(count, seed=DATA_SEED + 55):
+    """Small full-fit requests mixed into the serving stream: m, n ~
+    logU[64, 2048], r ~ U{4..32}, V = W0 H0 + |N(0, 0.01)|, U[0,1] factors."""
+    g = rng(seed)
+    ms = np.rint(np.exp(g.uniform(np.log(64), np.log(2048), count))).astype(int)
+    ns = np.rint(np.exp(g.uniform(np.log(64), np.log(2048), count))).astype(int)
+    rs = g.integers(4, 33, count)
+    out = []
+    for i in range(count):
+        V = dense_lowrank(int(ms[i]), int(ns[i]), int(rs[i]), seed * 10007 + i, "uniform", 0.01)
+        W, Ht = start_point(int(ms[i]), int(ns[i]), int(rs[i]), INIT_SEED + 55 + 7919 * (i + 1))
+        out.append(dict(V=V, r=int(rs[i]), W0=W, Ht0=Ht))
+    return out
+
+
+def poisson_arrivals(count, rate, seed):
+    """Arrival times (s) of a Poisson process of the given rate."""
+    return np.cumsum(rng(seed).exponential(1.0 / rate, count))
 
 
 def nqp_instance(r, ncols, seed, k=None, l1=0.0, l2=0.0, kind="random"):

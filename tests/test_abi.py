@@ -57,3 +57,44 @@ def test_null_pointers_are_rejected_and_empty_batch_is_a_noop():
     o = native.opts()
     assert L.nnls_solve_batch(10, 5, None, None, None, ctypes.byref(o), None, None) == native.NMF_E_INVAL
     assert L.nnls_solve_batch(10, 0, None, None, None, ctypes.byref(o), None, None) == native.NMF_OK
+
+
+def test_bad_lanes_option_is_rejected_on_host():
+    L = native.lib()
+    for lanes in [3, 32, -1]:
+        o = native.opts(lanes=lanes)
+        st = L.nnls_solve_batch(10, 10, None, None, None, ctypes.byref(o), None, None)
+        assert st == native.NMF_E_INVAL, lanes
+    # one lane per column holds at most rank 32, two at most 64
+    o = native.opts(lanes=1)
+    assert L.nnls_solve_batch(33, 10, None, None, None, ctypes.byref(o), None, None) == native.NMF_E_INVAL
+    with pytest.raises(native.NmfError):
+        native.layout(65, 100, lanes=2)
+
+
+@pytest.mark.parametrize("r", list(range(1, 129)))
+def test_layout_covers_every_rank(r):
+    # forced layouts: E * L covers r with the least padding the compiled table allows
+    for lanes, emax in [(1, 32), (2, 32), (4, 32), (8, 16), (16, 8)]:
+        if r > lanes * emax:
+            continue
+        E, L = native.layout(r, 1000, lanes)
+        assert L == lanes and E * L >= r
+        assert E * L - r < max(4 * L, 0.25 * r + L), (r, lanes, E)
+    # automatic: the throughput layout for many columns ...
+    E, L = native.layout(r, 10 ** 6)
+    assert L == (1 if r <= 32 else 2 if r <= 64 else 4) and E * L >= r
+    # ... and groups at least as wide for few columns, never padding a lane
+    # group beyond one coordinate per lane
+    E2, L2 = native.layout(r, 100)
+    assert L2 >= L and E2 * L2 >= r
+    assert L2 == L or -(-r // (L2 // 2)) > 1
+
+
+def test_layout_widens_monotonically_as_columns_shrink():
+    for r in [5, 13, 40, 100, 128]:
+        prev = 0
+        for ncols in [10 ** 6, 10 ** 5, 30000, 10000, 3000, 1000, 100, 1]:
+            E, L = native.layout(r, ncols)
+            assert L >= prev
+            prev = L

@@ -71,12 +71,18 @@ def test_converged_matches_oracle(r):
     assert np.quantile(e, 0.99) < 1e-4 and e.max() < 2e-4
 
 
+def throughput_lanes(r):
+    return 1 if r <= 32 else (2 if r <= 64 else 4)
+
+
 @pytest.mark.parametrize("r", [2, 10, 32, 64, 100, 128])
 @pytest.mark.parametrize("K", [1, 3])
-def test_fixed_iterations_match_oracle(r, K):
+@pytest.mark.parametrize("layout", ["auto", "throughput"])
+def test_fixed_iterations_match_oracle(r, K, layout):
     ncols = 1024 + 5
     G, h, x0 = make_batch(r, ncols, seed=1000 + r, l1=0.05)
-    Xg, itg = gpu_solve(G, h, x0, max_inner=K, eps=0.0)
+    lanes = 0 if layout == "auto" else throughput_lanes(r)
+    Xg, itg = gpu_solve(G, h, x0, max_inner=K, eps=0.0, lanes=lanes)
     Xo, ito = oracle.nqp_batch(G, h, x0, max_inner=K, eps=0.0)
     assert (itg <= K).all() and (np.mean(itg == K) > 0.9 or r <= 2)
     e = rel_err_rows(Xg, Xo)
@@ -89,6 +95,34 @@ def test_fixed_iterations_match_oracle(r, K):
     # a float32 near-tie can flip one greedy choice; the objective barely moves
     assert np.median(e) < 2e-4
     assert np.quantile(fr, 0.99) < 2e-5 and fr.max() < 5e-4
+
+
+# every compiled lanes-per-column layout against the oracle (converged mode)
+EMAX = {1: 32, 2: 32, 4: 32, 8: 16, 16: 8}
+LANE_CASES = [(r, L) for r in [1, 3, 8, 13, 24, 32, 40, 48, 64, 77, 100, 128]
+              for L in (1, 2, 4, 8, 16) if r <= L * EMAX[L]]
+_oracle_cache = {}
+
+
+@pytest.mark.parametrize("r,lanes", LANE_CASES)
+def test_every_layout_matches_oracle(r, lanes):
+    from paper_1506_08938_amd import native
+    ncols = 700 + r  # several lane groups and a ragged tail
+    G, h, x0 = make_batch(r, ncols, seed=500 + r, l1=0.02, l2=0.01 * (r % 2))
+    K = 200
+    if r not in _oracle_cache:
+        _oracle_cache[r] = oracle.nqp_batch(G, h, x0, max_inner=K, eps=0.0)
+    Xo, _ = _oracle_cache[r]
+    Xg, itg = gpu_solve(G, h, x0, max_inner=K, eps=0.0, lanes=lanes)
+    E, L = native.layout(r, ncols, lanes)
+    assert L == lanes and ((itg >= 1) & (itg <= K)).all() and (Xg >= 0).all()
+    e = rel_err_rows(Xg, Xo)
+    fg, fo = fvals(G, h, Xg), fvals(G, h, Xo)
+    fr = np.abs(fg - fo) / np.maximum(np.abs(fo), 1e-30)
+    print(f"r={r} E={E} L={L}: x rel p99 {np.quantile(e, .99):.2e} max {e.max():.2e}; "
+          f"f rel max {fr.max():.2e}")
+    assert fr.max() < 1e-9
+    assert np.quantile(e, 0.99) < 1e-4 and e.max() < 2e-4
 
 
 @pytest.mark.parametrize("r", [8, 100])
@@ -166,3 +200,25 @@ def test_nonfinite_input_rejected_when_checking():
     with pytest.raises(native.NmfError) as ei:
         native.nnls_solve_batch(Gd, hd, Xd, native.opts(check_finite=1))
     assert ei.value.status == native.NMF_E_NONFINITE
+
+
+def test_library_loaded_before_torch_shares_its_runtime():
+    # A process that touches the library before torch must still end up with
+    # a single HIP runtime (the binding imports torch before loading it).
+    import subprocess
+    import sys
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = (
+        "from paper_1506_08938_amd import native\n"
+        "o = native.opts(max_inner=20)\n"
+        "import torch\n"
+        "G = torch.eye(3, device='cuda'); h = -torch.ones(5, 3, device='cuda')\n"
+        "X = torch.zeros(5, 3, device='cuda')\n"
+        "native.nnls_solve_batch(G, h, X, o); torch.cuda.synchronize()\n"
+        "assert torch.allclose(X.cpu(), torch.ones(5, 3)), X\n"
+        "print('shared runtime ok')\n")
+    res = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True,
+                         timeout=180)
+    assert res.returncode == 0, res.stderr[-2000:]
+    assert "shared runtime ok" in res.stdout
