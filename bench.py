@@ -54,6 +54,35 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def kernel_source_hash(L):
+    """SHA-256 of the sources that define the solve kernel with L lanes per
+    column (its template, its instantiation file and the build flags)."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in ["paper_1506_08938_amd/csrc/nqp_kernel.h", f"paper_1506_08938_amd/csrc/k_nqp_l{L}.hip",
+                "paper_1506_08938_amd/build.py"]:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, L):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when there is none or the kernel's sources changed since."""
+    path = os.path.join(ROOT, "profiles", "k_nqp_sparse_r100_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].split(": ", 1)
+                fields[k.strip()] = v.strip().strip("`")
+    if fields.get("kernel") != kernel or fields.get("source_sha256") != kernel_source_hash(L):
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def serving_leg(native, synth, torch, n_req, load, seed=5005):
     """Saturated throughput and Poisson-arrival latency of nmf_server_*."""
     import numpy as np
@@ -215,6 +244,10 @@ def main():
     K = args.steps
     log(f"[bench] timed {K} steps in {elapsed:.3f}s")
 
+    E_h, L_h = native.layout(r, n)
+    E_w, L_w = native.layout(r, m)
+    kernel = f"k_nqp<{E_h}, {L_h}>" + ("" if (E_h, L_h) == (E_w, L_w) else f" / k_nqp<{E_w}, {L_w}>")
+    traffic = measured_traffic(kernel, L_h) if (E_h, L_h) == (E_w, L_w) else None
     solves = (m + n) * K
     value = solves / elapsed
     solve_ms, solve_calls = timers["solve"]
@@ -245,12 +278,12 @@ def main():
         },
         "roofline": {
             "bound": "alu",
-            "kernel": "k_nqp (Algorithm 3 solve)",
+            "kernel": kernel + " (Algorithm 3 solve)",
             "achieved": achieved,
             "peak": PEAK_LANE_OPS,
             "unit": "lane-ops/s",
             "frac": achieved / PEAK_LANE_OPS,
-            "traffic": None,
+            "traffic": traffic,
             "avg_launch_ms": solve_ms / solve_calls,
             "ops_per_launch": ops / solve_calls,
         },

@@ -14,7 +14,9 @@ hipError_t launch_bnqp_l8(int E, const BSolveChunk *chunks, int nchunks, unsigne
     case 4: return launch_bnqp_t<4, 8>(chunks, nchunks, queue, probs, max_inner, eps, ls_guard, s);
     case 6: return launch_bnqp_t<6, 8>(chunks, nchunks, queue, probs, max_inner, eps, ls_guard, s);
     case 8: return launch_bnqp_t<8, 8>(chunks, nchunks, queue, probs, max_inner, eps, ls_guard, s);
+    case 10: return launch_bnqp_t<10, 8>(chunks, nchunks, queue, probs, max_inner, eps, ls_guard, s);
     case 12: return launch_bnqp_t<12, 8>(chunks, nchunks, queue, probs, max_inner, eps, ls_guard, s);
+    case 13: return launch_bnqp_t<13, 8>(chunks, nchunks, queue, probs, max_inner, eps, ls_guard, s);
     case 16: return launch_bnqp_t<16, 8>(chunks, nchunks, queue, probs, max_inner, eps, ls_guard, s);
     default: return hipErrorInvalidValue;
     }

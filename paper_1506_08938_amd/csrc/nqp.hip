@@ -3,6 +3,7 @@
 #include <math.h>
 
 #include "nmf_internal.h"
+#include "nqp_tuned.h"
 
 namespace nmfi {
 
@@ -17,28 +18,25 @@ static int pick_e(int L, int r) {
 
 bool nqp_lanes_ok(int r, int lanes) { return pick_e(lanes, r) != 0; }
 
-// Lanes a launch should keep busy before widening stops paying: two waves on
-// each SIMD of a 256-CU chip.  A fixed constant (not the device's CU count),
-// so that the choice, and with it the rounding of every result, is the same
-// on every device.
-constexpr int64_t kLaneTarget = 256LL * 4 * 64 * 2;
-
 NqpVariant nqp_pick(int r, int64_t ncols, int lanes) {
     if (lanes > 0) {
         const int e = pick_e(lanes, r);
         return {e, e ? lanes : 0};
     }
-    // throughput layout: one lane per column up to r = 32, two up to 64, four
-    // up to 128 (E <= 32 registers-worth of coordinates per lane)
-    int L = r <= 32 ? 1 : (r <= 64 ? 2 : 4);
-    // few columns: widen the lane groups (shorter per-column critical path)
-    // while the launch stays under the lane target, each lane keeps more than
-    // one real coordinate and the padded rank grows by at most a quarter
-    while (L < 16 && ncols * L < kLaneTarget && (r + L - 1) / L > 1) {
-        const int e2 = pick_e(2 * L, r);
-        if (!e2 || 4 * (e2 * 2 * L) > 5 * (pick_e(L, r) * L)) break;
-        L *= 2;
-    }
+    // the autotuned table: the grid rank at or above r, the grid launch size
+    // at or below ncols.  A fixed function of (r, ncols), so the layout, and
+    // with it the rounding of every result, never depends on timing.
+    constexpr int nr = (int)(sizeof kTunedRanks / sizeof(int));
+    constexpr int nc = (int)(sizeof kTunedCols / sizeof(long long));
+    int ri = 0;
+    while (ri < nr - 1 && kTunedRanks[ri] < r) ri++;
+    int ci = 0;
+    while (ci < nc - 1 && kTunedCols[ci + 1] <= ncols) ci++;
+    int L = kTunedLanes[ri][ci];
+    // no more lanes than coordinates (the grid rank can be above r) ...
+    while (L > 1 && L / 2 >= r) L /= 2;
+    // ... and a layout that holds r
+    while (L < 16 && !pick_e(L, r)) L *= 2;
     return {pick_e(L, r), L};
 }
 

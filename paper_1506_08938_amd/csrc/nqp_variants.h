@@ -13,8 +13,8 @@ struct BSolveProb;
 constexpr int kNqpE1[] = {1, 2, 4, 6, 8, 12, 16, 20, 24, 28, 32};
 constexpr int kNqpE2[] = {2, 4, 6, 8, 12, 16, 20, 24, 28, 32};
 constexpr int kNqpE4[] = {1, 2, 4, 6, 8, 12, 16, 18, 20, 22, 24, 25, 26, 28, 30, 32};
-constexpr int kNqpE8[] = {1, 2, 3, 4, 6, 8, 12, 16};
-constexpr int kNqpE16[] = {1, 2, 3, 4, 6, 8};
+constexpr int kNqpE8[] = {1, 2, 3, 4, 6, 8, 10, 12, 13, 16};
+constexpr int kNqpE16[] = {1, 2, 3, 4, 5, 6, 7, 8};
 
 // E values compiled for L lanes per column (nullptr if none); *n = count.
 inline const int *nqp_e_table(int L, int *n) {

@@ -16,8 +16,8 @@ VARIANTS = {
     1: [1, 2, 4, 6, 8, 12, 16, 20, 24, 28, 32],
     2: [2, 4, 6, 8, 12, 16, 20, 24, 28, 32],
     4: [1, 2, 4, 6, 8, 12, 16, 18, 20, 22, 24, 25, 26, 28, 30, 32],
-    8: [1, 2, 3, 4, 6, 8, 12, 16],
-    16: [1, 2, 3, 4, 6, 8],
+    8: [1, 2, 3, 4, 6, 8, 10, 12, 13, 16],
+    16: [1, 2, 3, 4, 5, 6, 7, 8],
 }
 
 _SOLO = """// Solve-kernel instantiations with {L} lane(s) per column (nqp_kernel.h).

@@ -72,6 +72,15 @@ def test_bad_lanes_option_is_rejected_on_host():
         native.layout(65, 100, lanes=2)
 
 
+def tuned_table():
+    src = open(os.path.join(ROOT, "paper_1506_08938_amd", "csrc", "nqp_tuned.h")).read()
+    ranks = [int(x) for x in re.search(r"kTunedRanks\[\] = \{([^}]*)\}", src).group(1).split(",")]
+    cols = [int(x) for x in re.search(r"kTunedCols\[\] = \{([^}]*)\}", src).group(1).split(",")]
+    body = re.search(r"kTunedLanes\[\d+\]\[\d+\] = \{(.*?)\};", src, re.S).group(1)
+    rows = [[int(x) for x in row.split(",")] for row in re.findall(r"\{([^}]*)\}", body)]
+    return ranks, cols, rows
+
+
 @pytest.mark.parametrize("r", list(range(1, 129)))
 def test_layout_covers_every_rank(r):
     # forced layouts: E * L covers r with the least padding the compiled table allows
@@ -81,20 +90,26 @@ def test_layout_covers_every_rank(r):
         E, L = native.layout(r, 1000, lanes)
         assert L == lanes and E * L >= r
         assert E * L - r < max(4 * L, 0.25 * r + L), (r, lanes, E)
-    # automatic: the throughput layout for many columns ...
-    E, L = native.layout(r, 10 ** 6)
-    assert L == (1 if r <= 32 else 2 if r <= 64 else 4) and E * L >= r
-    # ... and groups at least as wide for few columns, never padding a lane
-    # group beyond one coordinate per lane
-    E2, L2 = native.layout(r, 100)
-    assert L2 >= L and E2 * L2 >= r
-    assert L2 == L or -(-r // (L2 // 2)) > 1
+    # automatic: a valid layout, never more lanes than coordinates
+    for ncols in [0, 1, 300, 5000, 70000, 10 ** 6]:
+        E, L = native.layout(r, ncols)
+        assert L in (1, 2, 4, 8, 16) and E * L >= r
+        assert L == 1 or L // 2 < r
 
 
-def test_layout_widens_monotonically_as_columns_shrink():
-    for r in [5, 13, 40, 100, 128]:
-        prev = 0
-        for ncols in [10 ** 6, 10 ** 5, 30000, 10000, 3000, 1000, 100, 1]:
-            E, L = native.layout(r, ncols)
-            assert L >= prev
-            prev = L
+def test_automatic_layout_follows_the_tuned_table():
+    ranks, cols, rows = tuned_table()
+    assert len(rows) == len(ranks) and all(len(x) == len(cols) for x in rows)
+    def capped(L, r):  # never more lanes than coordinates
+        while L > 1 and L // 2 >= r:
+            L //= 2
+        return L
+
+    for i, r in enumerate(ranks):
+        for j, c in enumerate(cols):
+            E, L = native.layout(r, c)
+            assert L == capped(rows[i][j], r), (r, c)
+            # a launch size between two grid points takes the lower one's layout
+            assert native.layout(r, c + 1) == (E, L)
+            if j:
+                assert native.layout(r, c - 1)[1] == capped(rows[i][j - 1], r)
