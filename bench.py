@@ -83,9 +83,12 @@ def measured_traffic(kernel, L):
     return float(fields["traffic_bytes_per_launch"])
 
 
-def serving_leg(native, synth, torch, n_req, load, seed=5005):
-    """Saturated throughput and Poisson-arrival latency of nmf_server_*."""
+def serving_leg(native, synth, torch, n_req, loads=(0.5,), seed=5005, n_warm=None):
+    """Saturated throughput and Poisson-arrival latency of nmf_server_* at each offered load
+    (a fraction of the saturated request rate)."""
     import numpy as np
+    loads = tuple(loads) if isinstance(loads, (tuple, list)) else (loads,)
+    n_warm = n_req // 10 if n_warm is None else n_warm
     t_setup = time.perf_counter()
     wb = synth.workload5_basis()
     m, r = wb["V"].shape[0], wb["r"]
@@ -102,76 +105,288 @@ def serving_leg(native, synth, torch, n_req, load, seed=5005):
             for i, c in enumerate(sizes)]
     fits = synth.workload5_fits(8)
     fit_V = [torch.from_numpy(f["V"]).cuda() for f in fits]
+    total = n_warm + n_req
     g = synth.rng(seed + 999)
-    is_fit = g.random(n_req) < 0.05
-    pick = g.integers(0, n_pool, n_req)
-    fpick = g.integers(0, len(fits), n_req)
+    is_fit = g.random(total) < 0.05
+    pick = g.integers(0, n_pool, total)
+    fpick = g.integers(0, len(fits), total)
+    csize = np.array([0 if is_fit[i] else int(sizes[pick[i]]) for i in range(total)])
     fit_opt = native.opts(max_outer=30)
+    outs = [None] * total
+    for i in range(total):
+        if not is_fit[i]:
+            outs[i] = torch.empty((int(csize[i]), r), device="cuda")
 
-    def make_outputs():
-        outs = []
-        for i in range(n_req):
+    def reset_fits():
+        for i in range(total):
             if is_fit[i]:
                 f = fits[fpick[i]]
-                outs.append((torch.from_numpy(f["W0"]).cuda(), torch.from_numpy(f["Ht0"]).cuda()))
-            else:
-                outs.append(torch.empty((int(sizes[pick[i]]), r), device="cuda"))
+                outs[i] = (torch.from_numpy(f["W0"]).cuda(), torch.from_numpy(f["Ht0"]).cuda())
         torch.cuda.synchronize()
-        return outs
 
-    def submit(S, i, outs):
+    def submit(S, i):
         if is_fit[i]:
             f = fits[fpick[i]]
             return S.submit_fit(fit_V[fpick[i]], f["r"], native.reg(), fit_opt, *outs[i])
         return S.submit_foldin(pool[pick[i]], outs[i])
 
     def run(arrivals):
-        outs = make_outputs()
+        """All requests at once (arrivals None) or at the given times; returns the elapsed
+        time of the measured requests and their latencies."""
+        reset_fits()
         S = native.Server(basis, hbm_budget=8 << 30, max_slots=4, max_batch_cols=16384)
         tickets = []
         t0 = time.perf_counter()
-        for i in range(n_req):
+        t_first = None
+        for i in range(total):
             if arrivals is not None:
                 while time.perf_counter() - t0 < arrivals[i]:
                     pass
-            tickets.append(submit(S, i, outs))
+            if i == n_warm:
+                t_first = time.perf_counter()
+            tickets.append(submit(S, i))
         S.wait()
-        elapsed = time.perf_counter() - t0
+        t_end = time.perf_counter()
         lat = np.array([S.poll(t)[1] for t in tickets])
         st = S.stats()
         S.close()
-        return elapsed, lat, st
+        return t_end - t_first, lat[n_warm:], st
 
-    cols = int(sum(int(sizes[pick[i]]) for i in range(n_req) if not is_fit[i]))
-    log(f"[bench] serving set up in {time.perf_counter() - t_setup:.1f}s; {n_req} requests, "
-        f"{cols} fold-in columns, {int(is_fit.sum())} fits")
+    meas = slice(n_warm, total)
+    cols = int(csize[meas].sum())
+    fold = ~is_fit[meas]
+    log(f"[bench] serving set up in {time.perf_counter() - t_setup:.1f}s; {n_req} measured requests "
+        f"after {n_warm} warm-up, {cols} fold-in columns, {int(is_fit[meas].sum())} fits")
     run(None)  # warm-up pass
-    el_sat, lat_sat, st_sat = run(None)
-    rate = load * n_req / el_sat
-    log(f"[bench] serving saturated {el_sat * 1e3:.1f} ms; Poisson arrivals at {rate:.0f} req/s")
-    arrivals = synth.poisson_arrivals(n_req, rate, seed + 7)
-    el, lat, st = run(arrivals)
-    fold = lat[~is_fit]
-    fitl = lat[is_fit]
+    el_sat, _, st_sat = run(None)
+    rate_sat = n_req / el_sat
+    log(f"[bench] serving saturated {el_sat * 1e3:.1f} ms ({rate_sat:.0f} req/s)")
+    per_load = []
+    for k, ld in enumerate(loads):
+        rate = ld * rate_sat
+        arrivals = synth.poisson_arrivals(total, rate, seed + 7 + k)
+        el, lat, st = run(arrivals)
+        lf = lat[fold]
+        sz = csize[meas][fold]
+        edges = np.quantile(sz, np.linspace(0, 1, 11))
+        dec = []
+        for d in range(10):
+            sel = (sz >= edges[d]) & ((sz < edges[d + 1]) if d < 9 else (sz <= edges[d + 1]))
+            if sel.any():
+                dec.append({"cols": [int(sz[sel].min()), int(sz[sel].max())], "n": int(sel.sum()),
+                            "p50_ms": float(np.percentile(lf[sel], 50)),
+                            "p99_ms": float(np.percentile(lf[sel], 99))})
+        per_load.append({
+            "load": ld, "arrival_rate_req_per_s": rate, "solves_per_s": cols / el,
+            "requests_per_s": n_req / el,
+            "fold_in_p50_ms": float(np.percentile(lf, 50)), "fold_in_p99_ms": float(np.percentile(lf, 99)),
+            "fit_p50_ms": float(np.percentile(lat[~fold], 50)) if (~fold).any() else None,
+            "batches": st["batches"], "by_size_decile": dec})
+        log(f"[bench] load {ld}: {rate:.0f} req/s, fold-in p50 {per_load[-1]['fold_in_p50_ms']:.3f} ms "
+            f"p99 {per_load[-1]['fold_in_p99_ms']:.3f} ms")
     basis.close()
-    return {
+    res = {
         "workload": "resident basis W 100000x128 (10 outer iterations fitted on the device to "
                     "Gamma(2,0.5)-factor data), L1=0.05, eps=1e-3; fold-in requests of "
                     "c~logU[1,8192] columns at 0.5% density, values log(1+Poisson(3)); 5% small "
-                    "full fits (m,n~logU[64,2048], r~U{4..32}, 30 outer iterations); 4 slots",
-        "requests": n_req,
+                    "full fits (m,n~logU[64,2048], r~U{4..32}, 30 outer iterations); 4 slots, "
+                    "batches of up to 16384 columns",
+        "requests": n_req, "warmup_requests": n_warm,
         "fold_in_columns": cols,
         "saturated_solves_per_s": cols / el_sat,
+        "saturated_requests_per_s": rate_sat,
         "saturated_ms": el_sat * 1e3,
         "saturated_batches": st_sat["batches"],
-        "arrival_rate_req_per_s": rate,
-        "load": load,
-        "poisson_solves_per_s": cols / el,
-        "fold_in_p50_ms": float(np.percentile(fold, 50)),
-        "fold_in_p99_ms": float(np.percentile(fold, 99)),
-        "fit_p50_ms": float(np.percentile(fitl, 50)) if fitl.size else None,
-        "poisson_batches": st["batches"],
+        "loads": per_load,
     }
+    if len(per_load) == 1:  # the headline line's short form
+        res.update({k: per_load[0][k] for k in ("fold_in_p50_ms", "fold_in_p99_ms", "fit_p50_ms")})
+        res["load"] = per_load[0]["load"]
+    return res
+
+
+def base_line(metric, value, unit, K, W, ms, dtype, config, **extra):
+    out = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": K, "warmup": W,
+           "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": dtype, "data": "synthetic", "config": config}
+    out.update(extra)
+    return out
+
+
+def timed_plan(native, torch, Vd, r, reg, opt, W0, Ht0, K, warm):
+    """ms per outer iteration and per-phase ms of a plan on fresh copies of the start point."""
+    plan = native.Plan(Vd, r, reg, opt)
+    W = W0.clone(); Ht = Ht0.clone()
+    for _ in range(warm):
+        plan.run(W, Ht, 1)
+    plan.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st = plan.run(W, Ht, K, want_stats=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    tm = plan.timers()
+    plan.close()
+    return el * 1e3 / K, {k: v[0] / K for k, v in tm.items()}, {k: v for k, v in tm.items()}, st
+
+
+def bench_dense(args, native, synth, torch, np):
+    """Dense workload (V 20000x10000 = Gamma-factor low rank + |N(0, 0.05)|, r = 64, L2 = 0.01 on
+    both factors): FP32 against BF16 products, per outer iteration and at equal objective
+    accuracy on the 2000x1000 slice (J* = the FP64 oracle's J after 100 iterations)."""
+    K, Wm = args.steps, args.warmup
+    log("[bench] generating the dense workload")
+    wl = synth.workload2()
+    m, n = wl["V"].shape
+    r = wl["r"]
+    V = torch.from_numpy(wl["V"]).cuda()
+    Vd = native.DeviceMatrix(V)
+    reg = native.reg(*wl["reg"])
+    W0 = torch.from_numpy(wl["W0"]).cuda()
+    H0 = torch.from_numpy(wl["Ht0"]).cuda()
+    modes = {}
+    for prec, name in ((0, "fp32"), (1, "bf16")):
+        ms, ph, tm, st = timed_plan(native, torch, Vd, r, reg,
+                                    native.opts(max_inner=100, eps=1e-3, precision=prec), W0, H0, K, Wm)
+        vbytes = (4 if prec == 0 else 2) * m * n
+        # per product launch: V once, the fixed factor once, the output once
+        prod_bytes = vbytes + 4 * (m + n) * r // 2 + 4 * (m + n) * r // 2
+        prod_ms = tm["product"][0] / tm["product"][1]
+        gram_ms = tm["gram"][0] / tm["gram"][1]
+        modes[name] = {
+            "ms_per_step": ms, "solves_per_s": (m + n) / (ms / 1e3), "phases_ms_per_step": ph,
+            "product_avg_ms": prod_ms,
+            "product_hbm_GBps": prod_bytes / (prod_ms / 1e3) / 1e9,
+            "product_frac_of_8TBps": prod_bytes / (prod_ms / 1e3) / 8e12,
+            "product_tflops": 2.0 * m * n * r / (prod_ms / 1e3) / 1e12,
+            "gram_avg_ms": gram_ms,
+            "gram_GBps": 4.0 * (m + n) / 2 * r / (gram_ms / 1e3) / 1e9,
+            "kbar": st["kbar"], "loss_after": st["loss"],
+        }
+        log(f"[bench] dense {name}: {ms:.3f} ms/step, product {prod_ms:.3f} ms")
+    del Vd, V
+    # equal accuracy on the slice
+    import oracle
+    sl = synth.workload2_slice()
+    T_or = 100
+    log("[bench] oracle: 100 outer iterations on the 2000x1000 slice")
+    t0 = time.perf_counter()
+    o = oracle.nmf_fit(sl["V"], r, sl["reg"], sl["W0"], sl["Ht0"], T=T_or, max_inner=100, eps=1e-3,
+                       ls_guard=1, want_trace=True)
+    t_or = time.perf_counter() - t0
+    Jstar = float(o["jhalf"][-1])
+    Vs = native.DeviceMatrix(torch.from_numpy(sl["V"]).cuda())
+    regs = native.reg(*sl["reg"])
+    acc = {}
+    Tmax = 3 * T_or
+    for prec, name in ((0, "fp32"), (1, "bf16")):
+        plan = native.Plan(Vs, r, regs, native.opts(max_inner=100, eps=1e-3, precision=prec))
+        W = torch.from_numpy(sl["W0"]).cuda(); Ht = torch.from_numpy(sl["Ht0"]).cuda()
+        Js = []
+        for t in range(Tmax):
+            plan.run(W, Ht, 1)
+            Js.append(native.objective(Vs, r, regs, W, Ht)[1])
+        ms_slice, _, _, _ = timed_plan(native, torch, Vs, r, regs,
+                                       native.opts(max_inner=100, eps=1e-3, precision=prec),
+                                       torch.from_numpy(sl["W0"]).cuda(), torch.from_numpy(sl["Ht0"]).cuda(),
+                                       20, 2)
+        plan.close()
+        reach = {}
+        for d in (1e-2, 1e-3, 1e-4):
+            it = next((i + 1 for i, J in enumerate(Js) if J <= Jstar * (1 + d)), None)
+            reach[f"{d:g}"] = {"iterations": it, "ms": None if it is None else it * ms_slice}
+        acc[name] = {"J_at_100_over_Jstar": Js[T_or - 1] / Jstar, "J_floor_over_Jstar": min(Js) / Jstar,
+                     "ms_per_iteration": ms_slice, "reach": reach}
+        log(f"[bench] slice {name}: J(100)/J* = {Js[T_or - 1] / Jstar:.6f}")
+    fp, bf = modes["fp32"], modes["bf16"]
+    out = base_line(
+        "dense NMF column NNLS solves/s (FP32 and BF16 products) and time to equal objective accuracy",
+        bf["solves_per_s"], "column NNLS solves/s", K, Wm, bf["ms_per_step"], "bf16",
+        {"workload": "dense V 20000x10000 = W0 H0 + |N(0,0.05)|, W0, H0 ~ Gamma(2,0.5) of inner "
+                     "dimension 64; r=64, L2=0.01 on W and H; eps=1e-3, max_inner=100; one step = one "
+                     "outer iteration; value = the BF16-product mode", "m": m, "n": n, "r": r},
+        modes=modes,
+        equal_accuracy={"slice": "V[:2000, :1000] of the same data as its own problem",
+                        "Jstar": Jstar, "oracle_iterations": T_or, "oracle_s": t_or,
+                        "oracle_threads": oracle.num_threads(), "modes": acc},
+    )
+    print(json.dumps(out), flush=True)
+
+
+def bench_batched(args, native, synth, torch, np):
+    """1024 uneven dense problems, 30 outer iterations each: one nmf_fit_batched call (a
+    captured hipGraph of all iterations) against a loop of per-problem nmf_fit calls."""
+    count, T = 1024, 30
+    log("[bench] generating 1024 problems")
+    t0 = time.perf_counter()
+    probs = synth.workload4(count=count)
+    log(f"[bench] generated in {time.perf_counter() - t0:.1f}s")
+    dev = [dict(V=torch.from_numpy(p["V"]).cuda(), r=p["r"], W0=torch.from_numpy(p["W0"]).cuda(),
+                Ht0=torch.from_numpy(p["Ht0"]).cuda()) for p in probs]
+    torch.cuda.synchronize()
+    cols = sum(p["V"].shape[0] + p["V"].shape[1] for p in probs)
+    vbytes = sum(4 * p["V"].size for p in probs)
+    res = {}
+    for prec, name in ((1, "bf16"), (0, "fp32")):
+        opt = native.opts(max_outer=T, max_inner=100, eps=1e-3, precision=prec)
+        best = None
+        for rep in range(2):
+            batch = [dict(V=d["V"], r=d["r"], reg=native.reg(), W=d["W0"].clone(), Ht=d["Ht0"].clone())
+                     for d in dev]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            native.fit_batched(batch, opt, want_stats=False)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            best = el if best is None else min(best, el)
+        st = native.fit_batched([dict(V=d["V"], r=d["r"], reg=native.reg(), W=d["W0"].clone(),
+                                      Ht=d["Ht0"].clone()) for d in dev[:64]],
+                                native.opts(max_outer=T, precision=prec))
+        res[name] = {"batched_s": best, "solves_per_s": cols * T / best,
+                     "problems_per_s": count / best, "kbar_first64": float(np.mean([x["kbar"] for x in st]))}
+        log(f"[bench] batched {name}: {best:.3f}s")
+    # per-problem baseline: plain FP32 nmf_fit calls, one after another
+    opt = native.opts(max_outer=T, max_inner=100, eps=1e-3, precision=0)
+    for d in dev[:8]:  # warm the per-shape code paths
+        native.fit(native.DeviceMatrix(d["V"]), d["r"], native.reg(), native.opts(max_outer=1),
+                   d["W0"].clone(), d["Ht0"].clone(), want_trace=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    inner = 0
+    for d in dev:
+        _, st = native.fit(native.DeviceMatrix(d["V"]), d["r"], native.reg(), opt, d["W0"].clone(),
+                           d["Ht0"].clone(), want_trace=False)
+    torch.cuda.synchronize()
+    base = time.perf_counter() - t0
+    log(f"[bench] per-problem loop: {base:.3f}s")
+    # roofline of one batched outer iteration: V read twice (BF16 copy: 2 bytes per entry)
+    b = res["bf16"]
+    t_hbm = 2 * (vbytes // 2) / 8e12
+    out = base_line(
+        "batched uneven NMF: column NNLS solves/s in one graph-captured launch sequence vs per-problem fits",
+        b["solves_per_s"], "column NNLS solves/s", T, 0, b["batched_s"] * 1e3 / T, "bf16",
+        {"workload": "1024 dense problems, m~logU[64,4096], n~logU[64,2048], r~U{4..64}, V = W0 H0 + "
+                     "|N(0,0.01)| with U[0,1] factors, FP32 storage; 30 outer iterations each; one step = "
+                     "one outer iteration of all problems; value = BF16 products, batched",
+         "problems": count, "columns_per_iteration": cols, "V_bytes_fp32": vbytes},
+        modes=res,
+        per_problem_fp32_s=base,
+        speedup_bf16_batched_vs_per_problem_fp32=base / b["batched_s"],
+        speedup_fp32_batched_vs_per_problem_fp32=base / res["fp32"]["batched_s"],
+        hbm_floor_ms_per_step=t_hbm * 1e3,
+    )
+    print(json.dumps(out), flush=True)
+
+
+def bench_serving(args, native, synth, torch, np):
+    """The serving configuration at several offered loads."""
+    loads = (0.3, 0.6, 0.9)
+    res = serving_leg(native, synth, torch, args.serve_requests, loads, n_warm=1000)
+    out = base_line(
+        "fold-in serving: column NNLS solves/s and p50/p99 latency at offered loads",
+        res["saturated_solves_per_s"], "column NNLS solves/s", args.serve_requests, 0,
+        res["saturated_ms"], "f32", {"workload": res["workload"]}, serving=res)
+    print(json.dumps(out), flush=True)
 
 
 def main():
@@ -186,6 +401,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-load", type=float, default=0.5,
                     help="Poisson arrival rate as a fraction of the saturated request rate")
+    ap.add_argument("--workload", default="sparse", choices=["sparse", "dense", "batched", "serving"],
+                    help="sparse: the headline line (default); the others print supplementary lines")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 1 GiB device buffer (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -210,6 +427,12 @@ def main():
     from paper_1506_08938_amd import native, synth
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload == "dense":
+        return bench_dense(args, native, synth, torch, np)
+    if args.workload == "batched":
+        return bench_batched(args, native, synth, torch, np)
+    if args.workload == "serving":
+        return bench_serving(args, native, synth, torch, np)
     log("[bench] generating the sparse workload")
     t_gen = time.perf_counter()
     wl = synth.workload3()
@@ -294,7 +517,7 @@ def main():
 
     plan.close()
     if not args.no_serve:
-        out["serving"] = serving_leg(native, synth, torch, args.serve_requests, args.serve_load)
+        out["serving"] = serving_leg(native, synth, torch, args.serve_requests, (args.serve_load,))
 
     if not args.no_cpu:
         import oracle

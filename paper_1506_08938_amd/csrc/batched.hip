@@ -3,7 +3,8 @@
 //
 // Every phase of a half-iteration is one launch across all problems: the
 // Gram partials (work item = problem x 512 rows), the Gram finish (one block
-// per problem), the data product (work item = problem x 64 output rows), and
+// per problem), the data product (work item = problem x 128 output rows x k
+// slice; in BF16 mode preceded by the factor's BF16 copy), and
 // one persistent solve per kernel variant whose blocks take (problem, column
 // range) chunks from a queue.  All max_outer outer iterations are captured
 // into one hipGraph and launched once.  Problems only ever read their own
@@ -22,7 +23,7 @@ namespace {
 size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 struct HalfLists {
-    std::vector<BItem> gram_items, prod_items, red_items;
+    std::vector<BItem> gram_items, prod_items, red_items, f16_items;
     std::vector<BGramProb> gram;
     std::vector<BProdProb> prod;
     std::vector<BSolveProb> solve;
@@ -30,12 +31,12 @@ struct HalfLists {
 };
 
 struct DevHalf {
-    BItem *gram_items = nullptr, *prod_items = nullptr, *red_items = nullptr;
+    BItem *gram_items = nullptr, *prod_items = nullptr, *red_items = nullptr, *f16_items = nullptr;
     BGramProb *gram = nullptr;
     BProdProb *prod = nullptr;
     BSolveProb *solve = nullptr;
     std::vector<std::pair<NqpVariant, std::pair<BSolveChunk *, int>>> groups;
-    int64_t n_gram_items = 0, n_prod_items = 0, n_red_items = 0;
+    int64_t n_gram_items = 0, n_prod_items = 0, n_red_items = 0, n_f16_items = 0;
 };
 
 template <class T>
@@ -77,7 +78,7 @@ extern "C" int nmf_fit_batched(int32_t count, const nmf_problem *probs, const nm
 
     // ---------------------------------------------------------------- buffers
     struct Slot {
-        size_t G, part, P, V16, inner, kpart[2];
+        size_t G, part, P, V16, V16t, A16, inner, kpart[2];
     };
     std::vector<Slot> slot(count);
     size_t off = 0;
@@ -89,6 +90,8 @@ extern "C" int nmf_fit_batched(int32_t count, const nmf_problem *probs, const nm
         slot[p].part = place(std::max(bgram_partial_floats(q.r, m), bgram_partial_floats(q.r, n)) * 4);
         slot[p].P = place((size_t)std::max(m, n) * r * 4);
         slot[p].V16 = bf16 ? place((size_t)m * n * 2) : 0;
+        slot[p].V16t = bf16 ? place((size_t)m * n * 2) : 0;
+        slot[p].A16 = bf16 ? place((size_t)((r + 31) / 32 * 32) * ((std::max(m, n) + 63) / 64 * 64) * 2) : 0;
         slot[p].inner = place(8);
         for (int h = 0; h < 2; h++) {  // split-K partials of each half's product
             const int64_t C = h == 0 ? n : m, K = h == 0 ? m : n;
@@ -125,13 +128,18 @@ extern "C" int nmf_fit_batched(int32_t count, const nmf_problem *probs, const nm
                         (float *)dptr(slot[p].G), (int)((k + BGRAM_ROWS - 1) / BGRAM_ROWS)};
             hl[h].gram.push_back(g);
             for (int c = 0; c < g.nchunks; c++) hl[h].gram_items.push_back({p, c});
-            const void *V = bf16 ? dptr(slot[p].V16) : (const void *)q.V.dense;
+            // BF16 reads the copy along k: V16t (n x m) for the H-update, V16 for the W-update
+            const void *V = bf16 ? dptr(H ? slot[p].V16t : slot[p].V16) : (const void *)q.V.dense;
             const int64_t kc = dense_kchunk(C, k);
             const int ns = (int)((k + kc - 1) / kc);
-            BProdProb pr{V, bf16 ? n : q.V.ld, C, k, A, r, (float *)dptr(slot[p].P),
-                         ns > 1 ? (float *)dptr(slot[p].kpart[h]) : nullptr, kc, ns};
+            const int64_t lda16 = (std::max(m, n) + 63) / 64 * 64;
+            BProdProb pr{V, bf16 ? k : q.V.ld, C, k, A, r, (float *)dptr(slot[p].P),
+                         ns > 1 ? (float *)dptr(slot[p].kpart[h]) : nullptr, kc, ns,
+                         bf16 ? (__bf16 *)dptr(slot[p].A16) : nullptr, bf16 ? lda16 : 0};
             hl[h].prod.push_back(pr);
-            for (int64_t cb = 0; cb < (C + 63) / 64; cb++)
+            if (bf16)
+                for (int64_t kb = 0; kb < (k + 63) / 64; kb++) hl[h].f16_items.push_back({p, (int32_t)kb});
+            for (int64_t cb = 0; cb < (C + DENSE_BM - 1) / DENSE_BM; cb++)
                 for (int sl = 0; sl < ns; sl++) hl[h].prod_items.push_back({p, (int32_t)(cb * ns + sl)});
             if (ns > 1)
                 for (int64_t eb = 0; eb < (C * r + 4095) / 4096; eb++) hl[h].red_items.push_back({p, (int32_t)eb});
@@ -151,7 +159,7 @@ extern "C" int nmf_fit_batched(int32_t count, const nmf_problem *probs, const nm
     size_t list_bytes = 0;
     for (int h = 0; h < 2; h++) {
         list_bytes += al256(hl[h].gram_items.size() * sizeof(BItem) + 1) + al256(hl[h].prod_items.size() * sizeof(BItem) + 1);
-        list_bytes += al256(hl[h].red_items.size() * sizeof(BItem) + 1);
+        list_bytes += al256(hl[h].red_items.size() * sizeof(BItem) + 1) + al256(hl[h].f16_items.size() * sizeof(BItem) + 1);
         list_bytes += al256(hl[h].gram.size() * sizeof(BGramProb) + 1) + al256(hl[h].prod.size() * sizeof(BProdProb) + 1);
         list_bytes += al256(hl[h].solve.size() * sizeof(BSolveProb) + 1);
         for (auto &kv : hl[h].chunks) list_bytes += al256(kv.second.size() * sizeof(BSolveChunk) + 1);
@@ -168,12 +176,14 @@ extern "C" int nmf_fit_batched(int32_t count, const nmf_problem *probs, const nm
         st = upload(hl[h].gram_items, &dh[h].gram_items, cur, s);
         if (!st) st = upload(hl[h].prod_items, &dh[h].prod_items, cur, s);
         if (!st) st = upload(hl[h].red_items, &dh[h].red_items, cur, s);
+        if (!st) st = upload(hl[h].f16_items, &dh[h].f16_items, cur, s);
         if (!st) st = upload(hl[h].gram, &dh[h].gram, cur, s);
         if (!st) st = upload(hl[h].prod, &dh[h].prod, cur, s);
         if (!st) st = upload(hl[h].solve, &dh[h].solve, cur, s);
         dh[h].n_gram_items = (int64_t)hl[h].gram_items.size();
         dh[h].n_prod_items = (int64_t)hl[h].prod_items.size();
         dh[h].n_red_items = (int64_t)hl[h].red_items.size();
+        dh[h].n_f16_items = (int64_t)hl[h].f16_items.size();
         for (auto &kv : hl[h].chunks) {
             BSolveChunk *d = nullptr;
             if (!st) st = upload(kv.second, &d, cur, s);
@@ -186,6 +196,8 @@ extern "C" int nmf_fit_batched(int32_t count, const nmf_problem *probs, const nm
         const nmf_problem &q = probs[p];
         if (bf16) {
             e = launch_to_bf16(q.V.dense, q.V.rows, q.V.cols, q.V.ld, (__bf16 *)dptr(slot[p].V16), s);
+            if (e == hipSuccess)
+                e = launch_to_bf16_t(q.V.dense, q.V.rows, q.V.cols, q.V.ld, (__bf16 *)dptr(slot[p].V16t), s);
             if (e != hipSuccess) st = hip_fail(e, "BF16 copies");
         }
         if (!st) {
@@ -214,7 +226,8 @@ extern "C" int nmf_fit_batched(int32_t count, const nmf_problem *probs, const nm
                                      opt->precision, cs);
                 if (e == hipSuccess)
                     e = launch_bdense(dh[h].prod_items, dh[h].n_prod_items, dh[h].prod, ntmax, h == 0,
-                                      bf16, dh[h].red_items, dh[h].n_red_items, cs);
+                                      bf16, dh[h].red_items, dh[h].n_red_items, dh[h].f16_items,
+                                      dh[h].n_f16_items, cs);
                 for (size_t g = 0; g < dh[h].groups.size() && e == hipSuccess; g++)
                     e = launch_bnqp(dh[h].groups[g].first, dh[h].groups[g].second.first,
                                     dh[h].groups[g].second.second, queues + gi + (int)g,

@@ -138,16 +138,18 @@ extern "C" int nmf_product(const nmf_matrix *V, int32_t trans, int32_t r, const 
     if (V->kind == NMF_DENSE) {
         const void *src = V->dense;
         __bf16 *v16 = nullptr;
-        if (precision == NMF_BF16) {
+        if (precision == NMF_BF16) {  // the BF16 copy the product reads along k
             NMF_HIP(hipMallocAsync((void **)&v16, (size_t)m * n * sizeof(__bf16), s));
-            NMF_HIP(launch_to_bf16(V->dense, m, n, V->ld, v16, s));
+            if (trans) NMF_HIP(launch_to_bf16(V->dense, m, n, V->ld, v16, s));
+            else NMF_HIP(launch_to_bf16_t(V->dense, m, n, V->ld, v16, s));
             src = v16;
         }
         float *scratch = nullptr;
         NMF_HIP(hipMallocAsync((void **)&scratch, dense_scratch_bytes(m, n, r), s));
         hipError_t e = launch_dense_product(src, precision == NMF_BF16, m, n,
-                                            precision == NMF_BF16 ? n : V->ld, trans, A, r, P,
-                                            scratch, s);
+                                            precision == NMF_BF16 ? n : V->ld,
+                                            (precision == NMF_BF16 && !trans) ? v16 : nullptr, trans,
+                                            A, r, P, scratch, s);
         (void)hipFreeAsync(scratch, s);
         if (v16) (void)hipFreeAsync(v16, s);
         if (e != hipSuccess) return hip_fail(e, "nmf_product");
@@ -199,7 +201,7 @@ struct nmf_plan {
     SpmmPlan sp_h{}, sp_w{};
     float *sp_partial = nullptr;
     // dense
-    __bf16 *V16 = nullptr;
+    __bf16 *V16 = nullptr, *V16t = nullptr;  // BF16 copies of V and V'
     float *dense_scratch = nullptr;
     // workspace
     char *ws = nullptr;
@@ -224,6 +226,7 @@ static void plan_free(nmf_plan *p) {
     free_spmm_plan(&p->sp_w);
     if (p->sp_partial) (void)hipFree(p->sp_partial);
     if (p->V16) (void)hipFree(p->V16);
+    if (p->V16t) (void)hipFree(p->V16t);
     if (p->dense_scratch) (void)hipFree(p->dense_scratch);
     if (p->ws) (void)hipFree(p->ws);
     delete p;
@@ -284,7 +287,9 @@ extern "C" int nmf_plan_create(const nmf_matrix *V, int32_t r, const nmf_reg *re
     } else {
         if (opt->precision == NMF_BF16) {
             hipError_t e = hipMalloc((void **)&p->V16, (size_t)p->m * p->n * sizeof(__bf16));
+            if (e == hipSuccess) e = hipMalloc((void **)&p->V16t, (size_t)p->m * p->n * sizeof(__bf16));
             if (e == hipSuccess) e = launch_to_bf16(V->dense, p->m, p->n, V->ld, p->V16, s);
+            if (e == hipSuccess) e = launch_to_bf16_t(V->dense, p->m, p->n, V->ld, p->V16t, s);
             if (e != hipSuccess) st = hip_fail(e, "BF16 copy of V");
         }
         if (!st) {
@@ -342,7 +347,7 @@ size_t plan_footprint(const nmf_matrix *V, int r, const nmf_opts *opt) {
     b += al256(objective_scratch_bytes(V, r));
     if (V->kind == NMF_DENSE) {
         b += al256(dense_scratch_bytes(m, n, r));
-        if (opt->precision == NMF_BF16) b += al256((size_t)m * n * 2);
+        if (opt->precision == NMF_BF16) b += 2 * al256((size_t)m * n * 2);  // V16 and V16t
     } else {
         b += 3 * al256((size_t)(V->nnz + n + 1) * 4);  // CSR(V') when built here
         b += al256((size_t)(V->nnz / SPMM_CHUNK + m + n + 2) * (sizeof(SpChunk) + sizeof(SpSplit)));
@@ -422,7 +427,7 @@ static hipError_t half_update(nmf_plan *p, bool h_update, const float *A, float 
         } else {
             const bool bf = p->V16 != nullptr;
             e = launch_dense_product(bf ? (const void *)p->V16 : (const void *)p->V.dense, bf, p->m, p->n,
-                                     bf ? p->n : p->V.ld, h_update ? 0 : 1, A, p->r, p->P,
+                                     bf ? p->n : p->V.ld, p->V16t, h_update ? 0 : 1, A, p->r, p->P,
                                      p->dense_scratch, s);
         }
     }
@@ -625,7 +630,7 @@ extern "C" int nmf_foldin(const nmf_basis *B, const nmf_matrix *Vnew, float *Ht_
     float *P = (float *)(ws + 256);
     hipError_t e;
     if (Vnew->kind == NMF_DENSE)
-        e = launch_dense_product(Vnew->dense, 0, B->m, c, Vnew->ld, 0, B->W, r, P,
+        e = launch_dense_product(Vnew->dense, 0, B->m, c, Vnew->ld, nullptr, 0, B->W, r, P,
                                  (float *)(ws + 256 + pbytes), s);
     else
         e = launch_spmm_rows(Vnew->t_rowptr, c, Vnew->t_colidx, Vnew->t_vals, B->W, r, P, s);

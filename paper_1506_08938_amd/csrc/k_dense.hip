@@ -3,194 +3,304 @@
 // A = W) or X = V (trans = 1: the W-update, A = Ht).  V is m x n row-major
 // with leading dimension ld.
 //
-// Each block of four waves computes a 64 x R32 slab of P over one slice of
-// k (split-K), staging a 64 x 32 tile of X and a 32 x R32 tile of A in LDS
-// per step and accumulating 32x32 MFMA tiles (FP32 32x32x2, or BF16 32x32x16
-// with FP32 accumulation on the BF16 copies).  Split-K partials are summed in
-// slice order by a second kernel, so the result is deterministic.
+// Each block of four waves computes a 128 x R32 slab of P (R32 = r rounded
+// up to 32) over one slice of k (split-K).  Per stage it streams a 128 x BK
+// tile of X (16 KB: BK = 32 floats or 64 BF16 values) and a BK x R32 tile of
+// A with 16-byte loads into registers, one stage ahead of the MFMAs, and
+// stores them into the other of two LDS buffers (one barrier per stage).
+// Wave w owns rows [32w, 32w + 32) of the slab and accumulates NT 32x32
+// tiles: FP32 32x32x2 MFMAs on float operands, or BF16 32x32x16 MFMAs with
+// FP32 accumulation.  In BF16 mode X is always read along k (V for the
+// W-update, a transposed BF16 copy of V for the H-update) and A arrives as a
+// BF16 copy transposed to R32 x K, so every tile moves with 16-byte loads and
+// stores and no lane-by-lane transposition.
+// Split-K partials are summed in slice order by a second kernel, so the
+// result is deterministic; a P entry's arithmetic depends only on its
+// slice's k range, never on the block that computes it.
 #include "kernels_common.h"
 #include "nmf_internal.h"
 
 namespace nmfi {
 
-constexpr int DP_BC = 64;  // rows of P per block
-constexpr int DP_KT = 32;  // k per LDS stage
+typedef float f32x4a __attribute__((ext_vector_type(4)));
 
-// LDS a block needs for the FP32 product body
+template <bool BF16>
+struct DenseCfg;
+template <>
+struct DenseCfg<false> {
+    using T = float;
+    static constexpr int BK = 32;    // k per stage
+    static constexpr int VEC = 4;    // elements per 16-byte load
+};
+template <>
+struct DenseCfg<true> {
+    using T = __bf16;
+    static constexpr int BK = 64;
+    static constexpr int VEC = 8;
+};
+
+// LDS layout of one stage buffer.
+//   FP32: Xs[BK][BM + 4] (k-major: a lane's MFMA operand is one float and the
+//         32 lanes of a half-wave read 32 consecutive rows of P), As[BK][R32 + 4].
+//   BF16: Xs[BM][BK + 8], As[R32][BK + 8] (row-major in k: a lane's operand is
+//         eight consecutive k, one 16-byte read; the 144-byte pitch spreads
+//         the 32 rows of a half-wave over all banks).
+template <bool BF16, int NT>
+struct DenseLds {
+    static constexpr int BK = DenseCfg<BF16>::BK;
+    static constexpr int R32 = 32 * NT;
+    static constexpr int XP = BF16 ? BK + 8 : DENSE_BM + 4;    // pitch (elements)
+    static constexpr int AP = BF16 ? BK + 8 : R32 + 4;
+    static constexpr int X_ELEMS = BF16 ? DENSE_BM * XP : BK * XP;
+    static constexpr int A_ELEMS = BF16 ? R32 * AP : BK * AP;
+    static constexpr int ESZ = BF16 ? 2 : 4;
+    static constexpr int STAGE_BYTES = ((X_ELEMS + A_ELEMS) * ESZ + 15) & ~15;
+    static constexpr int BYTES = 2 * STAGE_BYTES;
+};
+
 template <int NT>
-constexpr int dense_fp32_lds_floats() {
-    return DP_BC * (DP_KT + 1) + DP_KT * NT * 32;
+constexpr int dense_lds_bytes(bool bf16) {
+    return bf16 ? DenseLds<true, NT>::BYTES : DenseLds<false, NT>::BYTES;
 }
 
-// 64 rows of P = X A starting at row c0, summed over k in [kb, ke), written
-// to o (C x r).  lds: dense_fp32_lds_floats<NT>() floats.
-template <int NT, bool XT>
-__device__ __forceinline__ void dense_fp32_body(const float *__restrict__ V, int64_t ld, int64_t C,
-                                                const float *__restrict__ A, int r, int64_t c0,
-                                                int64_t kb, int64_t ke, float *lds,
-                                                float *__restrict__ o) {
-    constexpr int R32 = NT * 32;
-    constexpr int NTILES = 2 * NT;
-    constexpr int TPW = (NTILES + 3) / 4;
-    float(*Xs)[DP_KT + 1] = (float(*)[DP_KT + 1])lds;
-    float(*As)[R32] = (float(*)[R32])(lds + DP_BC * (DP_KT + 1));
+// 128 rows of P = X A starting at row c0, summed over k in [kb, ke), written
+// to o (C x r).  lds: DenseLds<BF16, NT>::BYTES bytes, 16-byte aligned.
+// vec_ok: V's rows and base are 16-byte aligned (ld * sizeof(T) % 16 == 0).
+// A16 (BF16 mode): the factor as BF16, transposed, R32 x lda16 (row j holds
+// A[., j]); unused in FP32 mode, where A (k x r float32) is read directly.
+template <bool BF16, bool XT, int NT>
+__device__ __forceinline__ void dense_body(const void *__restrict__ Vv, int64_t ld, int64_t C,
+                                           const float *__restrict__ A, int r,
+                                           const __bf16 *__restrict__ A16, int64_t lda16,
+                                           int64_t c0, int64_t kb, int64_t ke, bool vec_ok,
+                                           char *lds, float *__restrict__ o) {
+    static_assert(!(BF16 && XT), "BF16 products read X along k");
+    using Cfg = DenseCfg<BF16>;
+    using T = typename Cfg::T;
+    using L = DenseLds<BF16, NT>;
+    constexpr int BK = Cfg::BK, VEC = Cfg::VEC, R32 = 32 * NT, BM = DENSE_BM;
+    // X tile: 1024 16-byte chunks, four per thread
+    constexpr int XCH = 4;
+    // A tile in 16-byte chunks: FP32 float4 along r (BK * R32 / 4 of them);
+    // BF16 eight k of one row j (R32 * BK / 8)
+    constexpr int ACH = BK * R32 / 4 / 256 / (BF16 ? 2 : 1);
+    static_assert(ACH >= 1, "A tile smaller than one chunk per thread");
+    const T *__restrict__ V = (const T *)Vv;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const bool a_vec = (r % 4) == 0 && ((uintptr_t)A % 16) == 0;
 
-    f32x16 acc[TPW];
+    typedef T tvec __attribute__((ext_vector_type(VEC)));
+    tvec xr[XCH];
+    f32x4a ar[BF16 ? 1 : ACH];
+    bf16x8 ar16[BF16 ? ACH : 1];
+
+    auto load_stage = [&](int64_t k0) {
 #pragma unroll
-    for (int q = 0; q < TPW; q++) acc[q] = f32x16{};
-
-    for (int64_t k0 = kb; k0 < ke; k0 += DP_KT) {
-        if constexpr (XT) {  // X[c][k] = V[k][c]: rows of V, 64 contiguous columns
-            for (int e = tid; e < DP_KT * DP_BC; e += 256) {
-                const int kk = e / DP_BC, c = e % DP_BC;
-                const int64_t gk = k0 + kk, gc = c0 + c;
-                Xs[c][kk] = (gk < ke && gc < C) ? V[gk * ld + gc] : 0.f;
+        for (int u = 0; u < XCH; u++) {
+            const int q = tid + 256 * u;
+            int64_t row, col;  // element (row, col) of V where the chunk starts
+            int64_t lim;       // elements of the chunk inside the tile's bounds
+            if constexpr (XT) {  // V rows are k, 128 contiguous c per row
+                constexpr int CPR = BM / VEC;  // chunks per row
+                const int kk = q / CPR, cc = (q % CPR) * VEC;
+                row = k0 + kk;
+                col = c0 + cc;
+                lim = (row < ke) ? min<int64_t>(VEC, C - col) : 0;
+            } else {  // V rows are c, BK contiguous k per row
+                constexpr int CPR = BK / VEC;
+                const int rr = q / CPR, kk = (q % CPR) * VEC;
+                row = c0 + rr;
+                col = k0 + kk;
+                lim = (row < C) ? min<int64_t>(VEC, ke - col) : 0;
             }
-        } else {  // X[c][k] = V[c][k]: rows of V, 32 contiguous columns
-            for (int e = tid; e < DP_KT * DP_BC; e += 256) {
-                const int c = e / DP_KT, kk = e % DP_KT;
-                const int64_t gk = k0 + kk, gc = c0 + c;
-                Xs[c][kk] = (gk < ke && gc < C) ? V[gc * ld + gk] : 0.f;
+            if (vec_ok && lim == VEC) {
+                xr[u] = *(const tvec *)(V + row * ld + col);
+            } else {
+#pragma unroll
+                for (int e = 0; e < VEC; e++) xr[u][e] = e < lim ? V[row * ld + col + e] : (T)0.f;
             }
         }
-        for (int e = tid; e < DP_KT * R32; e += 256) {
-            const int kk = e / R32, a = e % R32;
-            const int64_t gk = k0 + kk;
-            As[kk][a] = (gk < ke && a < r) ? A[gk * r + a] : 0.f;
-        }
-        __syncthreads();
 #pragma unroll
-        for (int q = 0; q < TPW; q++) {
-            const int tile = wave + 4 * q;
-            if (tile < NTILES) {
-                const int rt = tile / NT, ct = tile % NT;
+        for (int u = 0; u < ACH; u++) {
+            const int q = tid + 256 * u;
+            if constexpr (BF16) {  // row j of A16, eight k
+                constexpr int CPR = BK / 8;
+                const int j = q / CPR, kk = (q % CPR) * 8;
+                const int64_t gk = k0 + kk;
+                if (gk + 8 <= ke) {
+                    ar16[u] = *(const bf16x8 *)(A16 + j * lda16 + gk);
+                } else {
 #pragma unroll
-                for (int kp = 0; kp < DP_KT / 2; kp++) {
-                    const float a_op = Xs[32 * rt + (lane & 31)][2 * kp + (lane >> 5)];
-                    const float b_op = As[2 * kp + (lane >> 5)][32 * ct + (lane & 31)];
-                    acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a_op, b_op, acc[q], 0, 0, 0);
+                    for (int e = 0; e < 8; e++) ar16[u][e] = gk + e < ke ? A16[j * lda16 + gk + e] : (__bf16)0.f;
+                }
+            } else {
+                constexpr int CPR = R32 / 4;
+                const int kk = q / CPR, j = (q % CPR) * 4;
+                const int64_t gk = k0 + kk;
+                if (gk < ke && a_vec && j + 4 <= r) {
+                    ar[u] = *(const f32x4a *)(A + gk * r + j);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; e++) ar[u][e] = (gk < ke && j + e < r) ? A[gk * r + j + e] : 0.f;
                 }
             }
         }
-        __syncthreads();
-    }
+    };
+
+    auto store_stage = [&](char *buf) {
+        T *Xs = (T *)buf;
+        T *As = (T *)(buf + L::X_ELEMS * L::ESZ);
 #pragma unroll
-    for (int q = 0; q < TPW; q++) {
-        const int tile = wave + 4 * q;
-        if (tile < NTILES) {
-            const int rt = tile / NT, ct = tile % NT;
+        for (int u = 0; u < XCH; u++) {
+            const int q = tid + 256 * u;
+            if constexpr (XT) {  // FP32 only: Xs[k][c]
+                constexpr int CPR = BM / VEC;
+                const int kk = q / CPR, cc = (q % CPR) * VEC;
+                *(tvec *)(Xs + kk * L::XP + cc) = xr[u];
+            } else {
+                constexpr int CPR = BK / VEC;
+                const int rr = q / CPR, kk = (q % CPR) * VEC;
+                if constexpr (BF16) {  // Xs[c][k]
+                    *(tvec *)(Xs + rr * L::XP + kk) = xr[u];
+                } else {  // Xs[k][c]: transpose the four k of one c
 #pragma unroll
-            for (int v = 0; v < 16; v++) {
-                const int i = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3), j = lane & 31;
-                const int64_t c = c0 + 32 * rt + i;
-                const int a = 32 * ct + j;
-                if (c < C && a < r) o[c * r + a] = acc[q][v];
+                    for (int e = 0; e < VEC; e++) Xs[(kk + e) * L::XP + rr] = xr[u][e];
+                }
             }
         }
-    }
-}
-
-template <int NT, bool XT>
-__global__ __launch_bounds__(256) void k_dense_fp32(const float *__restrict__ V, int64_t ld,
-                                                    int64_t C, int64_t K,
-                                                    const float *__restrict__ A, int r,
-                                                    int64_t kchunk, float *__restrict__ out) {
-    __shared__ float lds[dense_fp32_lds_floats<NT>()];
-    const int64_t kb = (int64_t)blockIdx.y * kchunk;
-    dense_fp32_body<NT, XT>(V, ld, C, A, r, (int64_t)blockIdx.x * DP_BC, kb, min(K, kb + kchunk),
-                            lds, out + (int64_t)blockIdx.y * C * r);
-}
-
-// BF16 operands (V16: the BF16 copy of V; A converted while staging)
-template <int NT>
-constexpr int dense_bf16_lds_bytes() {
-    return (DP_BC + NT * 32) * (DP_KT + 8) * 2;
-}
-
-template <int NT, bool XT>
-__device__ __forceinline__ void dense_bf16_body(const __bf16 *__restrict__ V16, int64_t ld,
-                                                int64_t C, const float *__restrict__ A, int r,
-                                                int64_t c0, int64_t kb, int64_t ke, void *lds,
-                                                float *__restrict__ o) {
-    constexpr int R32 = NT * 32;
-    constexpr int NTILES = 2 * NT;
-    constexpr int TPW = (NTILES + 3) / 4;
-    // k-major staging so that a lane's eight consecutive k are contiguous
-    __bf16(*Xs)[DP_KT + 8] = (__bf16(*)[DP_KT + 8])lds;
-    __bf16(*As)[DP_KT + 8] = (__bf16(*)[DP_KT + 8])((char *)lds + DP_BC * (DP_KT + 8) * 2);
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-
-    f32x16 acc[TPW];
 #pragma unroll
-    for (int q = 0; q < TPW; q++) acc[q] = f32x16{};
-    const __bf16 zero = (__bf16)0.f;
+        for (int u = 0; u < ACH; u++) {
+            const int q = tid + 256 * u;
+            if constexpr (BF16) {  // As[j][k]
+                constexpr int CPR = BK / 8;
+                const int j = q / CPR, kk = (q % CPR) * 8;
+                *(bf16x8 *)(As + j * L::AP + kk) = ar16[u];
+            } else {  // As[k][j]
+                constexpr int CPR = R32 / 4;
+                const int kk = q / CPR, j = (q % CPR) * 4;
+                *(f32x4a *)(As + kk * L::AP + j) = ar[u];
+            }
+        }
+    };
 
-    for (int64_t k0 = kb; k0 < ke; k0 += DP_KT) {
-        if constexpr (XT) {
-            for (int e = tid; e < DP_KT * DP_BC; e += 256) {
-                const int kk = e / DP_BC, c = e % DP_BC;
-                const int64_t gk = k0 + kk, gc = c0 + c;
-                Xs[c][kk] = (gk < ke && gc < C) ? V16[gk * ld + gc] : zero;
+    f32x16 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; t++) acc[t] = f32x16{};
+
+    auto compute_stage = [&](const char *buf) {
+        const T *Xs = (const T *)buf;
+        const T *As = (const T *)(buf + L::X_ELEMS * L::ESZ);
+        if constexpr (BF16) {
+#pragma unroll
+            for (int ks = 0; ks < BK / 16; ks++) {
+                const int kq = 16 * ks + 8 * (lane >> 5);
+                const bf16x8 a_op = *(const bf16x8 *)(Xs + (32 * wave + (lane & 31)) * L::XP + kq);
+#pragma unroll
+                for (int t = 0; t < NT; t++) {
+                    const bf16x8 b_op = *(const bf16x8 *)(As + (32 * t + (lane & 31)) * L::AP + kq);
+                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_op, b_op, acc[t], 0, 0, 0);
+                }
             }
         } else {
-            for (int e = tid; e < DP_KT * DP_BC; e += 256) {
-                const int c = e / DP_KT, kk = e % DP_KT;
-                const int64_t gk = k0 + kk, gc = c0 + c;
-                Xs[c][kk] = (gk < ke && gc < C) ? V16[gc * ld + gk] : zero;
-            }
-        }
-        for (int e = tid; e < DP_KT * R32; e += 256) {
-            const int kk = e / R32, a = e % R32;
-            const int64_t gk = k0 + kk;
-            As[a][kk] = (gk < ke && a < r) ? (__bf16)A[gk * r + a] : zero;
-        }
-        __syncthreads();
 #pragma unroll
-        for (int q = 0; q < TPW; q++) {
-            const int tile = wave + 4 * q;
-            if (tile < NTILES) {
-                const int rt = tile / NT, ct = tile % NT;
+            for (int kp = 0; kp < BK / 2; kp++) {
+                const int kk = 2 * kp + (lane >> 5);
+                const float a_op = Xs[kk * L::XP + 32 * wave + (lane & 31)];
 #pragma unroll
-                for (int ks = 0; ks < DP_KT / 16; ks++) {
-                    bf16x8 a_op, b_op;
-                    const int kq = 16 * ks + 8 * (lane >> 5);
-#pragma unroll
-                    for (int t = 0; t < 8; t++) {
-                        a_op[t] = Xs[32 * rt + (lane & 31)][kq + t];
-                        b_op[t] = As[32 * ct + (lane & 31)][kq + t];
-                    }
-                    acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_op, b_op, acc[q], 0, 0, 0);
+                for (int t = 0; t < NT; t++) {
+                    const float b_op = As[kk * L::AP + 32 * t + (lane & 31)];
+                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a_op, b_op, acc[t], 0, 0, 0);
                 }
             }
         }
+    };
+
+    const int64_t nstage = (ke - kb + BK - 1) / BK;
+    if (nstage > 0) {
+        load_stage(kb);
+        store_stage(lds);
         __syncthreads();
+        for (int64_t st = 0; st < nstage; st++) {
+            const bool more = st + 1 < nstage;
+            if (more) load_stage(kb + (st + 1) * BK);
+            compute_stage(lds + (st & 1) * L::STAGE_BYTES);
+            if (more) store_stage(lds + ((st + 1) & 1) * L::STAGE_BYTES);
+            __syncthreads();
+        }
     }
+    // acc[t][v]: row 8 (v / 4) + 4 (lane / 32) + v % 4 of the wave's 32, column lane % 32
 #pragma unroll
-    for (int q = 0; q < TPW; q++) {
-        const int tile = wave + 4 * q;
-        if (tile < NTILES) {
-            const int rt = tile / NT, ct = tile % NT;
+    for (int t = 0; t < NT; t++) {
 #pragma unroll
-            for (int v = 0; v < 16; v++) {
-                const int i = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3), j = lane & 31;
-                const int64_t c = c0 + 32 * rt + i;
-                const int a = 32 * ct + j;
-                if (c < C && a < r) o[c * r + a] = acc[q][v];
-            }
+        for (int v = 0; v < 16; v++) {
+            const int i = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3), j = lane & 31;
+            const int64_t c = c0 + 32 * wave + i;
+            const int a = 32 * t + j;
+            if (c < C && a < r) o[c * r + a] = acc[t][v];
         }
     }
 }
 
-template <int NT, bool XT>
-__global__ __launch_bounds__(256) void k_dense_bf16(const __bf16 *__restrict__ V16, int64_t ld,
-                                                    int64_t C, int64_t K,
-                                                    const float *__restrict__ A, int r,
-                                                    int64_t kchunk, float *__restrict__ out) {
-    __shared__ __attribute__((aligned(16))) char lds[dense_bf16_lds_bytes<NT>()];
+template <bool BF16, bool XT, int NT>
+__global__ __launch_bounds__(256) void k_dense(const void *__restrict__ V, int64_t ld, int64_t C,
+                                               int64_t K, const float *__restrict__ A, int r,
+                                               const __bf16 *__restrict__ A16, int64_t lda16,
+                                               int64_t kchunk, int vec_ok, float *__restrict__ out) {
+    __shared__ __attribute__((aligned(16))) char lds[DenseLds<BF16, NT>::BYTES];
     const int64_t kb = (int64_t)blockIdx.y * kchunk;
-    dense_bf16_body<NT, XT>(V16, ld, C, A, r, (int64_t)blockIdx.x * DP_BC, kb, min(K, kb + kchunk),
-                            lds, out + (int64_t)blockIdx.y * C * r);
+    dense_body<BF16, XT, NT>(V, ld, C, A, r, A16, lda16, (int64_t)blockIdx.x * DENSE_BM, kb,
+                             min(K, kb + kchunk), vec_ok != 0, lds, out + (int64_t)blockIdx.y * C * r);
+}
+
+// A16[j][k] = bf16(A[k][j]) for j < r, 0 for r <= j < R32 (rows of lda16 >= K
+// entries; columns K..lda16 are left alone).  A block moves 64 rows of A
+// through LDS so that both sides are read and written contiguously.
+__device__ __forceinline__ void factor_t16_body(const float *__restrict__ A, int64_t K, int r,
+                                                int R32, __bf16 *__restrict__ A16, int64_t lda16,
+                                                int64_t k0, float *tile /* 64 x 129 */) {
+    for (int e = threadIdx.x; e < 64 * R32; e += blockDim.x) {
+        const int kk = e / R32, j = e % R32;
+        const int64_t gk = k0 + kk;
+        tile[kk * 129 + j] = (gk < K && j < r) ? A[gk * r + j] : 0.f;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * R32; e += blockDim.x) {
+        const int j = e / 64, kk = e % 64;
+        const int64_t gk = k0 + kk;
+        if (gk < K) A16[j * lda16 + gk] = (__bf16)tile[kk * 129 + j];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_factor_t16(const float *__restrict__ A, int64_t K, int r,
+                                                    int R32, __bf16 *__restrict__ A16, int64_t lda16) {
+    __shared__ float tile[64 * 129];
+    factor_t16_body(A, K, r, R32, A16, lda16, (int64_t)blockIdx.x * 64, tile);
+}
+
+// y (cols x rows) = x' in BF16: 64 x 64 tiles through LDS
+__global__ __launch_bounds__(256) void k_to_bf16_t(const float *__restrict__ x, int64_t rows,
+                                                   int64_t cols, int64_t ld, __bf16 *__restrict__ y) {
+    __shared__ float tile[64 * 65];
+    const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+        const int i = e / 64, j = e % 64;
+        tile[i * 65 + j] = (r0 + i < rows && c0 + j < cols) ? x[(r0 + i) * ld + c0 + j] : 0.f;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+        const int j = e / 64, i = e % 64;
+        if (c0 + j < cols && r0 + i < rows) y[(c0 + j) * rows + r0 + i] = (__bf16)tile[i * 65 + j];
+    }
+}
+
+hipError_t launch_to_bf16_t(const float *x, int64_t rows, int64_t cols, int64_t ld, __bf16 *y,
+                            hipStream_t s) {
+    if (rows <= 0 || cols <= 0) return hipSuccess;
+    const int64_t gy = (rows + 63) / 64, gx = (cols + 63) / 64;
+    if (gy > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_to_bf16_t, dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, s, x, rows, cols,
+                       ld, y);
+    return hipGetLastError();
 }
 
 // P = sum over split-K slices in slice order
@@ -223,10 +333,10 @@ hipError_t launch_to_bf16(const float *x, int64_t rows, int64_t cols, int64_t ld
     return hipGetLastError();
 }
 
-// split-K factor: enough blocks to fill the chip, at least 256 k per slice
+// split-K factor: about 1024 blocks to fill the chip, at least 256 k per slice
 int dense_nsplit(int64_t C, int64_t K) {
-    const int64_t rb = (C + DP_BC - 1) / DP_BC;
-    int64_t ns = (2048 + rb - 1) / rb;
+    const int64_t rb = (C + DENSE_BM - 1) / DENSE_BM;
+    int64_t ns = (1024 + rb - 1) / rb;
     const int64_t maxs = (K + 255) / 256;
     if (ns > maxs) ns = maxs;
     if (ns < 1) ns = 1;
@@ -234,57 +344,87 @@ int dense_nsplit(int64_t C, int64_t K) {
     return (int)ns;
 }
 
+// slice length: a multiple of 64 (both stage depths)
 int64_t dense_kchunk(int64_t C, int64_t K) {
     const int ns = dense_nsplit(C, K);
     int64_t kchunk = (K + ns - 1) / ns;
-    kchunk = ((kchunk + DP_KT - 1) / DP_KT) * DP_KT;
-    return kchunk < DP_KT ? DP_KT : kchunk;
+    kchunk = ((kchunk + 63) / 64) * 64;
+    return kchunk < 64 ? 64 : kchunk;
 }
 
-size_t dense_scratch_bytes(int64_t m, int64_t n, int r) {
+// Split-K partials of the larger half, then the BF16 factor copy (R32 x
+// lda16 with lda16 = max(m, n) rounded up to 64).
+static size_t dense_partial_bytes(int64_t m, int64_t n, int r) {
     const int64_t a = (int64_t)dense_nsplit(n, m) * n, b = (int64_t)dense_nsplit(m, n) * m;
-    return (size_t)(a > b ? a : b) * r * sizeof(float) + 256;
+    return (((size_t)(a > b ? a : b) * r * sizeof(float)) + 255) & ~(size_t)255;
+}
+static int64_t dense_lda16(int64_t m, int64_t n) {
+    const int64_t k = m > n ? m : n;
+    return (k + 63) / 64 * 64;
+}
+size_t dense_scratch_bytes(int64_t m, int64_t n, int r) {
+    const int R32 = (r + 31) / 32 * 32;
+    return dense_partial_bytes(m, n, r) + (size_t)R32 * dense_lda16(m, n) * 2 + 256;
 }
 
 template <int NT>
-static void dense_launch_nt(bool bf16, bool xt, const void *V, int64_t ld, int64_t C, int64_t K,
-                            const float *A, int r, int64_t kchunk, float *out, dim3 grid,
-                            hipStream_t s) {
-    if (bf16) {
-        if (xt)
-            hipLaunchKernelGGL((k_dense_bf16<NT, true>), grid, dim3(256), 0, s,
-                               (const __bf16 *)V, ld, C, K, A, r, kchunk, out);
-        else
-            hipLaunchKernelGGL((k_dense_bf16<NT, false>), grid, dim3(256), 0, s,
-                               (const __bf16 *)V, ld, C, K, A, r, kchunk, out);
-    } else {
-        if (xt)
-            hipLaunchKernelGGL((k_dense_fp32<NT, true>), grid, dim3(256), 0, s, (const float *)V,
-                               ld, C, K, A, r, kchunk, out);
-        else
-            hipLaunchKernelGGL((k_dense_fp32<NT, false>), grid, dim3(256), 0, s,
-                               (const float *)V, ld, C, K, A, r, kchunk, out);
-    }
+static void dense_launch_nt(bool bf16, bool xt, const void *X, int64_t ld, int64_t C, int64_t K,
+                            const float *A, int r, const __bf16 *A16, int64_t lda16, int64_t kchunk,
+                            int vec_ok, float *out, dim3 grid, hipStream_t s) {
+#define NMF_DL(B, XTT) hipLaunchKernelGGL((k_dense<B, XTT, NT>), grid, dim3(256), 0, s, X, ld, C, K, A, \
+                                          r, A16, lda16, kchunk, vec_ok, out)
+    if (bf16) NMF_DL(true, false);
+    else if (xt) NMF_DL(false, true);
+    else NMF_DL(false, false);
+#undef NMF_DL
 }
 
-// V (m x n, ld): float32, or its BF16 copy when bf16 != 0.
+// 16-byte vector loads of V are used when its base and rows are 16-byte aligned
+int dense_vec_ok(const void *V, int64_t ld, int bf16) {
+    return ((uintptr_t)V % 16) == 0 && ((ld * (bf16 ? 2 : 4)) % 16) == 0;
+}
+
+// V (m x n, ld): float32, or its BF16 copy when bf16 != 0, in which case
+// V16t (n x m) is the transposed BF16 copy (the H-update reads it; the
+// W-update reads V).  trans = 0: P (n x r) = V' A; trans = 1: P (m x r) = V A.
+// scratch: dense_scratch_bytes(m, n, r) bytes.
 hipError_t launch_dense_product(const void *V, int bf16, int64_t m, int64_t n, int64_t ld,
-                                int trans, const float *A, int r, float *P, float *scratch,
-                                hipStream_t s) {
-    const bool xt = trans == 0;
-    const int64_t C = xt ? n : m, K = xt ? m : n;
+                                const __bf16 *V16t, int trans, const float *A, int r, float *P,
+                                float *scratch, hipStream_t s) {
+    const bool h_update = trans == 0;
+    const int64_t C = h_update ? n : m, K = h_update ? m : n;
     if (C == 0) return hipSuccess;
+    if (K == 0) return hipErrorInvalidValue;  // callers reject empty V
     const int64_t kchunk = dense_kchunk(C, K);
     const int nsplit = (int)((K + kchunk - 1) / kchunk);
     float *out = nsplit > 1 ? scratch : P;
-    dim3 grid((unsigned)((C + DP_BC - 1) / DP_BC), (unsigned)(nsplit > 0 ? nsplit : 1));
-    if (K == 0) return hipErrorInvalidValue;  // callers reject empty V
     const int NT = (r + 31) / 32;
+    const void *X = V;
+    int64_t ldx = ld;
+    bool xt = h_update;
+    __bf16 *A16 = nullptr;
+    int64_t lda16 = 0;
+    if (bf16) {
+        if (h_update) {
+            if (!V16t) return hipErrorInvalidValue;
+            X = V16t;
+            ldx = m;
+        }
+        xt = false;
+        lda16 = dense_lda16(m, n);
+        A16 = (__bf16 *)((char *)scratch + dense_partial_bytes(m, n, r));
+        hipLaunchKernelGGL(k_factor_t16, dim3((unsigned)((K + 63) / 64)), dim3(256), 0, s, A, K, r,
+                           32 * NT, A16, lda16);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    dim3 grid((unsigned)((C + DENSE_BM - 1) / DENSE_BM), (unsigned)(nsplit > 0 ? nsplit : 1));
+    const int vec = dense_vec_ok(X, ldx, bf16);
     switch (NT) {
-    case 1: dense_launch_nt<1>(bf16, xt, V, ld, C, K, A, r, kchunk, out, grid, s); break;
-    case 2: dense_launch_nt<2>(bf16, xt, V, ld, C, K, A, r, kchunk, out, grid, s); break;
-    case 3: dense_launch_nt<3>(bf16, xt, V, ld, C, K, A, r, kchunk, out, grid, s); break;
-    default: dense_launch_nt<4>(bf16, xt, V, ld, C, K, A, r, kchunk, out, grid, s); break;
+    case 1: dense_launch_nt<1>(bf16, xt, X, ldx, C, K, A, r, A16, lda16, kchunk, vec, out, grid, s); break;
+    case 2: dense_launch_nt<2>(bf16, xt, X, ldx, C, K, A, r, A16, lda16, kchunk, vec, out, grid, s); break;
+    case 3: dense_launch_nt<3>(bf16, xt, X, ldx, C, K, A, r, A16, lda16, kchunk, vec, out, grid, s); break;
+    default: dense_launch_nt<4>(bf16, xt, X, ldx, C, K, A, r, A16, lda16, kchunk, vec, out, grid, s); break;
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || nsplit <= 1) return e;
@@ -301,36 +441,40 @@ hipError_t launch_dense_product(const void *V, int bf16, int64_t m, int64_t n, i
 // ------------------------------------------------------------------ batched
 namespace nmfi {
 
-// Many problems at once: block b computes 64 rows of one problem's P over
-// one k slice (items[b].idx = row block * nsplit + slice), exactly as the
-// single-problem product does, so the result is bitwise the same.
+// Many problems at once: block b computes 128 rows of one problem's P over
+// one k slice (items[b].idx = row block * nsplit + slice) with the same body
+// as the single-problem product, so the result is bitwise the same.
 template <int NTMAX, bool XT, bool BF16>
 __global__ __launch_bounds__(256) void k_bdense(const BItem *__restrict__ items,
                                                 const BProdProb *__restrict__ probs) {
-    constexpr int FP32_BYTES = dense_fp32_lds_floats<NTMAX>() * 4;
-    constexpr int BF16_BYTES = dense_bf16_lds_bytes<NTMAX>();
-    __shared__ __attribute__((aligned(16))) char lds[BF16 ? BF16_BYTES : FP32_BYTES];
+    __shared__ __attribute__((aligned(16))) char lds[DenseLds<BF16, NTMAX>::BYTES];
     const BItem it = items[blockIdx.x];
     const BProdProb P = probs[it.prob];
     const int NT = (P.r + 31) / 32;
     const int slice = it.idx % P.nsplit;
-    const int64_t c0 = (int64_t)(it.idx / P.nsplit) * DP_BC;
+    const int64_t c0 = (int64_t)(it.idx / P.nsplit) * DENSE_BM;
     const int64_t kb = (int64_t)slice * P.kchunk;
     const int64_t ke = min(P.K, kb + P.kchunk);
     float *o = P.nsplit > 1 ? P.part + (int64_t)slice * P.C * P.r : P.P;
-#define NMF_BDENSE_CASE(N)                                                                     \
-    if constexpr (BF16)                                                                        \
-        dense_bf16_body<N, XT>((const __bf16 *)P.V, P.ld, P.C, P.A, P.r, c0, kb, ke, lds, o);  \
-    else                                                                                       \
-        dense_fp32_body<N, XT>((const float *)P.V, P.ld, P.C, P.A, P.r, c0, kb, ke,            \
-                               (float *)lds, o);
+    const bool vec = ((uintptr_t)P.V % 16) == 0 && ((P.ld * (BF16 ? 2 : 4)) % 16) == 0;
+#define NMF_BD_BODY(N) \
+    dense_body<BF16, XT, N>(P.V, P.ld, P.C, P.A, P.r, P.A16, P.lda16, c0, kb, ke, vec, lds, o)
     switch (NT) {
-    case 1: { NMF_BDENSE_CASE(1) } break;
-    case 2: if constexpr (NTMAX >= 2) { NMF_BDENSE_CASE(2) } break;
-    case 3: if constexpr (NTMAX >= 3) { NMF_BDENSE_CASE(3) } break;
-    default: if constexpr (NTMAX >= 4) { NMF_BDENSE_CASE(4) } break;
+    case 1: NMF_BD_BODY(1); break;
+    case 2: if constexpr (NTMAX >= 2) NMF_BD_BODY(2); break;
+    case 3: if constexpr (NTMAX >= 3) NMF_BD_BODY(3); break;
+    default: if constexpr (NTMAX >= 4) NMF_BD_BODY(4); break;
     }
-#undef NMF_BDENSE_CASE
+#undef NMF_BD_BODY
+}
+
+// BF16 factor copies of many problems: item = (problem, block of 64 rows of A)
+__global__ __launch_bounds__(256) void k_bfactor_t16(const BItem *__restrict__ items,
+                                                     const BProdProb *__restrict__ probs) {
+    __shared__ float tile[64 * 129];
+    const BItem it = items[blockIdx.x];
+    const BProdProb P = probs[it.prob];
+    factor_t16_body(P.A, P.K, P.r, (P.r + 31) / 32 * 32, P.A16, P.lda16, (int64_t)it.idx * 64, tile);
 }
 
 // split-K sums of many problems, the same loop as k_split_reduce
@@ -347,16 +491,21 @@ __global__ void k_bsplit_reduce(const BItem *__restrict__ items, const BProdProb
 }
 
 hipError_t launch_bdense(const BItem *items, int64_t nitems, const BProdProb *probs, int ntmax,
-                         bool xt, bool bf16, const BItem *red_items, int64_t nred, hipStream_t s) {
+                         bool xt, bool bf16, const BItem *red_items, int64_t nred,
+                         const BItem *f16_items, int64_t nf16, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
+    if (bf16 && nf16 > 0)
+        hipLaunchKernelGGL(k_bfactor_t16, dim3((unsigned)nf16), dim3(256), 0, s, f16_items, probs);
     const dim3 g((unsigned)nitems), b(256);
 #define NMF_BD(NTM, X, B) hipLaunchKernelGGL((k_bdense<NTM, X, B>), g, b, 0, s, items, probs)
     if (ntmax <= 2) {
-        if (xt) { if (bf16) NMF_BD(2, true, true); else NMF_BD(2, true, false); }
-        else { if (bf16) NMF_BD(2, false, true); else NMF_BD(2, false, false); }
+        if (bf16) NMF_BD(2, false, true);
+        else if (xt) NMF_BD(2, true, false);
+        else NMF_BD(2, false, false);
     } else {
-        if (xt) { if (bf16) NMF_BD(4, true, true); else NMF_BD(4, true, false); }
-        else { if (bf16) NMF_BD(4, false, true); else NMF_BD(4, false, false); }
+        if (bf16) NMF_BD(4, false, true);
+        else if (xt) NMF_BD(4, true, false);
+        else NMF_BD(4, false, false);
     }
 #undef NMF_BD
     if (nred > 0)

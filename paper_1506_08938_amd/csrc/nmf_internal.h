@@ -56,6 +56,7 @@ hipError_t launch_nqp(const NqpVariant &v, const NqpParams &p, hipStream_t s);
 
 // ------------------------------------------------------------------ products
 constexpr int SPMM_CHUNK = 512;  // stored entries per SpMM work item
+constexpr int DENSE_BM = 128;    // rows of P per dense-product block
 
 struct SpChunk {
     int32_t row, start, end, dest;  // dest < 0: write P[row]; else partial slot
@@ -88,8 +89,10 @@ size_t dense_scratch_bytes(int64_t m, int64_t n, int r);
 int dense_nsplit(int64_t C, int64_t K);
 int64_t dense_kchunk(int64_t C, int64_t K);
 hipError_t launch_dense_product(const void *V, int bf16, int64_t m, int64_t n, int64_t ld,
-                                int trans, const float *A, int r, float *P, float *scratch,
-                                hipStream_t s);
+                                const __bf16 *V16t, int trans, const float *A, int r, float *P,
+                                float *scratch, hipStream_t s);
+hipError_t launch_to_bf16_t(const float *x, int64_t rows, int64_t cols, int64_t ld, __bf16 *y,
+                            hipStream_t s);
 hipError_t launch_to_bf16(const float *x, int64_t rows, int64_t cols, int64_t ld, __bf16 *y,
                           hipStream_t s);
 
@@ -109,7 +112,8 @@ struct BGramProb {
     int nchunks;
 };
 struct BProdProb {
-    const void *V;  // float (m x n, ld) or its BF16 copy (ld = n)
+    const void *V;  // FP32: V (m x n, ld); BF16: the copy read along k (V16 for
+                    // the W-update, V16t for the H-update; ld = K)
     int64_t ld;
     int64_t C, K;   // P is C x r, summed over K
     const float *A; // K x r
@@ -118,6 +122,8 @@ struct BProdProb {
     float *part;    // nsplit x C x r split-K partials (when nsplit > 1)
     int64_t kchunk;
     int nsplit;
+    __bf16 *A16;    // BF16: the factor converted and transposed, R32 x lda16
+    int64_t lda16;
 };
 struct BSolveProb {
     const float *G;  // r x r
@@ -137,8 +143,10 @@ hipError_t launch_bgram(const BItem *items, int64_t nitems, const BGramProb *pro
                         int ntmax, int precision, hipStream_t s);
 // items: (problem, row block * nsplit + slice); reduce items: (problem,
 // block of 4096 entries of P) for problems with nsplit > 1
+// f16_items (BF16): (problem, block of 64 rows of A) for the factor conversion
 hipError_t launch_bdense(const BItem *items, int64_t nitems, const BProdProb *probs, int ntmax,
-                         bool xt, bool bf16, const BItem *red_items, int64_t nred, hipStream_t s);
+                         bool xt, bool bf16, const BItem *red_items, int64_t nred,
+                         const BItem *f16_items, int64_t nf16, hipStream_t s);
 hipError_t launch_bnqp(const NqpVariant &v, const BSolveChunk *chunks, int nchunks,
                        unsigned int *queue, const BSolveProb *probs, int max_inner, double eps,
                        int ls_guard, hipStream_t s);

@@ -108,7 +108,7 @@ int run_foldin_batch(nmf_server *S, std::vector<std::shared_ptr<Req>> &batch, hi
         float *Pj = P + off * r;
         probs[j].P = Pj;
         if (q.V.kind == NMF_DENSE)
-            e = launch_dense_product(q.V.dense, 0, B->m, q.V.cols, q.V.ld, 0, B->W, r, Pj, dscr, s);
+            e = launch_dense_product(q.V.dense, 0, B->m, q.V.cols, q.V.ld, nullptr, 0, B->W, r, Pj, dscr, s);
         else
             e = launch_spmm_rows(q.V.t_rowptr, q.V.cols, q.V.t_colidx, q.V.t_vals, B->W, r, Pj, s);
         off += q.V.cols;

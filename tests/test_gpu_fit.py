@@ -52,7 +52,8 @@ def test_gram_matches_oracle(r, k):
 
 # --------------------------------------------------------------------------- products
 @pytest.mark.parametrize("m,n,r", [(1, 1, 1), (37, 23, 5), (200, 150, 10), (1000, 777, 64),
-                                   (300, 5000, 100), (129, 65, 128)])
+                                   (300, 5000, 100), (129, 65, 128), (2048, 1536, 64),
+                                   (4100, 2056, 32), (6000, 136, 96)])
 def test_dense_product_matches_oracle(m, n, r):
     nat = native()
     g = np.random.default_rng(m + n + r)
