@@ -211,11 +211,27 @@ extern "C" int nmf_fit_batched(int32_t count, const nmf_problem *probs, const nm
     }
 
     // ---------------------------------------------------------------- graph
+    // The solve launches of a half (one per kernel variant) are independent:
+    // they are captured as parallel branches (fork/join through events on
+    // side streams), so one variant's tail overlaps the others' work.
     hipStream_t cs = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    size_t maxg = 0;
+    for (int h = 0; h < 2; h++) maxg = std::max(maxg, dh[h].groups.size());
+    std::vector<hipStream_t> side(maxg > 1 ? maxg - 1 : 0, nullptr);
+    std::vector<hipEvent_t> evs;
     if (!st && opt->max_outer > 0) {
         e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+        for (size_t i = 0; i < side.size() && e == hipSuccess; i++)
+            e = hipStreamCreateWithFlags(&side[i], hipStreamNonBlocking);
+        // one fork event and one join event per side stream and half-iteration
+        const size_t nev = (size_t)opt->max_outer * 2 * (1 + side.size());
+        for (size_t i = 0; i < nev && e == hipSuccess; i++) {
+            hipEvent_t ev = nullptr;
+            e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            if (e == hipSuccess) evs.push_back(ev);
+        }
         if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         for (int t = 0; t < opt->max_outer && e == hipSuccess; t++) {
             for (int h = 0; h < 2 && e == hipSuccess; h++) {
@@ -228,10 +244,19 @@ extern "C" int nmf_fit_batched(int32_t count, const nmf_problem *probs, const nm
                     e = launch_bdense(dh[h].prod_items, dh[h].n_prod_items, dh[h].prod, ntmax, h == 0,
                                       bf16, dh[h].red_items, dh[h].n_red_items, dh[h].f16_items,
                                       dh[h].n_f16_items, cs);
-                for (size_t g = 0; g < dh[h].groups.size() && e == hipSuccess; g++)
-                    e = launch_bnqp(dh[h].groups[g].first, dh[h].groups[g].second.first,
-                                    dh[h].groups[g].second.second, queues + gi + (int)g,
-                                    dh[h].solve, opt->max_inner, opt->eps, opt->ls_guard ? 1 : 0, cs);
+                const size_t ng = dh[h].groups.size();
+                const size_t ev0 = ((size_t)t * 2 + h) * (1 + side.size());
+                if (e == hipSuccess && ng > 1) e = hipEventRecord(evs[ev0], cs);  // fork
+                for (size_t g = 0; g < ng && e == hipSuccess; g++) {
+                    hipStream_t gs = g == 0 ? cs : side[g - 1];
+                    if (g > 0) e = hipStreamWaitEvent(gs, evs[ev0], 0);
+                    if (e == hipSuccess)
+                        e = launch_bnqp(dh[h].groups[g].first, dh[h].groups[g].second.first,
+                                        dh[h].groups[g].second.second, queues + gi + (int)g,
+                                        dh[h].solve, opt->max_inner, opt->eps, opt->ls_guard ? 1 : 0, gs);
+                    if (e == hipSuccess && g > 0) e = hipEventRecord(evs[ev0 + g], gs);
+                }
+                for (size_t g = 1; g < ng && e == hipSuccess; g++) e = hipStreamWaitEvent(cs, evs[ev0 + g], 0);  // join
             }
         }
         hipError_t e2 = hipStreamEndCapture(cs, &graph);
@@ -244,6 +269,9 @@ extern "C" int nmf_fit_batched(int32_t count, const nmf_problem *probs, const nm
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (cs) (void)hipStreamDestroy(cs);
+    for (hipStream_t x : side)
+        if (x) (void)hipStreamDestroy(x);
+    for (hipEvent_t ev : evs) (void)hipEventDestroy(ev);
 
     // ---------------------------------------------------------------- statistics
     if (!st && per_problem) {
