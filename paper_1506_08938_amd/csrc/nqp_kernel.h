@@ -29,7 +29,7 @@
 
 namespace nmfi {
 
-constexpr int NQP_BLOCK = 256;
+constexpr int NQP_BLOCK_SMALL = 256;  // threads per block of a small launch
 
 __device__ __forceinline__ int f2i(float v) { return __builtin_bit_cast(int, v); }
 __device__ __forceinline__ float i2f(int v) { return __builtin_bit_cast(float, v); }
@@ -180,13 +180,27 @@ constexpr int nqp_lds_bytes() {
     return (R * nqp_stride<R>() + 3 * R) * 4 + 64;
 }
 
+template <int E>
+constexpr int nqp_regs_waves() {
+    return NMF_NQP_WPE ? NMF_NQP_WPE : (E <= 12 ? 6 : (E <= 20 ? 4 : (E <= 28 ? 3 : 2)));
+}
+
+// Threads per block of a large launch.  The block's waves share one staged
+// Q, so eight waves per block halve the LDS per wave; used when registers
+// allow at least four waves per SIMD (two such blocks per CU), measured up to
+// 25% faster than four-wave blocks at r = 100..128.
+template <int E, int L>
+constexpr int nqp_block() {
+    return nqp_regs_waves<E>() >= 4 ? 512 : 256;
+}
+
 // Waves per SIMD: the register table, capped by how many blocks the 160 KB
-// of LDS of a CU holds (each block puts one wave on each of the 4 SIMDs).
+// of LDS of a CU holds (a block puts block/256 waves on each of the 4 SIMDs).
 // Asking for more than LDS allows makes the compiler drop the register cap.
 template <int E, int L>
 constexpr int nqp_waves_per_eu() {
-    constexpr int by_regs = NMF_NQP_WPE ? NMF_NQP_WPE : (E <= 12 ? 6 : (E <= 20 ? 4 : (E <= 28 ? 3 : 2)));
-    constexpr int by_lds = (160 * 1024) / nqp_lds_bytes<E * L>();
+    constexpr int by_regs = nqp_regs_waves<E>();
+    constexpr int by_lds = (160 * 1024) / nqp_lds_bytes<E * L>() * (nqp_block<E, L>() / 256);
     return by_regs < by_lds ? by_regs : (by_lds > 0 ? by_lds : 1);
 }
 
@@ -419,13 +433,13 @@ __device__ __forceinline__ void nqp_columns(const float *__restrict__ sQ,
 template <int R, int SQ>
 __device__ __forceinline__ void stage_q(const float *__restrict__ gram, int r, float *sQ,
                                         float *sD, float *sZ) {
-    for (int t = threadIdx.x; t < 2 * R; t += NQP_BLOCK) sZ[t] = t == R ? 1.f : 0.f;
-    for (int i = threadIdx.x; i < R; i += NQP_BLOCK) {
+    for (int t = threadIdx.x; t < 2 * R; t += blockDim.x) sZ[t] = t == R ? 1.f : 0.f;
+    for (int i = threadIdx.x; i < R; i += blockDim.x) {
         const float d = i < r ? gram[(size_t)i * r + i] : 0.f;
         sD[i] = d > 0.f ? sqrtf(d) : 0.f;
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < R * R; t += NQP_BLOCK) {
+    for (int t = threadIdx.x; t < R * R; t += blockDim.x) {
         const int i = t / R, j = t - (t / R) * R;
         float v;
         if (i == j) v = 1.f;
@@ -442,7 +456,7 @@ __device__ __forceinline__ void flush_inner(unsigned long long v, unsigned long 
 }
 
 template <int E, int L>
-__global__ __launch_bounds__(NQP_BLOCK)
+__global__ __launch_bounds__((nqp_block<E, L>()))
 __attribute__((amdgpu_waves_per_eu(nqp_waves_per_eu<E, L>(), 8))) void k_nqp(const NqpParams a) {
     constexpr int R = E * L;
     constexpr int SQ = nqp_stride<R>();
@@ -464,7 +478,7 @@ __attribute__((amdgpu_waves_per_eu(nqp_waves_per_eu<E, L>(), 8))) void k_nqp(con
 // solves the chunk's columns; its lane groups refill from an LDS counter.
 // All problems of one launch share the kernel variant (E, L).
 template <int E, int L>
-__global__ __launch_bounds__(NQP_BLOCK)
+__global__ __launch_bounds__((nqp_block<E, L>()))
 __attribute__((amdgpu_waves_per_eu(nqp_waves_per_eu<E, L>(), 8))) void k_bnqp(
     const BSolveChunk *__restrict__ chunks, int nchunks, unsigned int *queue,
     const BSolveProb *__restrict__ probs, int max_inner, double eps, int ls_guard) {
@@ -496,22 +510,29 @@ __attribute__((amdgpu_waves_per_eu(nqp_waves_per_eu<E, L>(), 8))) void k_bnqp(
     }
 }
 
+// Blocks of one kernel per CU at the given block size (cached per size).
+template <class K>
+int nqp_blocks_per_cu(K kernel, int block, int (&cache)[2]) {
+    int &c = cache[block == NQP_BLOCK_SMALL ? 0 : 1];
+    if (c < 0) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, block, 0) != hipSuccess || nb < 1) nb = 1;
+        c = nb;
+    }
+    return c;
+}
+
 template <int E, int L>
 hipError_t launch_bnqp_t(const BSolveChunk *chunks, int nchunks, unsigned int *queue,
                          const BSolveProb *probs, int max_inner, double eps, int ls_guard,
                          hipStream_t s) {
     if (nchunks <= 0) return hipSuccess;
-    static int per_cu = -1;
-    if (per_cu < 0) {
-        int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bnqp<E, L>, NQP_BLOCK, 0) !=
-                hipSuccess || nb < 1)
-            nb = 1;
-        per_cu = nb;
-    }
-    const int64_t cap = (int64_t)per_cu * device_cu_count();
+    static int cache[2] = {-1, -1};
+    // small launches spread four-wave blocks over more CUs
+    const int block = nchunks >= 2 * device_cu_count() ? nqp_block<E, L>() : NQP_BLOCK_SMALL;
+    const int64_t cap = (int64_t)nqp_blocks_per_cu(k_bnqp<E, L>, block, cache) * device_cu_count();
     const int grid = (int)(nchunks < cap ? nchunks : cap);
-    hipLaunchKernelGGL((k_bnqp<E, L>), dim3(grid), dim3(NQP_BLOCK), 0, s, chunks, nchunks, queue,
+    hipLaunchKernelGGL((k_bnqp<E, L>), dim3(grid), dim3(block), 0, s, chunks, nchunks, queue,
                        probs, max_inner, eps, ls_guard);
     return hipGetLastError();
 }
@@ -519,19 +540,16 @@ hipError_t launch_bnqp_t(const BSolveChunk *chunks, int nchunks, unsigned int *q
 template <int E, int L>
 hipError_t launch_nqp_t(const NqpParams &p, hipStream_t s) {
     if (p.ncols <= 0) return hipSuccess;
-    static int per_cu = -1;
-    if (per_cu < 0) {
-        int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_nqp<E, L>, NQP_BLOCK, 0) !=
-                hipSuccess || nb < 1)
-            nb = 1;
-        per_cu = nb;
-    }
-    const int64_t cols_per_block = (NQP_BLOCK / 64) * (64 / L);
-    int64_t want = (p.ncols + cols_per_block - 1) / cols_per_block;
-    int64_t cap = (int64_t)per_cu * device_cu_count();
-    int grid = (int)(want < cap ? want : cap);
-    hipLaunchKernelGGL((k_nqp<E, L>), dim3(grid), dim3(NQP_BLOCK), 0, s, p);
+    static int cache[2] = {-1, -1};
+    // a launch that cannot give every CU two large blocks uses four-wave blocks
+    const int big = nqp_block<E, L>();
+    const int64_t big_cols = (int64_t)2 * device_cu_count() * (big / 64) * (64 / L);
+    const int block = p.ncols >= big_cols ? big : NQP_BLOCK_SMALL;
+    const int64_t cols_per_block = (block / 64) * (64 / L);
+    const int64_t want = (p.ncols + cols_per_block - 1) / cols_per_block;
+    const int64_t cap = (int64_t)nqp_blocks_per_cu(k_nqp<E, L>, block, cache) * device_cu_count();
+    const int grid = (int)(want < cap ? want : cap);
+    hipLaunchKernelGGL((k_nqp<E, L>), dim3(grid), dim3(block), 0, s, p);
     return hipGetLastError();
 }
 
