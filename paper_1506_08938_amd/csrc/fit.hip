@@ -6,6 +6,8 @@
 
 #include <vector>
 
+#include <algorithm>
+
 #include "nmf_internal.h"
 
 using namespace nmfi;
@@ -200,6 +202,13 @@ struct nmf_plan {
     bool own_t = false;
     SpmmPlan sp_h{}, sp_w{};
     float *sp_partial = nullptr;
+    // hot columns of V (the H-update's longest rows of CSR(V')): their products
+    // come from a dense m x T copy through the dense product instead of row gathers
+    int T_hot = 0, ld_hot = 0;    // ld_hot: T rounded up to 4 (16-byte rows)
+    int32_t *hot_idx = nullptr;   // T column indices (device)
+    float *V_hot = nullptr;       // m x ld_hot
+    float *P_hot = nullptr;       // T x r
+    float *hot_scratch = nullptr; // dense_scratch_bytes(m, T, r)
     // dense
     __bf16 *V16 = nullptr, *V16t = nullptr;  // BF16 copies of V and V'
     float *dense_scratch = nullptr;
@@ -225,11 +234,59 @@ static void plan_free(nmf_plan *p) {
     free_spmm_plan(&p->sp_h);
     free_spmm_plan(&p->sp_w);
     if (p->sp_partial) (void)hipFree(p->sp_partial);
+    if (p->hot_idx) (void)hipFree(p->hot_idx);
+    if (p->V_hot) (void)hipFree(p->V_hot);
+    if (p->P_hot) (void)hipFree(p->P_hot);
+    if (p->hot_scratch) (void)hipFree(p->hot_scratch);
     if (p->V16) (void)hipFree(p->V16);
     if (p->V16t) (void)hipFree(p->V16t);
     if (p->dense_scratch) (void)hipFree(p->dense_scratch);
     if (p->ws) (void)hipFree(p->ws);
     delete p;
+}
+
+// Hot columns of a CSR V: a column j with c_j stored entries costs the
+// H-update c_j gathered rows of W (4r bytes each, from cache), and costs the
+// dense product about m (4 bytes + 2r flop).  At the gather and MFMA rates
+// measured on MI355X the dense side wins from c_j ~ m/17 on; columns with
+// c_j >= max(m/16, 256) are taken, the longest first (ties: lower index),
+// at most 256 of them and only when there are at least 4.
+static int choose_hot_columns(nmf_plan *p, const std::vector<int32_t> &t_rowptr,
+                              std::vector<char> &hot, hipStream_t s) {
+    const int64_t n = p->n, m = p->m;
+    const int64_t thr = std::max<int64_t>((m + 15) / 16, 256);
+    std::vector<int32_t> cand;
+    for (int64_t j = 0; j < n; j++)
+        if (t_rowptr[j + 1] - t_rowptr[j] >= thr) cand.push_back((int32_t)j);
+    std::stable_sort(cand.begin(), cand.end(), [&](int32_t a, int32_t b) {
+        return t_rowptr[a + 1] - t_rowptr[a] > t_rowptr[b + 1] - t_rowptr[b];
+    });
+    if (cand.size() > 256) cand.resize(256);
+    if (cand.size() < 4) return NMF_OK;
+    std::sort(cand.begin(), cand.end());  // slots in column order
+    const int T = (int)cand.size(), ldT = (T + 3) / 4 * 4;
+    hot.assign(n, 0);
+    std::vector<int32_t> slot(n, -1);
+    for (int t = 0; t < T; t++) {
+        hot[cand[t]] = 1;
+        slot[cand[t]] = t;
+    }
+    int32_t *dslot = nullptr;
+    hipError_t e = hipMalloc((void **)&p->hot_idx, T * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc((void **)&dslot, n * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc((void **)&p->V_hot, (size_t)m * ldT * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc((void **)&p->P_hot, (size_t)T * p->r * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc((void **)&p->hot_scratch, dense_scratch_bytes(m, T, p->r));
+    if (e == hipSuccess) e = hipMemcpyAsync(p->hot_idx, cand.data(), T * sizeof(int32_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(dslot, slot.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = launch_hot_scatter_v(p->V.rowptr, m, p->V.colidx, p->V.vals, dslot, ldT, p->V_hot, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (dslot) (void)hipFree(dslot);
+    if (e != hipSuccess) return hip_fail(e, "hot columns");
+    p->T_hot = T;
+    p->ld_hot = ldT;
+    return NMF_OK;
 }
 
 extern "C" int nmf_plan_create(const nmf_matrix *V, int32_t r, const nmf_reg *reg, const nmf_opts *opt,
@@ -274,7 +331,9 @@ extern "C" int nmf_plan_create(const nmf_matrix *V, int32_t r, const nmf_reg *re
         }
         std::vector<int32_t> h;
         if (!st) st = host_rowptr(p->t_rowptr, p->n, h, s);
-        if (!st) st = build_spmm_plan(h, &p->sp_h, s);
+        std::vector<char> hot;
+        if (!st) st = choose_hot_columns(p, h, hot, s);
+        if (!st) st = build_spmm_plan(h, &p->sp_h, s, p->T_hot ? &hot : nullptr);
         if (!st) st = host_rowptr(V->rowptr, p->m, h, s);
         if (!st) st = build_spmm_plan(h, &p->sp_w, s);
         if (!st) {
@@ -350,6 +409,7 @@ size_t plan_footprint(const nmf_matrix *V, int r, const nmf_opts *opt) {
         if (opt->precision == NMF_BF16) b += 2 * al256((size_t)m * n * 2);  // V16 and V16t
     } else {
         b += 3 * al256((size_t)(V->nnz + n + 1) * 4);  // CSR(V') when built here
+        b += al256((size_t)m * 256 * 4) + al256(dense_scratch_bytes(m, 256, r));  // hot columns, at most
         b += al256((size_t)(V->nnz / SPMM_CHUNK + m + n + 2) * (sizeof(SpChunk) + sizeof(SpSplit)));
     }
     return b + 65536;
@@ -422,8 +482,16 @@ static hipError_t half_update(nmf_plan *p, bool h_update, const float *A, float 
     {
         PhaseMark pm(p, NMF_PHASE_PRODUCT, s);
         if (p->V.kind == NMF_CSR) {
-            if (h_update) e = launch_spmm(p->sp_h, p->t_colidx, p->t_vals, A, p->r, p->P, p->sp_partial, s);
-            else e = launch_spmm(p->sp_w, p->V.colidx, p->V.vals, A, p->r, p->P, p->sp_partial, s);
+            if (h_update) {
+                e = launch_spmm(p->sp_h, p->t_colidx, p->t_vals, A, p->r, p->P, p->sp_partial, s);
+                if (e == hipSuccess && p->T_hot) {  // the hot rows: (V_hot' W), then into P
+                    e = launch_dense_product(p->V_hot, 0, p->m, p->T_hot, p->ld_hot, nullptr, 0, A, p->r,
+                                             p->P_hot, p->hot_scratch, s);
+                    if (e == hipSuccess) e = launch_hot_rows_out(p->P_hot, p->hot_idx, p->T_hot, p->r, p->P, s);
+                }
+            } else {
+                e = launch_spmm(p->sp_w, p->V.colidx, p->V.vals, A, p->r, p->P, p->sp_partial, s);
+            }
         } else {
             const bool bf = p->V16 != nullptr;
             e = launch_dense_product(bf ? (const void *)p->V16 : (const void *)p->V.dense, bf, p->m, p->n,

@@ -340,7 +340,7 @@ int dense_nsplit(int64_t C, int64_t K) {
     const int64_t maxs = (K + 255) / 256;
     if (ns > maxs) ns = maxs;
     if (ns < 1) ns = 1;
-    if (ns > 64) ns = 64;
+    if (ns > 512) ns = 512;
     return (int)ns;
 }
 
@@ -355,7 +355,13 @@ int64_t dense_kchunk(int64_t C, int64_t K) {
 // Split-K partials of the larger half, then the BF16 factor copy (R32 x
 // lda16 with lda16 = max(m, n) rounded up to 64).
 static size_t dense_partial_bytes(int64_t m, int64_t n, int r) {
-    const int64_t a = (int64_t)dense_nsplit(n, m) * n, b = (int64_t)dense_nsplit(m, n) * m;
+    // slices actually used (a single slice writes P directly)
+    auto used = [](int64_t C, int64_t K) {
+        const int64_t kc = dense_kchunk(C, K);
+        const int64_t ns = K > 0 ? (K + kc - 1) / kc : 0;
+        return ns > 1 ? ns * C : 0;
+    };
+    const int64_t a = used(n, m), b = used(m, n);
     return (((size_t)(a > b ? a : b) * r * sizeof(float)) + 255) & ~(size_t)255;
 }
 static int64_t dense_lda16(int64_t m, int64_t n) {

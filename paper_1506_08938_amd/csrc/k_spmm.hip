@@ -193,13 +193,15 @@ hipError_t launch_spmm(const SpmmPlan &pl, const int32_t *colidx, const float *v
 }
 
 // Chunk list of a CSR matrix from its host row pointers.
-int build_spmm_plan(const std::vector<int32_t> &rowptr, SpmmPlan *pl, hipStream_t s) {
+int build_spmm_plan(const std::vector<int32_t> &rowptr, SpmmPlan *pl, hipStream_t s,
+                    const std::vector<char> *skip) {
     const int64_t nrows = (int64_t)rowptr.size() - 1;
     std::vector<SpChunk> ch;
     std::vector<SpSplit> sp;
     ch.reserve(nrows + 16);
     int32_t slots = 0;
     for (int64_t i = 0; i < nrows; i++) {
+        if (skip && (*skip)[i]) continue;  // written by someone else
         const int32_t b = rowptr[i], e = rowptr[i + 1];
         const int32_t len = e - b;
         if (len <= SPMM_CHUNK) {
@@ -274,6 +276,58 @@ hipError_t launch_spmm_rows(const int32_t *rowptr, int64_t nrows, const int32_t 
         hipLaunchKernelGGL((k_spmm_rows<1, 64, 1>), grid, blk, 0, s, rowptr, nrows, colidx, vals, A, r, P);
     else
         hipLaunchKernelGGL((k_spmm_rows<1, 64, 2>), grid, blk, 0, s, rowptr, nrows, colidx, vals, A, r, P);
+    return hipGetLastError();
+}
+
+}  // namespace nmfi
+
+// ------------------------------------------------------------------ hot columns
+namespace nmfi {
+
+// V_hot (m x T with row stride T, T >= the number of hot columns; zero
+// elsewhere): V_hot[i][slot[j]] = V[i][j] for the stored entries of the hot
+// columns (slot[j] >= 0).
+__global__ void k_hot_scatter_v(const int32_t *__restrict__ rowptr, int64_t m,
+                                const int32_t *__restrict__ colidx, const float *__restrict__ vals,
+                                const int32_t *__restrict__ slot, int T, float *__restrict__ Vhot) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        float *row = Vhot + i * T;
+        for (int t = 0; t < T; t++) row[t] = 0.f;
+        for (int32_t e = rowptr[i]; e < rowptr[i + 1]; e++) {
+            const int32_t sl = slot[colidx[e]];
+            if (sl >= 0) row[sl] = vals[e];
+        }
+    }
+}
+
+hipError_t launch_hot_scatter_v(const int32_t *rowptr, int64_t m, const int32_t *colidx,
+                                const float *vals, const int32_t *slot, int T, float *Vhot,
+                                hipStream_t s) {
+    if (m <= 0 || T <= 0) return hipSuccess;
+    int64_t blocks = (m + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_hot_scatter_v, dim3((unsigned)blocks), dim3(256), 0, s, rowptr, m, colidx,
+                       vals, slot, T, Vhot);
+    return hipGetLastError();
+}
+
+// P[idx[t]] = Phot[t] for the T hot rows (r floats each)
+__global__ void k_hot_rows_out(const float *__restrict__ Phot, const int32_t *__restrict__ idx,
+                               int T, int r, float *__restrict__ P) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)T * r;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t = e / r, a = e - t * r;
+        P[(int64_t)idx[t] * r + a] = Phot[e];
+    }
+}
+
+hipError_t launch_hot_rows_out(const float *Phot, const int32_t *idx, int T, int r, float *P,
+                               hipStream_t s) {
+    if (T <= 0) return hipSuccess;
+    int64_t blocks = ((int64_t)T * r + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(k_hot_rows_out, dim3((unsigned)blocks), dim3(256), 0, s, Phot, idx, T, r, P);
     return hipGetLastError();
 }
 

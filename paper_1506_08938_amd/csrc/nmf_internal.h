@@ -70,7 +70,14 @@ struct SpmmPlan {
     int64_t nrows, nchunks, nsplits;
     int32_t nslots;
 };
-int build_spmm_plan(const std::vector<int32_t> &rowptr, SpmmPlan *pl, hipStream_t s);
+// skip (optional, one flag per row): rows that get no chunk (written elsewhere)
+int build_spmm_plan(const std::vector<int32_t> &rowptr, SpmmPlan *pl, hipStream_t s,
+                    const std::vector<char> *skip = nullptr);
+hipError_t launch_hot_scatter_v(const int32_t *rowptr, int64_t m, const int32_t *colidx,
+                                const float *vals, const int32_t *slot, int T, float *Vhot,
+                                hipStream_t s);
+hipError_t launch_hot_rows_out(const float *Phot, const int32_t *idx, int T, int r, float *P,
+                               hipStream_t s);
 void free_spmm_plan(SpmmPlan *pl);
 hipError_t launch_spmm(const SpmmPlan &pl, const int32_t *colidx, const float *vals, const float *A,
                        int r, float *P, float *partial, hipStream_t s);
