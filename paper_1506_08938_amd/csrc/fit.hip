@@ -249,8 +249,9 @@ static void plan_free(nmf_plan *p) {
 // H-update c_j gathered rows of W (4r bytes each, from cache), and costs the
 // dense product about m (4 bytes + 2r flop).  At the gather and MFMA rates
 // measured on MI355X the dense side wins from c_j ~ m/17 on; columns with
-// c_j >= max(m/16, 256) are taken, the longest first (ties: lower index),
-// at most 256 of them and only when there are at least 4.
+// c_j >= max(m/16, 256) are taken, the longest first (ties: lower index):
+// all of them up to 127, else 128 or 256 (whole 128-row slabs of the dense
+// product), and only when there are at least 4.
 static int choose_hot_columns(nmf_plan *p, const std::vector<int32_t> &t_rowptr,
                               std::vector<char> &hot, hipStream_t s) {
     const int64_t n = p->n, m = p->m;
@@ -261,7 +262,8 @@ static int choose_hot_columns(nmf_plan *p, const std::vector<int32_t> &t_rowptr,
     std::stable_sort(cand.begin(), cand.end(), [&](int32_t a, int32_t b) {
         return t_rowptr[a + 1] - t_rowptr[a] > t_rowptr[b + 1] - t_rowptr[b];
     });
-    if (cand.size() > 256) cand.resize(256);
+    // whole 128-row slabs of the dense product once there are enough
+    if (cand.size() >= 128) cand.resize(std::min<size_t>(cand.size(), 256) / 128 * 128);
     if (cand.size() < 4) return NMF_OK;
     std::sort(cand.begin(), cand.end());  // slots in column order
     const int T = (int)cand.size(), ldT = (T + 3) / 4 * 4;

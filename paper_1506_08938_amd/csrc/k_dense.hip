@@ -304,14 +304,71 @@ hipError_t launch_to_bf16_t(const float *x, int64_t rows, int64_t cols, int64_t 
 }
 
 // P = sum over split-K slices in slice order
+// The split-K sum of one entry, in a fixed order: slices in groups of
+// SPLIT_GROUP, each group summed in slice order, the group sums added in
+// group order.  (Up to SPLIT_GROUP slices this is the plain slice-order sum.)
+constexpr int SPLIT_GROUP = 8;
+
+__device__ __forceinline__ float split_sum(const float *__restrict__ part, int nsplit, int64_t n,
+                                           int64_t i) {
+    float s = 0.f;
+    for (int g0 = 0; g0 < nsplit; g0 += SPLIT_GROUP) {
+        float gs = 0.f;
+        const int g1 = min(nsplit, g0 + SPLIT_GROUP);
+        for (int k = g0; k < g1; k++) gs += part[(int64_t)k * n + i];
+        s += gs;
+    }
+    return s;
+}
+
 __global__ void k_split_reduce(const float *__restrict__ part, int nsplit, int64_t n,
                                float *__restrict__ P) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        P[i] = split_sum(part, nsplit, n, i);
+}
+
+// Many slices: the same sum in two parallel passes.  Pass 1 writes each
+// group's sum over the group's first slice (in place: a group is read and
+// written by one thread per entry), pass 2 adds the group sums in order.
+__global__ void k_split_groups(float *__restrict__ part, int nsplit, int64_t n) {
+    const int ng = (nsplit + SPLIT_GROUP - 1) / SPLIT_GROUP;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * ng;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int g = (int)(e / n);
+        const int64_t i = e - (int64_t)g * n;
+        const int g0 = g * SPLIT_GROUP, g1 = min(nsplit, g0 + SPLIT_GROUP);
+        float gs = 0.f;
+        for (int k = g0; k < g1; k++) gs += part[(int64_t)k * n + i];
+        part[(int64_t)g0 * n + i] = gs;
+    }
+}
+
+__global__ void k_split_final(const float *__restrict__ part, int nsplit, int64_t n,
+                              float *__restrict__ P) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         float s = 0.f;
-        for (int k = 0; k < nsplit; k++) s += part[(int64_t)k * n + i];
+        for (int g0 = 0; g0 < nsplit; g0 += SPLIT_GROUP) s += part[(int64_t)g0 * n + i];
         P[i] = s;
     }
+}
+
+static hipError_t launch_split_reduce(float *part, int nsplit, int64_t n, float *P, hipStream_t s) {
+    if (nsplit <= 4 * SPLIT_GROUP) {
+        int64_t blocks = (n + 255) / 256;
+        if (blocks > 4096) blocks = 4096;
+        hipLaunchKernelGGL(k_split_reduce, dim3((unsigned)blocks), dim3(256), 0, s, part, nsplit, n, P);
+        return hipGetLastError();
+    }
+    const int64_t ng = (nsplit + SPLIT_GROUP - 1) / SPLIT_GROUP;
+    int64_t b1 = (n * ng + 255) / 256;
+    if (b1 > 16384) b1 = 16384;
+    hipLaunchKernelGGL(k_split_groups, dim3((unsigned)b1), dim3(256), 0, s, part, nsplit, n);
+    int64_t b2 = (n + 255) / 256;
+    if (b2 > 4096) b2 = 4096;
+    hipLaunchKernelGGL(k_split_final, dim3((unsigned)b2), dim3(256), 0, s, part, nsplit, n, P);
+    return hipGetLastError();
 }
 
 __global__ void k_to_bf16(const float *__restrict__ x, int64_t rows, int64_t cols, int64_t ld,
@@ -434,12 +491,7 @@ hipError_t launch_dense_product(const void *V, int bf16, int64_t m, int64_t n, i
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || nsplit <= 1) return e;
-    const int64_t nel = C * r;
-    int64_t blocks = (nel + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_split_reduce, dim3((unsigned)blocks), dim3(256), 0, s, scratch, nsplit,
-                       nel, P);
-    return hipGetLastError();
+    return launch_split_reduce(scratch, nsplit, C * r, P, s);
 }
 
 }  // namespace nmfi
@@ -483,17 +535,14 @@ __global__ __launch_bounds__(256) void k_bfactor_t16(const BItem *__restrict__ i
     factor_t16_body(P.A, P.K, P.r, (P.r + 31) / 32 * 32, P.A16, P.lda16, (int64_t)it.idx * 64, tile);
 }
 
-// split-K sums of many problems, the same loop as k_split_reduce
+// split-K sums of many problems, in the same order as the single-problem sum
 __global__ void k_bsplit_reduce(const BItem *__restrict__ items, const BProdProb *__restrict__ probs) {
     const BItem it = items[blockIdx.x];
     const BProdProb P = probs[it.prob];
     const int64_t n = P.C * P.r;
     const int64_t e0 = (int64_t)it.idx * 4096;
-    for (int64_t i = e0 + threadIdx.x; i < min(n, e0 + 4096); i += blockDim.x) {
-        float s = 0.f;
-        for (int k = 0; k < P.nsplit; k++) s += P.part[(int64_t)k * n + i];
-        P.P[i] = s;
-    }
+    for (int64_t i = e0 + threadIdx.x; i < min(n, e0 + 4096); i += blockDim.x)
+        P.P[i] = split_sum(P.part, P.nsplit, n, i);
 }
 
 hipError_t launch_bdense(const BItem *items, int64_t nitems, const BProdProb *probs, int ntmax,
