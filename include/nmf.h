@@ -252,7 +252,9 @@ NMF_API void nmf_basis_destroy(nmf_basis *B);
  * from the head of the arrival-ordered queue while the HBM footprint of the
  * admitted work stays within hbm_budget bytes, packing consecutive fold-in
  * requests (up to max_batch_cols columns) into one batch with a single solve
- * launch; a fit request runs alone on its slot.  Requests arriving while
+ * launch; a fit request runs alone on its slot, and fits hold at most
+ * max_slots - 1 slots (fold-in requests queued behind a waiting fit go
+ * ahead of it).  Requests arriving while
  * others run are picked up by the next free slot, so batches overlap on the
  * device.  A request's result does not depend on what it is batched with.
  * Request memory is the caller's (device pointers): its inputs must be

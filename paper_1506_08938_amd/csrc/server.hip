@@ -3,7 +3,9 @@
 //
 // Each of `max_slots` worker threads owns a HIP stream (default priority).
 // Requests queue in arrival order; a free worker admits from the head of the
-// queue while the HBM footprint of the admitted work stays within the budget:
+// queue (fit requests hold at most max_slots - 1 slots: one stays free for
+// fold-ins, which pass a fit that has to wait) while the HBM footprint of the
+// admitted work stays within the budget:
 // consecutive fold-in requests (up to max_batch_cols columns) become one
 // batch -- one product launch per request, then ONE solve launch over all of
 // the batch's columns -- and a full-fit request runs alone on its slot.
@@ -52,6 +54,8 @@ struct nmf_server {
     const nmf_basis *B = nullptr;
     size_t budget = 0, in_use = 0;
     int64_t max_cols = 0;
+    int max_fits = 1;      // fit requests running at once: one slot stays free for fold-ins
+    int fits_running = 0;
     int device = 0;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -140,30 +144,44 @@ void worker(nmf_server *S) {
     for (;;) {
         std::vector<std::shared_ptr<Req>> batch;
         size_t fp = 0;
+        bool is_fit = false;
         {
             std::unique_lock<std::mutex> lk(S->mu);
+            // The first request this worker may start: the head of the queue,
+            // except that a fit request waits while max_fits fits run, and the
+            // fold-in requests queued behind it go ahead meanwhile.
+            auto first = [&]() -> std::deque<std::shared_ptr<Req>>::iterator {
+                for (auto it = S->queue.begin(); it != S->queue.end(); ++it) {
+                    if ((*it)->q.kind == NMF_REQ_FIT && S->fits_running >= S->max_fits) continue;
+                    return it;
+                }
+                return S->queue.end();
+            };
             S->cv_work.wait(lk, [&] {
                 if (S->stop && S->queue.empty()) return true;
-                return !S->queue.empty() && S->in_use + S->queue.front()->footprint <= S->budget;
+                auto it = first();
+                return it != S->queue.end() && S->in_use + (*it)->footprint <= S->budget;
             });
             if (S->queue.empty()) break;  // stopping
-            // admit from the head, in arrival order
-            auto head = S->queue.front();
-            if (head->q.kind == NMF_REQ_FIT) {
-                batch.push_back(head);
-                fp = head->footprint;
-                S->queue.pop_front();
+            auto it = first();
+            if ((*it)->q.kind == NMF_REQ_FIT) {
+                batch.push_back(*it);
+                fp = (*it)->footprint;
+                S->queue.erase(it);
+                is_fit = true;
+                S->fits_running++;
             } else {
+                // consecutive fold-in requests from there, in arrival order
                 int64_t cols = 0;
-                while (!S->queue.empty()) {
-                    auto &q = S->queue.front();
+                while (it != S->queue.end()) {
+                    auto &q = *it;
                     if (q->q.kind != NMF_REQ_FOLDIN) break;
                     if (!batch.empty() && cols + req_cols(q->q) > S->max_cols) break;
                     if (S->in_use + fp + q->footprint > S->budget) break;
                     cols += req_cols(q->q);
                     fp += q->footprint;
                     batch.push_back(q);
-                    S->queue.pop_front();
+                    it = S->queue.erase(it);
                 }
             }
             S->in_use += fp;
@@ -176,6 +194,7 @@ void worker(nmf_server *S) {
         {
             std::lock_guard<std::mutex> lk(S->mu);
             S->in_use -= fp;
+            if (is_fit) S->fits_running--;
             S->batches++;
             for (auto &q : batch) {
                 q->state = 2;
@@ -205,6 +224,7 @@ extern "C" int nmf_server_create(const nmf_basis *B, size_t hbm_budget, int32_t 
     S->B = B;
     S->budget = hbm_budget;
     S->max_cols = max_batch_cols;
+    S->max_fits = max_slots > 1 ? max_slots - 1 : 1;
     if (hipGetDevice(&S->device) != hipSuccess) S->device = 0;
     for (int i = 0; i < max_slots; i++) S->workers.emplace_back(worker, S);
     *out = S;
