@@ -3,8 +3,9 @@
 //
 // Mapping.  L lanes (1, 2, 4, 8 or 16: a DPP quad, half-row or row)
 // cooperate on one column; lane `sub` of the group owns the E contiguous
-// coordinates [sub*E, sub*E + E) of the padded rank R = E*L.  The rescaled Hessian Q
-// (unit diagonal) sits in LDS, row-major with stride SQ; because Q is
+// coordinates [sub*E, sub*E + E) of the padded rank R = E*L.  The rescaled
+// Hessian Q (unit diagonal) sits in LDS (QLayout: row stride SQ, each lane's
+// segment of a row padded to a multiple of four floats); because Q is
 // symmetric, both the matrix-vector products and the coordinate-descent
 // gradient update read one row segment per lane: Q[j][sub*E .. sub*E+E).
 // Group reductions (sums, the greedy argmax) are DPP butterflies, so every
@@ -99,9 +100,27 @@ __device__ __forceinline__ double grp_sum_d(double v) {
     return v;
 }
 
+#ifndef NMF_NQP_ARGMAX64
+#define NMF_NQP_ARGMAX64 1  // 1: one 64-bit key compare per step (no branches)
+#endif
+
 // (best, idx, m) <- the entry with the largest best; lowest idx on ties.
+// best >= 0 (a decrease), so its bit pattern orders like its value (after
+// clearing the sign of a -0); the key (bits(best), ~idx) compares as one
+// 64-bit unsigned integer: larger best first, then the lower index.
 template <int CTRL>
 __device__ __forceinline__ void argmax_step(float &best, int &idx, float &m) {
+#if NMF_NQP_ARGMAX64
+    const unsigned hi = (unsigned)f2i(best) & 0x7fffffffu, lo = ~(unsigned)idx;
+    const unsigned ohi = (unsigned)dppi<CTRL>((int)hi), olo = (unsigned)dppi<CTRL>((int)lo);
+    const float om = dppf<CTRL>(m);
+    const unsigned long long k = ((unsigned long long)hi << 32) | lo;
+    const unsigned long long ok = ((unsigned long long)ohi << 32) | olo;
+    const bool take = ok > k;
+    best = i2f((int)(take ? ohi : hi));
+    idx = (int)~(take ? olo : lo);
+    m = take ? om : m;
+#else
     float ob = dppf<CTRL>(best);
     int oi = dppi<CTRL>(idx);
     float om = dppf<CTRL>(m);
@@ -109,6 +128,7 @@ __device__ __forceinline__ void argmax_step(float &best, int &idx, float &m) {
     best = take ? ob : best;
     idx = take ? oi : idx;
     m = take ? om : m;
+#endif
 }
 template <int L>
 __device__ __forceinline__ void grp_argmax(float &best, int &idx, float &m) {
@@ -118,20 +138,57 @@ __device__ __forceinline__ void grp_argmax(float &best, int &idx, float &m) {
     if constexpr (L >= 16) argmax_step<DPP_MIRROR>(best, idx, m);
 }
 
+#ifndef NMF_NQP_PADSEG
+#define NMF_NQP_PADSEG 1  // 1: lane segments of Q rows padded to 16 bytes (b128 reads)
+#endif
+
+// LDS layout of Q: row j (of R) at j * SQ; within a row, group member sub's
+// E entries start at sub * ES.  With ES a multiple of four every lane's
+// segment is 16-byte aligned and a row segment is read with 128-bit loads
+// at immediate offsets from one base address.
+template <int E, int L>
+struct QLayout {
+    static constexpr int R = E * L;
+    static constexpr int ES = NMF_NQP_PADSEG ? ((E + 3) & ~3) : E;
+    static constexpr int SQ = NMF_NQP_PADSEG ? L * ES + 4 : ((R + 3) & ~3) + 4;
+    __device__ static constexpr int col(int j) { return (j / E) * ES + (j % E); }
+};
+
+// the E entries of one lane's row segment
+template <int E, int ES>
+__device__ __forceinline__ void load_seg(const float *__restrict__ p, float (&x)[E]) {
+    if constexpr (ES % 4 == 0) {
+        float t[ES];
+#pragma unroll
+        for (int q = 0; q < ES / 4; q++) {
+            const float4 v = ((const float4 *)p)[q];
+            t[4 * q] = v.x; t[4 * q + 1] = v.y; t[4 * q + 2] = v.z; t[4 * q + 3] = v.w;
+        }
+#pragma unroll
+        for (int e = 0; e < E; e++) x[e] = t[e];
+    } else {
+#pragma unroll
+        for (int e = 0; e < E; e++) x[e] = p[e];
+    }
+}
+
 // out[e] = sum_j Q[sub*E + e][j] v_j for this lane's E rows; v is spread over
-// the group (entry j lives in member j / E).  qseg = &Q[0][sub*E].
-template <int E, int L, int SQ, int S = 0>
+// the group (entry j lives in member j / E).  qseg = this lane's segment of
+// row 0.
+template <int E, int L, int S = 0>
 __device__ __forceinline__ void matvec_acc(const float *__restrict__ qseg, const float (&v)[E],
                                            float (&out)[E]) {
+    using QL = QLayout<E, L>;
     if constexpr (S < L) {
 #pragma unroll
         for (int e2 = 0; e2 < E; e2++) {
             const float w = grp_bcast<L, S>(v[e2]);
-            const float *row = qseg + (S * E + e2) * SQ;  // Q symmetric: row j = column j
+            float row[E];
+            load_seg<E, QL::ES>(qseg + (S * E + e2) * QL::SQ, row);  // Q symmetric: row j = column j
 #pragma unroll
             for (int e = 0; e < E; e++) out[e] = fmaf(row[e], w, out[e]);
         }
-        matvec_acc<E, L, SQ, S + 1>(qseg, v, out);
+        matvec_acc<E, L, S + 1>(qseg, v, out);
     }
 }
 // The rescaled Hessian in LDS never changes inside the kernel, so without a
@@ -139,13 +196,13 @@ __device__ __forceinline__ void matvec_acc(const float *__restrict__ qseg, const
 // keep R*E of them in registers.  The fence makes every use reload it.
 __device__ __forceinline__ void lds_reload_fence() { asm volatile("" ::: "memory"); }
 
-template <int E, int L, int SQ>
+template <int E, int L>
 __device__ __forceinline__ void matvec(const float *__restrict__ qseg, const float (&v)[E],
                                        float (&out)[E]) {
     lds_reload_fence();
 #pragma unroll
     for (int e = 0; e < E; e++) out[e] = 0.f;
-    matvec_acc<E, L, SQ>(qseg, v, out);
+    matvec_acc<E, L>(qseg, v, out);
 }
 
 __device__ __forceinline__ bool passive(float y, float g) { return y > 0.f || g < 0.f; }
@@ -168,16 +225,11 @@ __device__ __forceinline__ float relu(float a) {
 #define NMF_NQP_ONEHOT_LDS 0  // 0: compare/select (measured faster); 1: y update through the LDS unit vector
 #endif
 
-template <int R>
-constexpr int nqp_stride() {
-    return ((R + 3) & ~3) + 4;
-}
-
 // LDS of one block: Q (R x SQ), sqrt-diagonal (R), unit-vector window (2R),
 // and a few counters
-template <int R>
+template <int E, int L>
 constexpr int nqp_lds_bytes() {
-    return (R * nqp_stride<R>() + 3 * R) * 4 + 64;
+    return (E * L * QLayout<E, L>::SQ + 3 * E * L) * 4 + 64;
 }
 
 template <int E>
@@ -200,7 +252,7 @@ constexpr int nqp_block() {
 template <int E, int L>
 constexpr int nqp_waves_per_eu() {
     constexpr int by_regs = nqp_regs_waves<E>();
-    constexpr int by_lds = (160 * 1024) / nqp_lds_bytes<E * L>() * (nqp_block<E, L>() / 256);
+    constexpr int by_lds = (160 * 1024) / nqp_lds_bytes<E, L>() * (nqp_block<E, L>() / 256);
     return by_regs < by_lds ? by_regs : (by_lds > 0 ? by_lds : 1);
 }
 
@@ -242,7 +294,7 @@ struct LdsFetch {
 // sZ (LDS, 2R floats) holds a single 1 at index R: sZ + R + base - p is this
 // lane's segment of the unit vector e_p, so the coordinate-descent update of y
 // is one FMA per entry, fma(-m, 1, y) = y - m at p and y elsewhere.
-template <int E, int L, int SQ, class Fetch>
+template <int E, int L, class Fetch>
 __device__ __forceinline__ void nqp_columns(const float *__restrict__ sQ,
                                             const float *__restrict__ sD,
                                             const float *__restrict__ sZ, const ColumnIO &a,
@@ -250,7 +302,8 @@ __device__ __forceinline__ void nqp_columns(const float *__restrict__ sQ,
     const int lane = threadIdx.x & 63;
     const int sub = lane & (L - 1);
     const int base = sub * E;
-    const float *qseg = sQ + base;
+    using QL = QLayout<E, L>;
+    const float *qseg = sQ + sub * QL::ES;
     const int r = a.r;
 
     float y[E], g[E];
@@ -299,7 +352,7 @@ __device__ __forceinline__ void nqp_columns(const float *__restrict__ sQ,
                         q[e] = ds > 0.f ? hv / ds : 1.f;
                     }
                     float u[E];
-                    matvec<E, L, SQ>(qseg, y, u);
+                    matvec<E, L>(qseg, y, u);
                     double nl = 0.0;
 #pragma unroll
                     for (int e = 0; e < E; e++) {
@@ -326,7 +379,7 @@ __device__ __forceinline__ void nqp_columns(const float *__restrict__ sQ,
             }
             const float s = grp_sum<L>(sl);
             if (s > 0.f) {
-                matvec<E, L, SQ>(qseg, gb, u);
+                matvec<E, L>(qseg, gb, u);
                 float dl = 0.f;
 #pragma unroll
                 for (int e = 0; e < E; e++) dl = fmaf(gb[e], u[e], dl);
@@ -335,7 +388,7 @@ __device__ __forceinline__ void nqp_columns(const float *__restrict__ sQ,
                     const float alpha = s / den;
 #pragma unroll
                     for (int e = 0; e < E; e++) gb[e] = relu(fmaf(-alpha, gb[e], y[e])) - y[e];
-                    matvec<E, L, SQ>(qseg, gb, u);
+                    matvec<E, L>(qseg, gb, u);
                     bool accept = true;
                     if (a.ls_guard) {
                         float gl = 0.f;
@@ -382,7 +435,8 @@ __device__ __forceinline__ void nqp_columns(const float *__restrict__ sQ,
                 if (!__ballot(go)) break;
                 lds_reload_fence();
                 if (go) {
-                    const float *row = qseg + bi * SQ;
+                    float row[E];
+                    load_seg<E, QL::ES>(qseg + bi * QL::SQ, row);
                     const float *onehot = sZ + (E * L) + base - bi;
 #pragma unroll
                     for (int e = 0; e < E; e++) g[e] = fmaf(-bm, row[e], g[e]);
@@ -430,9 +484,11 @@ __device__ __forceinline__ void nqp_columns(const float *__restrict__ sQ,
 // and for the pads r <= i < R); sQ[i][j] = Gamma_ij / (sD[i] sD[j]) with a
 // unit diagonal, zero rows/columns off the diagonal for frozen or pad
 // coordinates.  Every block forms the same Q from the same Gamma.
-template <int R, int SQ>
+template <int E, int L>
 __device__ __forceinline__ void stage_q(const float *__restrict__ gram, int r, float *sQ,
                                         float *sD, float *sZ) {
+    using QL = QLayout<E, L>;
+    constexpr int R = E * L;
     for (int t = threadIdx.x; t < 2 * R; t += blockDim.x) sZ[t] = t == R ? 1.f : 0.f;
     for (int i = threadIdx.x; i < R; i += blockDim.x) {
         const float d = i < r ? gram[(size_t)i * r + i] : 0.f;
@@ -445,7 +501,7 @@ __device__ __forceinline__ void stage_q(const float *__restrict__ gram, int r, f
         if (i == j) v = 1.f;
         else if (i >= r || j >= r || sD[i] == 0.f || sD[j] == 0.f) v = 0.f;
         else v = gram[(size_t)i * r + j] / (sD[i] * sD[j]);
-        sQ[i * SQ + j] = v;
+        sQ[i * QL::SQ + QL::col(j)] = v;
     }
 }
 
@@ -459,17 +515,16 @@ template <int E, int L>
 __global__ __launch_bounds__((nqp_block<E, L>()))
 __attribute__((amdgpu_waves_per_eu(nqp_waves_per_eu<E, L>(), 8))) void k_nqp(const NqpParams a) {
     constexpr int R = E * L;
-    constexpr int SQ = nqp_stride<R>();
-    __shared__ float sQ[R * SQ];
+    __shared__ __attribute__((aligned(16))) float sQ[R * QLayout<E, L>::SQ];
     __shared__ float sD[R];
     __shared__ float sZ[2 * R];
-    stage_q<R, SQ>(a.gram, a.r, sQ, sD, sZ);
+    stage_q<E, L>(a.gram, a.r, sQ, sD, sZ);
     __syncthreads();
     ColumnIO io{a.P, a.hsign, a.hadd, a.X, a.ldp, a.ldx, a.iters, a.r, a.max_inner, a.eps,
                 a.ls_guard, a.cold};
     GlobalFetch f{a.counter, a.ncols};
     unsigned long long my_inner = 0;
-    nqp_columns<E, L, SQ>(sQ, sD, sZ, io, f, my_inner);
+    nqp_columns<E, L>(sQ, sD, sZ, io, f, my_inner);
     flush_inner(my_inner, a.inner_total);
 }
 
@@ -483,8 +538,7 @@ __attribute__((amdgpu_waves_per_eu(nqp_waves_per_eu<E, L>(), 8))) void k_bnqp(
     const BSolveChunk *__restrict__ chunks, int nchunks, unsigned int *queue,
     const BSolveProb *__restrict__ probs, int max_inner, double eps, int ls_guard) {
     constexpr int R = E * L;
-    constexpr int SQ = nqp_stride<R>();
-    __shared__ float sQ[R * SQ];
+    __shared__ __attribute__((aligned(16))) float sQ[R * QLayout<E, L>::SQ];
     __shared__ float sD[R];
     __shared__ float sZ[2 * R];
     __shared__ unsigned int s_task, s_ctr;
@@ -498,13 +552,13 @@ __attribute__((amdgpu_waves_per_eu(nqp_waves_per_eu<E, L>(), 8))) void k_bnqp(
         if (t >= (unsigned int)nchunks) break;
         const BSolveChunk ch = chunks[t];
         const BSolveProb P = probs[ch.prob];
-        stage_q<R, SQ>(P.G, P.r, sQ, sD, sZ);
+        stage_q<E, L>(P.G, P.r, sQ, sD, sZ);
         __syncthreads();
         ColumnIO io{P.P + (int64_t)ch.c0 * P.r, -1.f, P.l1, P.X + (int64_t)ch.c0 * P.r, P.r, P.r,
                     P.iters ? P.iters + ch.c0 : nullptr, P.r, max_inner, eps, ls_guard, P.cold};
         LdsFetch f{&s_ctr, (int64_t)(ch.c1 - ch.c0)};
         unsigned long long my_inner = 0;
-        nqp_columns<E, L, SQ>(sQ, sD, sZ, io, f, my_inner);
+        nqp_columns<E, L>(sQ, sD, sZ, io, f, my_inner);
         flush_inner(my_inner, P.inner);
         __syncthreads();
     }
