@@ -24,8 +24,8 @@ import os
 import sys
 import time
 
-RANKS = [4, 8, 16, 24, 32, 48, 64, 80, 100, 128]
-COLS = [256, 1024, 4096, 16384, 65536, 262144]
+RANKS = [4, 8, 12, 16, 20, 24, 32, 40, 48, 56, 64, 72, 80, 90, 100, 112, 128]
+COLS = [256, 1024, 4096, 16384, 32768, 65536, 131072, 262144]
 LANES = [1, 2, 4, 8, 16]
 REPS = 5
 

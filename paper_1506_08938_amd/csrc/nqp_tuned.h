@@ -5,20 +5,27 @@
 
 namespace nmfi {
 
-constexpr int kTunedRanks[] = {4, 8, 16, 24, 32, 48, 64, 80, 100, 128};
-constexpr long long kTunedCols[] = {256, 1024, 4096, 16384, 65536, 262144};
+constexpr int kTunedRanks[] = {4, 8, 12, 16, 20, 24, 32, 40, 48, 56, 64, 72, 80, 90, 100, 112, 128};
+constexpr long long kTunedCols[] = {256, 1024, 4096, 16384, 32768, 65536, 131072, 262144};
 // [rank index][column index]
-constexpr int kTunedLanes[10][6] = {
-    {16, 8, 2, 1, 1, 1},
-    {8, 8, 4, 2, 1, 1},
-    {16, 16, 8, 4, 2, 1},
-    {8, 16, 8, 4, 2, 2},
-    {16, 16, 16, 8, 4, 2},
-    {16, 16, 16, 8, 4, 4},
-    {16, 16, 16, 8, 8, 4},
-    {16, 16, 16, 16, 8, 8},
-    {16, 16, 16, 16, 8, 4},
-    {16, 16, 16, 16, 16, 8},
+constexpr int kTunedLanes[17][8] = {
+    {16, 2, 2, 1, 1, 1, 1, 1},
+    {4, 4, 4, 4, 2, 1, 1, 1},
+    {8, 8, 8, 2, 2, 2, 1, 1},
+    {16, 8, 8, 4, 2, 2, 2, 1},
+    {16, 16, 8, 4, 4, 2, 1, 1},
+    {16, 16, 8, 4, 4, 4, 2, 2},
+    {16, 16, 16, 4, 4, 4, 2, 2},
+    {16, 16, 16, 8, 4, 4, 4, 2},
+    {16, 16, 16, 8, 8, 4, 4, 4},
+    {16, 16, 16, 8, 8, 8, 4, 4},
+    {16, 16, 16, 16, 8, 8, 4, 4},
+    {16, 16, 16, 8, 8, 4, 4, 4},
+    {16, 16, 16, 8, 8, 8, 8, 4},
+    {16, 16, 16, 16, 8, 16, 8, 8},
+    {16, 16, 16, 16, 16, 8, 8, 4},
+    {16, 16, 16, 16, 16, 16, 16, 4},
+    {16, 16, 16, 16, 16, 16, 8, 8},
 };
 
 }  // namespace nmfi
