@@ -130,38 +130,73 @@ __device__ __forceinline__ void argmax_step(float &best, int &idx, float &m) {
     m = take ? om : m;
 #endif
 }
+#if NMF_NQP_ARGMAX64
+// one butterfly step on the key halves (hi = bits of the decrease, lo = ~index)
+template <int CTRL>
+__device__ __forceinline__ void argmax_key_step(unsigned &hi, unsigned &lo, float &m) {
+    const unsigned ohi = (unsigned)dppi<CTRL>((int)hi), olo = (unsigned)dppi<CTRL>((int)lo);
+    const float om = dppf<CTRL>(m);
+    const bool take = (((unsigned long long)ohi << 32) | olo) > (((unsigned long long)hi << 32) | lo);
+    hi = take ? ohi : hi;
+    lo = take ? olo : lo;
+    m = take ? om : m;
+}
+#endif
+
 template <int L>
 __device__ __forceinline__ void grp_argmax(float &best, int &idx, float &m) {
+#if NMF_NQP_ARGMAX64
+    if constexpr (L >= 2) {
+        // the key is formed once, carried through every step, and unpacked once
+        unsigned hi = (unsigned)f2i(best) & 0x7fffffffu, lo = ~(unsigned)idx;
+        argmax_key_step<DPP_XOR1>(hi, lo, m);
+        if constexpr (L >= 4) argmax_key_step<DPP_XOR2>(hi, lo, m);
+        if constexpr (L >= 8) argmax_key_step<DPP_HALF_MIRROR>(hi, lo, m);
+        if constexpr (L >= 16) argmax_key_step<DPP_MIRROR>(hi, lo, m);
+        best = i2f((int)hi);
+        idx = (int)~lo;
+    }
+#else
     if constexpr (L >= 2) argmax_step<DPP_XOR1>(best, idx, m);
     if constexpr (L >= 4) argmax_step<DPP_XOR2>(best, idx, m);
     if constexpr (L >= 8) argmax_step<DPP_HALF_MIRROR>(best, idx, m);
     if constexpr (L >= 16) argmax_step<DPP_MIRROR>(best, idx, m);
+#endif
 }
 
 #ifndef NMF_NQP_PADSEG
 #define NMF_NQP_PADSEG 1  // 1: lane segments of Q rows padded to 16 bytes (b128 reads)
 #endif
 
-// LDS layout of Q: row j (of R) at j * SQ; within a row, group member sub's
-// E entries start at sub * ES.  With ES a multiple of four every lane's
-// segment is 16-byte aligned and a row segment is read with 128-bit loads
-// at immediate offsets from one base address.
+// LDS layout of Q: row j (of R) at j * SQ.  Padded form: group member sub's
+// E entries, padded to ES (a multiple of four), are stored as ES/4 float4
+// blocks interleaved across the group -- block q of member sub at
+// (q * L + sub) * 4 -- so one 128-bit load per block q reads a contiguous
+// run of the row across the group's lanes (no bank conflicts) at an
+// immediate offset from one base address.  Plain form: member sub's entries
+// contiguous at sub * E.
 template <int E, int L>
 struct QLayout {
     static constexpr int R = E * L;
     static constexpr int ES = NMF_NQP_PADSEG ? ((E + 3) & ~3) : E;
     static constexpr int SQ = NMF_NQP_PADSEG ? L * ES + 4 : ((R + 3) & ~3) + 4;
-    __device__ static constexpr int col(int j) { return (j / E) * ES + (j % E); }
+    // this member's first entry in row 0
+    __device__ static constexpr int seg(int sub) { return NMF_NQP_PADSEG ? sub * 4 : sub * E; }
+    // position of entry j within a row
+    __device__ static constexpr int col(int j) {
+        return NMF_NQP_PADSEG ? ((j % E) / 4 * L + j / E) * 4 + (j % E) % 4 : j;
+    }
 };
 
-// the E entries of one lane's row segment
-template <int E, int ES>
+// the E entries of one lane's row segment, starting at p = row + seg(sub)
+template <int E, int L>
 __device__ __forceinline__ void load_seg(const float *__restrict__ p, float (&x)[E]) {
-    if constexpr (ES % 4 == 0) {
+    if constexpr (NMF_NQP_PADSEG) {
+        constexpr int ES = QLayout<E, L>::ES;
         float t[ES];
 #pragma unroll
         for (int q = 0; q < ES / 4; q++) {
-            const float4 v = ((const float4 *)p)[q];
+            const float4 v = *(const float4 *)(p + q * L * 4);
             t[4 * q] = v.x; t[4 * q + 1] = v.y; t[4 * q + 2] = v.z; t[4 * q + 3] = v.w;
         }
 #pragma unroll
@@ -184,7 +219,7 @@ __device__ __forceinline__ void matvec_acc(const float *__restrict__ qseg, const
         for (int e2 = 0; e2 < E; e2++) {
             const float w = grp_bcast<L, S>(v[e2]);
             float row[E];
-            load_seg<E, QL::ES>(qseg + (S * E + e2) * QL::SQ, row);  // Q symmetric: row j = column j
+            load_seg<E, L>(qseg + (S * E + e2) * QL::SQ, row);  // Q symmetric: row j = column j
 #pragma unroll
             for (int e = 0; e < E; e++) out[e] = fmaf(row[e], w, out[e]);
         }
@@ -303,7 +338,7 @@ __device__ __forceinline__ void nqp_columns(const float *__restrict__ sQ,
     const int sub = lane & (L - 1);
     const int base = sub * E;
     using QL = QLayout<E, L>;
-    const float *qseg = sQ + sub * QL::ES;
+    const float *qseg = sQ + QL::seg(sub);
     const int r = a.r;
 
     float y[E], g[E];
@@ -436,7 +471,7 @@ __device__ __forceinline__ void nqp_columns(const float *__restrict__ sQ,
                 lds_reload_fence();
                 if (go) {
                     float row[E];
-                    load_seg<E, QL::ES>(qseg + bi * QL::SQ, row);
+                    load_seg<E, L>(qseg + bi * QL::SQ, row);
                     const float *onehot = sZ + (E * L) + base - bi;
 #pragma unroll
                     for (int e = 0; e < E; e++) g[e] = fmaf(-bm, row[e], g[e]);
@@ -445,8 +480,9 @@ __device__ __forceinline__ void nqp_columns(const float *__restrict__ sQ,
                     for (int e = 0; e < E; e++) y[e] = fmaf(-bm, onehot[e], y[e]);
 #else
                     (void)onehot;
+                    const int el = bi - base;  // the step's coordinate in this lane's segment, if any
 #pragma unroll
-                    for (int e = 0; e < E; e++) y[e] = (base + e == bi) ? y[e] - bm : y[e];
+                    for (int e = 0; e < E; e++) y[e] = (el == e) ? y[e] - bm : y[e];
 #endif
                 }
             }
