@@ -39,32 +39,36 @@ struct DenseCfg<true> {
     static constexpr int VEC = 8;
 };
 
-// LDS layout of one stage buffer.
-//   FP32: Xs[BK][BM + 4] (k-major: a lane's MFMA operand is one float and the
-//         32 lanes of a half-wave read 32 consecutive rows of P), As[BK][R32 + 4].
-//   BF16: Xs[BM][BK + 8], As[R32][BK + 8] (row-major in k: a lane's operand is
-//         eight consecutive k, one 16-byte read; the 144-byte pitch spreads
-//         the 32 rows of a half-wave over all banks).
-template <bool BF16, int NT>
+// LDS layout of one stage buffer: one row per row of P (Xs) and per column of
+// P (As), k along the row.
+//   FP32: Xs[BM][BK + 4], As[R32][BK + 4], the 32 k of a stage stored
+//         even k first, then odd k (position perm(k) = (k % 2) * 16 + k / 2):
+//         the 32x32x2 MFMA's lanes 0-31 take the even k and lanes 32-63 the
+//         odd k of each pair, so a lane's sixteen operands of a stage are 16
+//         consecutive floats -- four 128-bit reads; the 144-byte pitch spreads
+//         16 lanes' rows over all banks.
+//   BF16: Xs[BM][BK + 8], As[R32][BK + 8] (a lane's operand is eight
+//         consecutive k, one 16-byte read; the 144-byte pitch spreads the 32
+//         rows of a half-wave over all banks).
+//   FP32 with X = V' (XT): Xs[BK][BM + 4] instead (k-major, as V's rows
+//         arrive: 16-byte stores; a lane reads its one-float operands per k).
+template <bool BF16, bool XT, int NT>
 struct DenseLds {
     static constexpr int BK = DenseCfg<BF16>::BK;
     static constexpr int R32 = 32 * NT;
-    static constexpr int XP = BF16 ? BK + 8 : DENSE_BM + 4;    // pitch (elements)
-    static constexpr int AP = BF16 ? BK + 8 : R32 + 4;
-    static constexpr int X_ELEMS = BF16 ? DENSE_BM * XP : BK * XP;
-    static constexpr int A_ELEMS = BF16 ? R32 * AP : BK * AP;
+    static constexpr bool XKMAJOR = XT && !BF16;
+    static constexpr int XP = BF16 ? BK + 8 : (XKMAJOR ? DENSE_BM + 4 : BK + 4);  // pitch (elements)
+    static constexpr int AP = BF16 ? BK + 8 : BK + 4;
+    static constexpr int X_ELEMS = XKMAJOR ? BK * XP : DENSE_BM * XP;
+    static constexpr int A_ELEMS = R32 * AP;
     static constexpr int ESZ = BF16 ? 2 : 4;
     static constexpr int STAGE_BYTES = ((X_ELEMS + A_ELEMS) * ESZ + 15) & ~15;
     static constexpr int BYTES = 2 * STAGE_BYTES;
 };
 
-template <int NT>
-constexpr int dense_lds_bytes(bool bf16) {
-    return bf16 ? DenseLds<true, NT>::BYTES : DenseLds<false, NT>::BYTES;
-}
 
 // 128 rows of P = X A starting at row c0, summed over k in [kb, ke), written
-// to o (C x r).  lds: DenseLds<BF16, NT>::BYTES bytes, 16-byte aligned.
+// to o (C x r).  lds: DenseLds<BF16, XT, NT>::BYTES bytes, 16-byte aligned.
 // vec_ok: V's rows and base are 16-byte aligned (ld * sizeof(T) % 16 == 0).
 // A16 (BF16 mode): the factor as BF16, transposed, R32 x lda16 (row j holds
 // A[., j]); unused in FP32 mode, where A (k x r float32) is read directly.
@@ -77,7 +81,7 @@ __device__ __forceinline__ void dense_body(const void *__restrict__ Vv, int64_t 
     static_assert(!(BF16 && XT), "BF16 products read X along k");
     using Cfg = DenseCfg<BF16>;
     using T = typename Cfg::T;
-    using L = DenseLds<BF16, NT>;
+    using L = DenseLds<BF16, XT, NT>;
     constexpr int BK = Cfg::BK, VEC = Cfg::VEC, R32 = 32 * NT, BM = DENSE_BM;
     // X tile: 1024 16-byte chunks, four per thread
     constexpr int XCH = 4;
@@ -150,6 +154,8 @@ __device__ __forceinline__ void dense_body(const void *__restrict__ Vv, int64_t 
     auto store_stage = [&](char *buf) {
         T *Xs = (T *)buf;
         T *As = (T *)(buf + L::X_ELEMS * L::ESZ);
+        // FP32 position of stage-local k within a row
+        auto perm = [](int k) { return (k & 1) * 16 + (k >> 1); };
 #pragma unroll
         for (int u = 0; u < XCH; u++) {
             const int q = tid + 256 * u;
@@ -162,9 +168,12 @@ __device__ __forceinline__ void dense_body(const void *__restrict__ Vv, int64_t 
                 const int rr = q / CPR, kk = (q % CPR) * VEC;
                 if constexpr (BF16) {  // Xs[c][k]
                     *(tvec *)(Xs + rr * L::XP + kk) = xr[u];
-                } else {  // Xs[k][c]: transpose the four k of one c
-#pragma unroll
-                    for (int e = 0; e < VEC; e++) Xs[(kk + e) * L::XP + rr] = xr[u][e];
+                } else {  // k .. k+3 of one c (k % 4 == 0): evens and odds are pairs
+                    f32x2 ev, od;
+                    ev[0] = xr[u][0]; ev[1] = xr[u][2];
+                    od[0] = xr[u][1]; od[1] = xr[u][3];
+                    *(f32x2 *)(Xs + rr * L::XP + (kk >> 1)) = ev;
+                    *(f32x2 *)(Xs + rr * L::XP + 16 + (kk >> 1)) = od;
                 }
             }
         }
@@ -175,10 +184,11 @@ __device__ __forceinline__ void dense_body(const void *__restrict__ Vv, int64_t 
                 constexpr int CPR = BK / 8;
                 const int j = q / CPR, kk = (q % CPR) * 8;
                 *(bf16x8 *)(As + j * L::AP + kk) = ar16[u];
-            } else {  // As[k][j]
+            } else {  // the four j of one k, into four rows
                 constexpr int CPR = R32 / 4;
                 const int kk = q / CPR, j = (q % CPR) * 4;
-                *(f32x4a *)(As + kk * L::AP + j) = ar[u];
+#pragma unroll
+                for (int e = 0; e < 4; e++) As[(j + e) * L::AP + perm(kk)] = ar[u][e];
             }
         }
     };
@@ -202,14 +212,31 @@ __device__ __forceinline__ void dense_body(const void *__restrict__ Vv, int64_t 
                 }
             }
         } else {
+            // lane half h takes k = 2 kp + h: the sixteen floats at h * 16 of its row
+            const int h16 = 16 * (lane >> 5);
 #pragma unroll
-            for (int kp = 0; kp < BK / 2; kp++) {
-                const int kk = 2 * kp + (lane >> 5);
-                const float a_op = Xs[kk * L::XP + 32 * wave + (lane & 31)];
+            for (int half = 0; half < 2; half++) {  // kp in [8 half, 8 half + 8)
+                float a_op[8];
+                if constexpr (L::XKMAJOR) {
+#pragma unroll
+                    for (int e = 0; e < 8; e++)
+                        a_op[e] = Xs[(2 * (8 * half + e) + (lane >> 5)) * L::XP + 32 * wave + (lane & 31)];
+                } else {
+                    const f32x4a *pa = (const f32x4a *)(Xs + (32 * wave + (lane & 31)) * L::XP + h16 + 8 * half);
+                    const f32x4a a0 = pa[0], a1 = pa[1];
+#pragma unroll
+                    for (int e = 0; e < 4; e++) { a_op[e] = a0[e]; a_op[4 + e] = a1[e]; }
+                }
 #pragma unroll
                 for (int t = 0; t < NT; t++) {
-                    const float b_op = As[kk * L::AP + 32 * t + (lane & 31)];
-                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a_op, b_op, acc[t], 0, 0, 0);
+                    const f32x4a *pb = (const f32x4a *)(As + (32 * t + (lane & 31)) * L::AP + h16 + 8 * half);
+                    const f32x4a b0 = pb[0], b1 = pb[1];
+                    float b_op[8];
+#pragma unroll
+                    for (int e = 0; e < 4; e++) { b_op[e] = b0[e]; b_op[4 + e] = b1[e]; }
+#pragma unroll
+                    for (int kp = 0; kp < 8; kp++)
+                        acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a_op[kp], b_op[kp], acc[t], 0, 0, 0);
                 }
             }
         }
@@ -246,7 +273,7 @@ __global__ __launch_bounds__(256) void k_dense(const void *__restrict__ V, int64
                                                int64_t K, const float *__restrict__ A, int r,
                                                const __bf16 *__restrict__ A16, int64_t lda16,
                                                int64_t kchunk, int vec_ok, float *__restrict__ out) {
-    __shared__ __attribute__((aligned(16))) char lds[DenseLds<BF16, NT>::BYTES];
+    __shared__ __attribute__((aligned(16))) char lds[DenseLds<BF16, XT, NT>::BYTES];
     const int64_t kb = (int64_t)blockIdx.y * kchunk;
     dense_body<BF16, XT, NT>(V, ld, C, A, r, A16, lda16, (int64_t)blockIdx.x * DENSE_BM, kb,
                              min(K, kb + kchunk), vec_ok != 0, lds, out + (int64_t)blockIdx.y * C * r);
@@ -505,7 +532,7 @@ namespace nmfi {
 template <int NTMAX, bool XT, bool BF16>
 __global__ __launch_bounds__(256) void k_bdense(const BItem *__restrict__ items,
                                                 const BProdProb *__restrict__ probs) {
-    __shared__ __attribute__((aligned(16))) char lds[DenseLds<BF16, NTMAX>::BYTES];
+    __shared__ __attribute__((aligned(16))) char lds[DenseLds<BF16, XT, NTMAX>::BYTES];
     const BItem it = items[blockIdx.x];
     const BProdProb P = probs[it.prob];
     const int NT = (P.r + 31) / 32;
