@@ -148,15 +148,42 @@ __device__ __forceinline__ void gram_reduce_entry(const float *__restrict__ part
     G[(size_t)b * r + a] = s;
 }
 
+// The same sums as gram_reduce_entry, eight threads per entry: thread q of
+// an entry forms that entry's interleaved sum acc[q] (partials q, q + 8, ...
+// in order, then its tail partial), and the eight are combined in the same
+// fixed order.  32 entries per block, consecutive entries on consecutive
+// lanes (coalesced reads of each partial).
 template <int NT>
 __global__ __launch_bounds__(256) void k_gram_reduce(const float *__restrict__ partial, int nblocks,
                                                      int r, float l2, float *__restrict__ G,
                                                      unsigned long long *counter) {
     constexpr int NTILE = NT * (NT + 1) / 2;
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e == 0 && counter) *counter = 0ull;
-    if (e >= NTILE * 1024) return;
-    gram_reduce_entry<NT>(partial, nblocks, r, l2, G, e);
+    constexpr int N = NTILE * 1024;
+    __shared__ float sm[8][32];
+    const int el = threadIdx.x & 31, q = threadIdx.x >> 5;
+    const int e = blockIdx.x * 32 + el;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && counter) *counter = 0ull;
+    float a = 0.f;
+    if (e < N) {
+        const int full = nblocks / 8 * 8;
+        for (int pb = q; pb < full; pb += 8) a += partial[(size_t)pb * N + e];
+        if (full + q < nblocks) a += partial[(size_t)(full + q) * N + e];
+    }
+    sm[q][el] = a;
+    __syncthreads();
+    if (q != 0 || e >= N) return;
+    float s = ((sm[0][el] + sm[1][el]) + (sm[2][el] + sm[3][el])) +
+              ((sm[4][el] + sm[5][el]) + (sm[6][el] + sm[7][el]));
+    const int ti = e >> 10, rem = e & 1023, qq = rem >> 6, lane = rem & 63;
+    int ta, tb;
+    tile_of<NT>(ti, ta, tb);
+    const int i = 8 * (qq >> 2) + 4 * (lane >> 5) + (qq & 3), j = lane & 31;
+    const int ra = ta * 32 + i, cb = tb * 32 + j;
+    if (ra >= r || cb >= r) return;
+    if (ta == tb && ra > cb) return;  // the diagonal tile writes its upper half only
+    if (ra == cb) s += 2.f * l2;
+    G[(size_t)ra * r + cb] = s;
+    G[(size_t)cb * r + ra] = s;
 }
 
 // Blocks of BGRAM_ROWS rows (the batched fit uses the same blocks, so a
@@ -168,7 +195,7 @@ static hipError_t gram_t(const float *A, int64_t k, int r, float l2, float *G, f
     const int64_t nb = k > 0 ? (k + BGRAM_ROWS - 1) / BGRAM_ROWS : 1;
     hipLaunchKernelGGL((k_gram_partial<NT, PREC>), dim3((unsigned)nb), dim3(GRAM_BLOCK), 0, s, A, k,
                        r, (int64_t)BGRAM_ROWS, scratch);
-    hipLaunchKernelGGL((k_gram_reduce<NT>), dim3((NTILE * 1024 + 255) / 256), dim3(256), 0, s,
+    hipLaunchKernelGGL((k_gram_reduce<NT>), dim3((NTILE * 1024 + 31) / 32), dim3(256), 0, s,
                        scratch, (int)nb, r, l2, G, counter);
     return hipGetLastError();
 }

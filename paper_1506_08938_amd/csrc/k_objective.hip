@@ -178,7 +178,7 @@ __global__ __launch_bounds__(256) void k_sums(const float *__restrict__ x, int64
 // out[o] = sum_i in[i * stride + o] for o < width (single block, ordered)
 __global__ __launch_bounds__(256) void k_reduce_ordered(const double *__restrict__ in, int64_t count,
                                                         int width, double *__restrict__ out) {
-    for (int o = threadIdx.x; o < width; o += 256) {
+    for (int o = blockIdx.x * 256 + threadIdx.x; o < width; o += gridDim.x * 256) {
         double s = 0.0;
         for (int64_t i = 0; i < count; i++) s += in[i * width + o];
         out[o] = s;
@@ -297,7 +297,8 @@ static hipError_t gram64(const float *A, int64_t k, int r, double *partial, doub
     nb = (k + rpb - 1) / rpb;
     if (nb < 1) nb = 1;
     hipLaunchKernelGGL(k_gram64, dim3((unsigned)nb), dim3(256), 0, s, A, k, r, rpb, partial);
-    hipLaunchKernelGGL(k_reduce_ordered, dim3(1), dim3(256), 0, s, partial, nb, r * r, G);
+    hipLaunchKernelGGL(k_reduce_ordered, dim3((unsigned)((r * r + 255) / 256)), dim3(256), 0, s,
+                       partial, nb, r * r, G);
     return hipGetLastError();
 }
 

@@ -108,7 +108,7 @@ hipError_t launch_to_bf16(const float *x, int64_t rows, int64_t cols, int64_t ld
 struct BItem {
     int32_t prob, idx;
 };
-constexpr int BGRAM_ROWS = 512;  // rows of A per batched Gram work item
+constexpr int BGRAM_ROWS = 512;  // rows of A per Gram work item (solo and batched)
 struct BGramProb {
     const float *A;
     int64_t k;
