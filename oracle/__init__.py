@@ -58,6 +58,12 @@ def lib():
         L.oracle_nqp_batch.argtypes = [ctypes.c_int, ctypes.c_long, _d, _d, _d, ctypes.c_int,
                                        ctypes.c_double, ctypes.c_int, _i]
         L.oracle_nqp_batch.restype = ctypes.c_long
+        L.oracle_nqp_trace.argtypes = [ctypes.c_int, _d, _d, _d, ctypes.c_int, ctypes.c_double,
+                                       ctypes.c_int, _d]
+        L.oracle_nqp_trace.restype = ctypes.c_int
+        L.oracle_nqp_batch_faststop.argtypes = [ctypes.c_int, ctypes.c_long, _d, _d, _d, ctypes.c_int,
+                                                ctypes.c_double, ctypes.c_int, ctypes.c_long, _i, _d]
+        L.oracle_nqp_batch_faststop.restype = ctypes.c_long
         L.oracle_gram.argtypes = [ctypes.c_long, ctypes.c_int, _d, ctypes.c_double, _d]
         L.oracle_product_dense.argtypes = [ctypes.c_long, ctypes.c_long, _d, ctypes.c_int,
                                            ctypes.c_int, _d, _d]
@@ -122,6 +128,29 @@ def nqp_batch(H, h, x0, max_inner=100, eps=1e-3, ls_guard=1):
     lib().oracle_nqp_batch(r, ncols, _p(H), _p(h), _p(x), int(max_inner), float(eps),
                            int(ls_guard), _p(it, _i))
     return x, it
+
+
+def nqp_trace(H, h, x0, max_inner=100, eps=1e-3, ls_guard=1):
+    """Algorithm 3 on one problem, returning (x, iters, nk) with nk[k] =
+    ||f~_k||^2 for k = 0..iters (no fast-break)."""
+    H = _f64(H); h = _f64(h); x = _f64(x0).copy()
+    r = H.shape[0]
+    nk = np.full(max_inner + 1, np.nan)
+    k = lib().oracle_nqp_trace(r, _p(H), _p(h), _p(x), int(max_inner), float(eps), int(ls_guard),
+                               _p(nk))
+    return x, k, nk[:k + 1]
+
+
+def nqp_batch_faststop(H, h, x0, chunk, max_inner=100, eps=1e-3, ls_guard=1):
+    """Independent NQPs with Algorithm 3's fast-break over fixed chunks of
+    `chunk` consecutive columns.  Returns (x, iters, final ||f~||^2)."""
+    H = _f64(H); h = _f64(h); x = _f64(x0).copy()
+    ncols, r = h.shape
+    it = np.zeros(ncols, dtype=np.int32)
+    nk = np.zeros(ncols)
+    lib().oracle_nqp_batch_faststop(r, ncols, _p(H), _p(h), _p(x), int(max_inner), float(eps),
+                                    int(ls_guard), int(chunk), _p(it, _i), _p(nk))
+    return x, it, nk
 
 
 def gram(A, l2=0.0):

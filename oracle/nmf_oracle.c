@@ -113,8 +113,22 @@ static double quad_form_value(int r, const double *Q, const double *q, const dou
  * solution is unscaled, x = y / sqrt(diag H).
  * The fast-break test against a per-thread maxStop is not part of this
  * oracle: columns are solved independently. */
+/* Algorithm 3 with its optional fast-break: besides ||f~_k||^2 <= eps
+ * ||f~_0||^2 the loop also ends once ||f~_k||^2 <= max_stop (max_stop < 0:
+ * no fast-break).  nk_out (optional) gets the final ||f~_k||^2; nk_trace
+ * (optional, max_inner + 1 entries) gets ||f~_k||^2 for k = 0..iters. */
+static int nqp_core(int r, const double *H, const double *h, double *x, int max_inner, double eps,
+                    int ls_guard, int flags, double *fk, double max_stop, double *nk_out,
+                    double *nk_trace);
+
 int oracle_nqp_flags(int r, const double *H, const double *h, double *x, int max_inner, double eps,
                      int ls_guard, int flags, double *fk) {
+    return nqp_core(r, H, h, x, max_inner, eps, ls_guard, flags, fk, -1.0, NULL, NULL);
+}
+
+static int nqp_core(int r, const double *H, const double *h, double *x, int max_inner, double eps,
+                    int ls_guard, int flags, double *fk, double max_stop, double *nk_out,
+                    double *nk_trace) {
     double *Q = (double *)malloc(sizeof(double) * (size_t)r * r);
     double *buf = (double *)malloc(sizeof(double) * (size_t)r * 8);
     int *frozen = (int *)malloc(sizeof(int) * (size_t)r);
@@ -140,6 +154,8 @@ int oracle_nqp_flags(int r, const double *H, const double *h, double *x, int max
     }
     if (fk) fk[0] = quad_form_value(r, Q, q, y);
     double n0 = pg_norm2(r, y, g, frozen);
+    double nk = n0;
+    if (nk_trace) nk_trace[0] = n0;
 
     int k = 0;
     for (;;) {
@@ -198,9 +214,11 @@ int oracle_nqp_flags(int r, const double *H, const double *h, double *x, int max
             }
         }
         if (fk) fk[k] = quad_form_value(r, Q, q, y);
-        double nk = pg_norm2(r, y, g, frozen);
-        if (nk <= eps * n0 || k >= max_inner) break;
+        nk = pg_norm2(r, y, g, frozen);
+        if (nk_trace) nk_trace[k] = nk;
+        if (nk <= eps * n0 || nk <= max_stop || k >= max_inner) break;
     }
+    if (nk_out) *nk_out = nk;
     for (int i = 0; i < r; i++) x[i] = frozen[i] ? 0.0 : y[i] / d[i];
     free(Q); free(buf); free(frozen);
     return k;
@@ -222,6 +240,43 @@ long oracle_nqp_batch(int r, long ncols, const double *H, const double *h, doubl
         int k = oracle_nqp(r, H, h + (size_t)j * r, x + (size_t)j * r, max_inner, eps, ls_guard);
         if (iters) iters[j] = k;
         total += k;
+    }
+    return total;
+}
+
+/* One NQP with the per-iteration projected-gradient norms ||f~_k||^2
+ * (k = 0..iters) written to nk_trace; no fast-break. */
+int oracle_nqp_trace(int r, const double *H, const double *h, double *x, int max_inner, double eps,
+                     int ls_guard, double *nk_trace) {
+    return nqp_core(r, H, h, x, max_inner, eps, ls_guard, 0, NULL, -1.0, NULL, nk_trace);
+}
+
+/* Independent NQPs with the fast-break of Algorithm 3: the columns are cut
+ * into "threads of computation" of `chunk` consecutive columns (a fixed
+ * partition, so the result never depends on scheduling); within one, the
+ * columns are solved in order with maxStop starting at 0 (Algorithm 2 resets
+ * it before each half) and raised to the final ||f~||^2 of every solved
+ * column; a column also stops once ||f~_k||^2 <= maxStop.  nk (optional) gets
+ * each column's final ||f~||^2.  Returns the total number of iterations. */
+long oracle_nqp_batch_faststop(int r, long ncols, const double *H, const double *h, double *x,
+                               int max_inner, double eps, int ls_guard, long chunk, int *iters,
+                               double *nk) {
+    long total = 0;
+    if (chunk < 1) chunk = 1;
+    const long nch = (ncols + chunk - 1) / chunk;
+#pragma omp parallel for schedule(dynamic, 4) reduction(+ : total)
+    for (long c = 0; c < nch; c++) {
+        double max_stop = 0.0;
+        const long j1 = (c + 1) * chunk < ncols ? (c + 1) * chunk : ncols;
+        for (long j = c * chunk; j < j1; j++) {
+            double fin = 0.0;
+            int k = nqp_core(r, H, h + (size_t)j * r, x + (size_t)j * r, max_inner, eps, ls_guard, 0,
+                             NULL, max_stop, &fin, NULL);
+            if (fin > max_stop) max_stop = fin;
+            if (iters) iters[j] = k;
+            if (nk) nk[j] = fin;
+            total += k;
+        }
     }
     return total;
 }

@@ -326,3 +326,52 @@ def test_workload1_fit_converges_and_is_deterministic():
     assert np.all(np.diff(a["loss"]) <= 1e-12 * vv)
     kbar = a["inner"].sum() / (wl["T"] * sum(wl["V"].shape))
     assert 1.0 <= kbar < 20.0
+
+
+# ---------------------------------------------------------------------------
+# Fast-break of Algorithm 3 (the maxStop condition), over fixed chunks of
+# consecutive columns ("threads of computation"; maxStop reset per half).
+
+def _faststop_instance(r=12, ncols=61, seed=41):
+    inst = synth.nqp_instance(r, ncols, seed=seed, l1=0.02)
+    A = inst["A"].astype(np.float64); B = inst["B"].astype(np.float64)
+    return A.T @ A, -(B.T @ A) + 0.02, inst["x0"].astype(np.float64)
+
+
+def test_faststop_with_one_column_chunks_is_the_plain_solver():
+    # maxStop starts at 0 in every chunk, so a one-column chunk never fast-breaks
+    G, h, x0 = _faststop_instance()
+    xa, ia = oracle.nqp_batch(G, h, x0, max_inner=40, eps=1e-5)
+    xb, ib, _ = oracle.nqp_batch_faststop(G, h, x0, chunk=1, max_inner=40, eps=1e-5)
+    assert np.array_equal(xa, xb) and np.array_equal(ia, ib)
+
+
+@pytest.mark.parametrize("chunk", [4, 16, 61])
+def test_faststop_follows_the_rule_on_each_columns_own_trace(chunk):
+    # The fast-break only truncates a column's iterations.  From each column's
+    # plain trace of ||f~_k||^2 the stopping iteration is the first k >= 1 with
+    # ||f~_k||^2 <= eps ||f~_0||^2 or <= the largest final ||f~||^2 of the
+    # earlier columns of its chunk (0 for the first one), else max_inner.
+    G, h, x0 = _faststop_instance()
+    K, eps = 40, 1e-5
+    x, it, nk = oracle.nqp_batch_faststop(G, h, x0, chunk=chunk, max_inner=K, eps=eps)
+    ncols = h.shape[0]
+    saw_break = False
+    for c0 in range(0, ncols, chunk):
+        m = 0.0
+        for j in range(c0, min(ncols, c0 + chunk)):
+            _, kt, tr = oracle.nqp_trace(G, h[j], x0[j], max_inner=K, eps=0.0)
+            want = K
+            for k in range(1, len(tr)):
+                if tr[k] <= eps * tr[0] or tr[k] <= m:
+                    want = k
+                    break
+            plain = next((k for k in range(1, len(tr)) if tr[k] <= eps * tr[0]), K)
+            saw_break |= want < plain
+            assert it[j] == want, (chunk, j, it[j], want)
+            assert nk[j] == tr[want]
+            m = max(m, tr[want])
+            xt, _ = oracle.nqp(G, h[j], x0[j], max_inner=want, eps=0.0)
+            assert np.array_equal(x[j], xt)
+    if chunk > 1:
+        assert saw_break  # the instance does exercise the fast-break
