@@ -102,7 +102,13 @@ typedef struct {
  * lanes of a wavefront that cooperate on one column in the solve kernel
  * (1, 2, 4, 8 or 16; 0 = chosen from r and the launch's column count: few
  * columns get wider groups).  It is a layout choice: results for different
- * lanes agree to rounding, and are bitwise reproducible for a fixed choice. */
+ * lanes agree to rounding, and are bitwise reproducible for a fixed choice.
+ * fast_break_cols: Algorithm 3's fast-break (maxStop) with each thread of
+ * computation a fixed run of this many consecutive columns, solved in order:
+ * within a run a column also stops once ||f~_k||^2 falls to the largest final
+ * ||f~||^2 of the run's earlier columns (the first column of every run, and
+ * every run of each half-iteration, start from 0).  0 (default) or 1: off.
+ * The runs are a fixed partition, so results stay reproducible. */
 typedef struct {
     int32_t max_outer;
     int32_t max_inner;
@@ -112,6 +118,7 @@ typedef struct {
     int32_t objective_every;
     int32_t check_finite;
     int32_t lanes;
+    int32_t fast_break_cols;
 } nmf_opts;
 
 /* Statistics of a fit.  loss = 0.5||V - W H||^2, objective = J above (both
@@ -125,7 +132,8 @@ typedef struct {
 } nmf_stats;
 
 /* Fills *o with the defaults: max_outer 50, max_inner 100, eps 1e-3,
- * ls_guard 1, NMF_FP32, objective_every 0, check_finite 0, lanes 0. */
+ * ls_guard 1, NMF_FP32, objective_every 0, check_finite 0, lanes 0,
+ * fast_break_cols 0. */
 NMF_API void nmf_default_opts(nmf_opts *o);
 
 /* Message describing the calling thread's last non-OK status. */

@@ -149,7 +149,7 @@ extern "C" int nmf_fit_batched(int32_t count, const nmf_problem *probs, const nm
             hl[h].solve.push_back(sv);
             // the layout is chosen for the whole launch's column count
             const NqpVariant v = nqp_pick(r, ctot[h], opt->lanes);
-            const int chunk = bnqp_chunk_cols(v.L);
+            const int chunk = bnqp_chunk_cols(v.L, opt->fast_break_cols);
             auto &lst = hl[h].chunks[{v.E, v.L}];
             for (int64_t c0 = 0; c0 < C; c0 += chunk)
                 lst.push_back({p, (int32_t)c0, (int32_t)std::min<int64_t>(C, c0 + chunk)});
@@ -253,7 +253,8 @@ extern "C" int nmf_fit_batched(int32_t count, const nmf_problem *probs, const nm
                     if (e == hipSuccess)
                         e = launch_bnqp(dh[h].groups[g].first, dh[h].groups[g].second.first,
                                         dh[h].groups[g].second.second, queues + gi + (int)g,
-                                        dh[h].solve, opt->max_inner, opt->eps, opt->ls_guard ? 1 : 0, gs);
+                                        dh[h].solve, opt->max_inner, opt->eps, opt->ls_guard ? 1 : 0,
+                                        opt->fast_break_cols, gs);
                     if (e == hipSuccess && g > 0) e = hipEventRecord(evs[ev0 + g], gs);
                 }
                 for (size_t g = 1; g < ng && e == hipSuccess; g++) e = hipStreamWaitEvent(cs, evs[ev0 + g], 0);  // join
@@ -305,13 +306,13 @@ extern "C" int nmf_fit_batched(int32_t count, const nmf_problem *probs, const nm
 namespace nmfi {
 hipError_t launch_bnqp(const NqpVariant &v, const BSolveChunk *chunks, int nchunks,
                        unsigned int *queue, const BSolveProb *probs, int max_inner, double eps,
-                       int ls_guard, hipStream_t s) {
+                       int ls_guard, int unit, hipStream_t s) {
     switch (v.L) {
-    case 1: return launch_bnqp_l1(v.E, chunks, nchunks, queue, probs, max_inner, eps, ls_guard, s);
-    case 2: return launch_bnqp_l2(v.E, chunks, nchunks, queue, probs, max_inner, eps, ls_guard, s);
-    case 4: return launch_bnqp_l4(v.E, chunks, nchunks, queue, probs, max_inner, eps, ls_guard, s);
-    case 8: return launch_bnqp_l8(v.E, chunks, nchunks, queue, probs, max_inner, eps, ls_guard, s);
-    case 16: return launch_bnqp_l16(v.E, chunks, nchunks, queue, probs, max_inner, eps, ls_guard, s);
+    case 1: return launch_bnqp_l1(v.E, chunks, nchunks, queue, probs, max_inner, eps, ls_guard, unit, s);
+    case 2: return launch_bnqp_l2(v.E, chunks, nchunks, queue, probs, max_inner, eps, ls_guard, unit, s);
+    case 4: return launch_bnqp_l4(v.E, chunks, nchunks, queue, probs, max_inner, eps, ls_guard, unit, s);
+    case 8: return launch_bnqp_l8(v.E, chunks, nchunks, queue, probs, max_inner, eps, ls_guard, unit, s);
+    case 16: return launch_bnqp_l16(v.E, chunks, nchunks, queue, probs, max_inner, eps, ls_guard, unit, s);
     default: return hipErrorInvalidValue;
     }
 }

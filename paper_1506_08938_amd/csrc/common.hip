@@ -51,6 +51,7 @@ extern "C" void nmf_default_opts(nmf_opts *o) {
     o->objective_every = 0;
     o->check_finite = 0;
     o->lanes = 0;
+    o->fast_break_cols = 0;
 }
 
 namespace nmfi {

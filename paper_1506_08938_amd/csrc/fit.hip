@@ -507,6 +507,7 @@ static hipError_t half_update(nmf_plan *p, bool h_update, const float *A, float 
     q.ncols = c; q.r = p->r; q.ldp = p->r; q.ldx = p->r;
     q.max_inner = p->opt.max_inner; q.eps = p->opt.eps; q.ls_guard = p->opt.ls_guard ? 1 : 0;
     q.cold = 0; q.iters = nullptr; q.counter = p->counter; q.inner_total = p->inner_total;
+    q.unit = p->opt.fast_break_cols;
     PhaseMark pm(p, NMF_PHASE_SOLVE, s);
     return launch_nqp(h_update ? p->var_h : p->var_w, q, s);
 }
@@ -668,6 +669,7 @@ int basis_solve(const nmf_basis *B, const float *P, int64_t c, float *Ht_new, in
     q.ncols = c; q.r = B->r; q.ldp = B->r; q.ldx = B->r;
     q.max_inner = B->opt.max_inner; q.eps = B->opt.eps; q.ls_guard = B->opt.ls_guard ? 1 : 0;
     q.cold = 1; q.iters = iters; q.counter = counter; q.inner_total = nullptr;
+    q.unit = B->opt.fast_break_cols;
     NMF_HIP(launch_nqp(B->var, q, s));
     return NMF_OK;
 }

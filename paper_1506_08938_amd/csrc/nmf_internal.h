@@ -38,6 +38,7 @@ struct NqpParams {
     int32_t *iters;                    // optional, per column
     unsigned long long *counter;       // work counter; must be zero at launch
     unsigned long long *inner_total;   // optional accumulator of iterations
+    int unit;  // columns per fast-break thread of computation (<= 1: off)
 };
 
 // Kernel variant (entries per lane E, lanes per column L).
@@ -154,12 +155,19 @@ hipError_t launch_bgram(const BItem *items, int64_t nitems, const BGramProb *pro
 hipError_t launch_bdense(const BItem *items, int64_t nitems, const BProdProb *probs, int ntmax,
                          bool xt, bool bf16, const BItem *red_items, int64_t nred,
                          const BItem *f16_items, int64_t nf16, hipStream_t s);
+// unit: columns per fast-break thread of computation (<= 1: no fast-break)
 hipError_t launch_bnqp(const NqpVariant &v, const BSolveChunk *chunks, int nchunks,
                        unsigned int *queue, const BSolveProb *probs, int max_inner, double eps,
-                       int ls_guard, hipStream_t s);
+                       int ls_guard, int unit, hipStream_t s);
 // columns per chunk of a batched solve launch: four trips of every lane
 // group of a block
 inline int bnqp_chunk_cols(int L) { return 4 * (64 / L) * 4; }
+// ... rounded up to whole fast-break units, so that a chunk's units are the
+// units a single launch over the same columns would form
+inline int bnqp_chunk_cols(int L, int unit) {
+    const int c = bnqp_chunk_cols(L);
+    return unit > 1 ? (c + unit - 1) / unit * unit : c;
+}
 hipError_t launch_zero_u32(unsigned int *p, int n, hipStream_t s);
 
 // ------------------------------------------------------------------ objective

@@ -60,6 +60,8 @@ int validate_opts(const nmf_opts *o) {
         return fail(NMF_E_INVAL, "precision must be NMF_FP32 or NMF_BF16");
     if (o->lanes != 0 && o->lanes != 1 && o->lanes != 2 && o->lanes != 4 && o->lanes != 8 && o->lanes != 16)
         return fail(NMF_E_INVAL, "lanes must be 0, 1, 2, 4, 8 or 16 (got %d)", o->lanes);
+    if (o->fast_break_cols < 0 || o->fast_break_cols > (1 << 20))
+        return fail(NMF_E_INVAL, "fast_break_cols must be in [0, 2^20] (got %d)", o->fast_break_cols);
     return NMF_OK;
 }
 
@@ -106,6 +108,7 @@ extern "C" int nnls_solve_batch(int32_t r, int64_t ncols, const float *gram, con
         p.ncols = ncols; p.r = r; p.ldp = r; p.ldx = r;
         p.max_inner = opt->max_inner; p.eps = opt->eps; p.ls_guard = opt->ls_guard ? 1 : 0;
         p.cold = 0; p.iters = iters; p.counter = counter; p.inner_total = nullptr;
+        p.unit = opt->fast_break_cols;
         e = launch_nqp(v, p, s);
     }
     hipError_t e2 = hipFreeAsync(counter, s);

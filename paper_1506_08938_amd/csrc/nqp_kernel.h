@@ -303,10 +303,12 @@ struct ColumnIO {
     double eps;
     int ls_guard;
     int cold;
+    int64_t ncols;     // columns of this launch (or chunk)
+    int unit;          // columns per work unit; > 1: the fast-break's thread of computation
 };
 
-// Work counters: a global 64-bit counter over [0, n) columns, or a 32-bit LDS
-// counter over the columns of one chunk.
+// Work counters over [0, n) work units: a global 64-bit counter, or a
+// 32-bit LDS counter over the units of one chunk.
 struct GlobalFetch {
     unsigned long long *ctr;
     int64_t n;
@@ -346,14 +348,24 @@ __device__ __forceinline__ void nqp_columns(const float *__restrict__ sQ,
     for (int e = 0; e < E; e++) { y[e] = 0.f; g[e] = 1.f; }
     bool active = false;
     bool exhausted = false;  // wave-uniform
-    int64_t col = 0;
+    int64_t col = 0, cend = 0;  // current column; end of the group's work unit
+    // fast-break threshold of the unit's thread of computation (Algorithm 3):
+    // reset to 0 per unit, raised to each finished column's ||f~||^2;
+    // negative when the fast-break is off
+    double mstop = -1.0;
     double n0 = 0.0;
     int k = 0;
 
     for (;;) {
         // ------------------------------------------------ refill finished groups
+        // the next column of the group's own unit, in order; else a new unit
+        bool fresh = false;
+        if (!active && col + 1 < cend) {
+            col++;
+            fresh = true;
+        }
         if (!exhausted) {
-            const unsigned long long needmask = __ballot(!active && sub == 0);
+            const unsigned long long needmask = __ballot(!active && !fresh && sub == 0);
             if (needmask) {
                 const int cnt = __popcll(needmask);
                 unsigned long long b0 = 0;
@@ -364,11 +376,19 @@ __device__ __forceinline__ void nqp_columns(const float *__restrict__ sQ,
                 if (b0 + (unsigned long long)cnt >= (unsigned long long)fetch.n) exhausted = true;
                 const int leader = lane - sub;
                 const int rank = __popcll(needmask & ((1ull << leader) - 1ull));
-                bool fresh = false;
-                if (!active) {
-                    const unsigned long long c = b0 + (unsigned long long)rank;
-                    if (c < (unsigned long long)fetch.n) { col = (int64_t)c; fresh = true; }
+                if (!active && !fresh) {
+                    const unsigned long long u = b0 + (unsigned long long)rank;
+                    if (u < (unsigned long long)fetch.n) {
+                        col = (int64_t)u * a.unit;
+                        cend = min(a.ncols, col + a.unit);
+                        mstop = a.unit > 1 ? 0.0 : -1.0;
+                        fresh = true;
+                    }
                 }
+            }
+        }
+        {
+            {
                 if (fresh) {
                     // y0 = x0 * sqrt(diag), q = h / sqrt(diag), g0 = Q y0 + q
                     float q[E];
@@ -495,7 +515,8 @@ __device__ __forceinline__ void nqp_columns(const float *__restrict__ sQ,
                 nl = fma((double)p, (double)p, nl);
             }
             const double nk = grp_sum_d<L>(nl);
-            if (nk <= a.eps * n0 || k >= a.max_inner) {
+            if (nk <= a.eps * n0 || nk <= mstop || k >= a.max_inner) {
+                if (mstop >= 0.0 && nk > mstop) mstop = nk;
                 float *xrow = a.X + col * (int64_t)a.ldx;
 #pragma unroll
                 for (int e = 0; e < E; e++) {
@@ -556,9 +577,10 @@ __attribute__((amdgpu_waves_per_eu(nqp_waves_per_eu<E, L>(), 8))) void k_nqp(con
     __shared__ float sZ[2 * R];
     stage_q<E, L>(a.gram, a.r, sQ, sD, sZ);
     __syncthreads();
+    const int unit = a.unit > 1 ? a.unit : 1;
     ColumnIO io{a.P, a.hsign, a.hadd, a.X, a.ldp, a.ldx, a.iters, a.r, a.max_inner, a.eps,
-                a.ls_guard, a.cold};
-    GlobalFetch f{a.counter, a.ncols};
+                a.ls_guard, a.cold, a.ncols, unit};
+    GlobalFetch f{a.counter, (a.ncols + unit - 1) / unit};
     unsigned long long my_inner = 0;
     nqp_columns<E, L>(sQ, sD, sZ, io, f, my_inner);
     flush_inner(my_inner, a.inner_total);
@@ -572,7 +594,7 @@ template <int E, int L>
 __global__ __launch_bounds__((nqp_block<E, L>()))
 __attribute__((amdgpu_waves_per_eu(nqp_waves_per_eu<E, L>(), 8))) void k_bnqp(
     const BSolveChunk *__restrict__ chunks, int nchunks, unsigned int *queue,
-    const BSolveProb *__restrict__ probs, int max_inner, double eps, int ls_guard) {
+    const BSolveProb *__restrict__ probs, int max_inner, double eps, int ls_guard, int unit) {
     constexpr int R = E * L;
     __shared__ __attribute__((aligned(16))) float sQ[R * QLayout<E, L>::SQ];
     __shared__ float sD[R];
@@ -590,9 +612,11 @@ __attribute__((amdgpu_waves_per_eu(nqp_waves_per_eu<E, L>(), 8))) void k_bnqp(
         const BSolveProb P = probs[ch.prob];
         stage_q<E, L>(P.G, P.r, sQ, sD, sZ);
         __syncthreads();
+        const int64_t nc = ch.c1 - ch.c0;
+        const int u = unit > 1 ? unit : 1;
         ColumnIO io{P.P + (int64_t)ch.c0 * P.r, -1.f, P.l1, P.X + (int64_t)ch.c0 * P.r, P.r, P.r,
-                    P.iters ? P.iters + ch.c0 : nullptr, P.r, max_inner, eps, ls_guard, P.cold};
-        LdsFetch f{&s_ctr, (int64_t)(ch.c1 - ch.c0)};
+                    P.iters ? P.iters + ch.c0 : nullptr, P.r, max_inner, eps, ls_guard, P.cold, nc, u};
+        LdsFetch f{&s_ctr, (nc + u - 1) / u};
         unsigned long long my_inner = 0;
         nqp_columns<E, L>(sQ, sD, sZ, io, f, my_inner);
         flush_inner(my_inner, P.inner);
@@ -614,7 +638,7 @@ int nqp_blocks_per_cu(K kernel, int block, int (&cache)[2]) {
 
 template <int E, int L>
 hipError_t launch_bnqp_t(const BSolveChunk *chunks, int nchunks, unsigned int *queue,
-                         const BSolveProb *probs, int max_inner, double eps, int ls_guard,
+                         const BSolveProb *probs, int max_inner, double eps, int ls_guard, int unit,
                          hipStream_t s) {
     if (nchunks <= 0) return hipSuccess;
     static int cache[2] = {-1, -1};
@@ -623,7 +647,7 @@ hipError_t launch_bnqp_t(const BSolveChunk *chunks, int nchunks, unsigned int *q
     const int64_t cap = (int64_t)nqp_blocks_per_cu(k_bnqp<E, L>, block, cache) * device_cu_count();
     const int grid = (int)(nchunks < cap ? nchunks : cap);
     hipLaunchKernelGGL((k_bnqp<E, L>), dim3(grid), dim3(block), 0, s, chunks, nchunks, queue,
-                       probs, max_inner, eps, ls_guard);
+                       probs, max_inner, eps, ls_guard, unit);
     return hipGetLastError();
 }
 

@@ -31,22 +31,22 @@ inline const int *nqp_e_table(int L, int *n) {
 hipError_t launch_nqp_l1(int E, const NqpParams &p, hipStream_t s);
 hipError_t launch_bnqp_l1(int E, const BSolveChunk *chunks, int nchunks, unsigned int *queue,
                           const BSolveProb *probs, int max_inner, double eps, int ls_guard,
-                          hipStream_t s);
+                          int unit, hipStream_t s);
 hipError_t launch_nqp_l2(int E, const NqpParams &p, hipStream_t s);
 hipError_t launch_bnqp_l2(int E, const BSolveChunk *chunks, int nchunks, unsigned int *queue,
                           const BSolveProb *probs, int max_inner, double eps, int ls_guard,
-                          hipStream_t s);
+                          int unit, hipStream_t s);
 hipError_t launch_nqp_l4(int E, const NqpParams &p, hipStream_t s);
 hipError_t launch_bnqp_l4(int E, const BSolveChunk *chunks, int nchunks, unsigned int *queue,
                           const BSolveProb *probs, int max_inner, double eps, int ls_guard,
-                          hipStream_t s);
+                          int unit, hipStream_t s);
 hipError_t launch_nqp_l8(int E, const NqpParams &p, hipStream_t s);
 hipError_t launch_bnqp_l8(int E, const BSolveChunk *chunks, int nchunks, unsigned int *queue,
                           const BSolveProb *probs, int max_inner, double eps, int ls_guard,
-                          hipStream_t s);
+                          int unit, hipStream_t s);
 hipError_t launch_nqp_l16(int E, const NqpParams &p, hipStream_t s);
 hipError_t launch_bnqp_l16(int E, const BSolveChunk *chunks, int nchunks, unsigned int *queue,
                           const BSolveProb *probs, int max_inner, double eps, int ls_guard,
-                          hipStream_t s);
+                          int unit, hipStream_t s);
 
 }  // namespace nmfi

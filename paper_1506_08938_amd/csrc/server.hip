@@ -87,7 +87,7 @@ int run_foldin_batch(nmf_server *S, std::vector<std::shared_ptr<Req>> &batch, hi
     }
     std::vector<BSolveProb> probs;
     std::vector<BSolveChunk> chunks;
-    const int chunk = bnqp_chunk_cols(B->var.L);
+    const int chunk = bnqp_chunk_cols(B->var.L, B->opt.fast_break_cols);
     int64_t off = 0;
     for (size_t j = 0; j < batch.size(); j++) {
         const nmf_request &q = batch[j]->q;
@@ -124,7 +124,7 @@ int run_foldin_batch(nmf_server *S, std::vector<std::shared_ptr<Req>> &batch, hi
     if (e == hipSuccess) e = launch_zero_u32(queue, 1, s);
     if (e == hipSuccess)
         e = launch_bnqp(B->var, dchunks, (int)chunks.size(), queue, dprobs, B->opt.max_inner,
-                        B->opt.eps, B->opt.ls_guard ? 1 : 0, s);
+                        B->opt.eps, B->opt.ls_guard ? 1 : 0, B->opt.fast_break_cols, s);
     (void)hipFreeAsync(ws, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host vectors live until here
     if (e != hipSuccess) return hip_fail(e, "server fold-in batch");

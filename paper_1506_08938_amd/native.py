@@ -48,7 +48,8 @@ class NmfOpts(ctypes.Structure):
     _fields_ = [("max_outer", ctypes.c_int32), ("max_inner", ctypes.c_int32),
                 ("eps", ctypes.c_double), ("ls_guard", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("objective_every", ctypes.c_int32),
-                ("check_finite", ctypes.c_int32), ("lanes", ctypes.c_int32)]
+                ("check_finite", ctypes.c_int32), ("lanes", ctypes.c_int32),
+                ("fast_break_cols", ctypes.c_int32)]
 
 
 class NmfStats(ctypes.Structure):

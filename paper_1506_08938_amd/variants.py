@@ -44,7 +44,7 @@ namespace nmfi {{
 
 hipError_t launch_bnqp_l{L}(int E, const BSolveChunk *chunks, int nchunks, unsigned int *queue,
                           const BSolveProb *probs, int max_inner, double eps, int ls_guard,
-                          hipStream_t s) {{
+                          int unit, hipStream_t s) {{
     switch (E) {{
 {cases}
     default: return hipErrorInvalidValue;
@@ -97,7 +97,7 @@ def generate() -> None:
         _write(os.path.join(CSRC, f"k_nqp_l{L}.hip"), _SOLO.format(L=L, cases=cases))
         cases = "\n".join(
             f"    case {e}: return launch_bnqp_t<{e}, {L}>(chunks, nchunks, queue, probs, max_inner, "
-            f"eps, ls_guard, s);" for e in es)
+            f"eps, ls_guard, unit, s);" for e in es)
         _write(os.path.join(CSRC, f"k_nqp_b{L}.hip"), _BATCH.format(L=L, cases=cases))
     tables = "\n".join(
         f"constexpr int kNqpE{L}[] = {{{', '.join(str(e) for e in es)}}};" for L, es in VARIANTS.items())
@@ -108,7 +108,7 @@ def generate() -> None:
         f"hipError_t launch_nqp_l{L}(int E, const NqpParams &p, hipStream_t s);\n"
         f"hipError_t launch_bnqp_l{L}(int E, const BSolveChunk *chunks, int nchunks, unsigned int *queue,\n"
         f"                          const BSolveProb *probs, int max_inner, double eps, int ls_guard,\n"
-        f"                          hipStream_t s);" for L in VARIANTS)
+        f"                          int unit, hipStream_t s);" for L in VARIANTS)
     _write(os.path.join(CSRC, "nqp_variants.h"),
            _HEADER.format(tables=tables, switch=switch, decls=decls))
 

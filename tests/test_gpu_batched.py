@@ -30,14 +30,14 @@ def problems(count, first_seed=0):
 # The batched fit chooses the solve layout from the column count of the whole
 # launch, a solo fit from its own; with the layout fixed (opts.lanes) every
 # problem's arithmetic is the same in both, so the results are bitwise equal.
-@pytest.mark.parametrize("precision,lanes", [(0, 2), (0, 8), (1, 4)])
-def test_batched_equals_solo_fits(precision, lanes):
+@pytest.mark.parametrize("precision,lanes,fb", [(0, 2, 0), (0, 8, 0), (1, 4, 0), (0, 4, 24)])
+def test_batched_equals_solo_fits(precision, lanes, fb):
     from paper_1506_08938_amd import native as nat
     probs = problems(24)
     # make the regularisation differ per problem
     for i, p in enumerate(probs):
         p["reg"] = (0.01 * (i % 2), 0.02 * (i % 3 == 0), 0.05 * (i % 4 == 1), 0.01 * (i % 5 == 2))
-    opt = nat.opts(max_outer=3, precision=precision, lanes=lanes)
+    opt = nat.opts(max_outer=3, precision=precision, lanes=lanes, fast_break_cols=fb)
     batch = [dict(V=T(p["V"]), r=p["r"], reg=nat.reg(*p["reg"]), W=T(p["W0"]), Ht=T(p["Ht0"]))
              for p in probs]
     stats = nat.fit_batched(batch, opt)

@@ -98,3 +98,24 @@ def test_budget_refusal_and_latency(basis):
         S.submit_foldin(big, torch.empty((3000, r), device="cuda"))
     assert ei.value.status == nat.NMF_E_BUSY
     S.close()
+
+
+def test_fast_break_results_do_not_depend_on_the_batch():
+    import torch
+    from paper_1506_08938_amd import native as nat
+    m, r = 3000, 40
+    W = np.random.default_rng(8).gamma(2.0, 0.5, (m, r)).astype(np.float32)
+    B = nat.Basis(T(W), l1=0.05, l2=0.0, opt=nat.opts(max_inner=100, eps=1e-3, fast_break_cols=24))
+    req = nat.sparse_request(synth.foldin_columns(m, 333, 40, seed=11), m)
+    direct = H(B.foldin(req))
+    S = nat.Server(B, hbm_budget=1 << 30, max_slots=3, max_batch_cols=4096)
+    outs, tickets = [], []
+    for i, c in enumerate([5, 333, 100, 17]):
+        q = req if c == 333 else nat.sparse_request(synth.foldin_columns(m, c, 40, seed=50 + i), m)
+        o = torch.empty((c, r), device="cuda")
+        outs.append(o)
+        tickets.append(S.submit_foldin(q, o))
+    S.wait()
+    assert np.array_equal(H(outs[1]), direct)
+    S.close()
+    B.close()
