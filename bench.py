@@ -328,7 +328,8 @@ def bench_batched(args, native, synth, torch, np):
     vbytes = sum(4 * p["V"].size for p in probs)
     res = {}
     for prec, name in ((1, "bf16"), (0, "fp32")):
-        opt = native.opts(max_outer=T, max_inner=100, eps=1e-3, precision=prec)
+        opt = native.opts(max_outer=T, max_inner=100, eps=1e-3, precision=prec,
+                          fast_break_cols=args.fast_break)
         best = None
         for rep in range(2):
             batch = [dict(V=d["V"], r=d["r"], reg=native.reg(), W=d["W0"].clone(), Ht=d["Ht0"].clone())
@@ -412,6 +413,8 @@ def main():
                     help="Poisson arrival rate as a fraction of the saturated request rate")
     ap.add_argument("--workload", default="sparse", choices=["sparse", "dense", "batched", "serving"],
                     help="sparse: the headline line (default); the others print supplementary lines")
+    ap.add_argument("--fast-break", type=int, default=0,
+                    help="Algorithm 3's fast-break over runs of this many columns (0: off)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 1 GiB device buffer (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -452,7 +455,7 @@ def main():
 
     Vd = native.DeviceMatrix(V, with_transpose=False)  # CSR(V') is built on the device
     reg = native.reg(*wl["reg"])
-    opt = native.opts(max_inner=100, eps=1e-3, ls_guard=1)
+    opt = native.opts(max_inner=100, eps=1e-3, ls_guard=1, fast_break_cols=args.fast_break)
     plan = native.Plan(Vd, r, reg, opt)
     W = torch.from_numpy(wl["W0"]).cuda()
     Ht = torch.from_numpy(wl["Ht0"]).cuda()
@@ -505,7 +508,8 @@ def main():
         "config": {
             "workload": "sparse text-like CSR V 200000x100000, 100 Zipf(1.1) columns per row "
                         "(0.1% density), values log(1+Poisson(3)), r=100, L1=0.1 on H, L2=0.01 "
-                        "on W, eps=1e-3, max_inner=100; one step = one outer iteration",
+                        "on W, eps=1e-3, max_inner=100; one step = one outer iteration"
+                        + (f"; fast-break over runs of {args.fast_break} columns" if args.fast_break > 1 else ""),
             "m": m, "n": n, "nnz": int(V.nnz), "r": r,
         },
         "roofline": {

@@ -8,8 +8,9 @@
 // half's NQPs: max over entries of |min(x, g)| with g = Gamma x + h in the
 // original scale (zero exactly at a KKT point).
 //
-// Every reduction writes per-block partials that a single block then sums in
-// index order, so results are bitwise reproducible.
+// Work is dealt to a grid whose size depends only on the problem's shape,
+// and every reduction sums per-block partials in a fixed order (in fixed
+// groups first where there are many), so results are bitwise reproducible.
 #include "nmf_internal.h"
 
 namespace nmfi {
@@ -72,79 +73,193 @@ __global__ __launch_bounds__(256) void k_loss_dense(const float *__restrict__ V,
 }
 
 // ------------------------------------------------------------ CSR cross term
-// one wave per row i: sum over stored (i, j) of V_ij * <W_i, H_j> and V_ij^2
+// Rows are dealt to the waves of a fixed grid (row i to wave i mod 4 * grid).
+// For row i the wave forms acc_a = sum over the stored (i, j) of V_ij H_ja in
+// double (a product of two floats is exact in double), then adds W_ia acc_a:
+// the cross term <V, W H'> taken as sum_i W_i . (V H')_i.  The squares of the
+// stored values give ||V||^2.  One (cross, ||V||^2) pair per block, summed in
+// a fixed order.
+//
+// VEC floats of a factor row per lane: with VEC = 4 a half-wave covers a row
+// (r <= 128) and one 128-bit load per lane fetches two stored entries' rows;
+// VEC = 2 and 1 serve ranks that are not multiples of 4 (one entry per load,
+// a second load for r > 64 when VEC = 1).
+constexpr int LOSS_CSR_GRID = 2048;
+constexpr int LOSS_CSR_UNROLL = 8;  // loads in flight per lane
+
+// sum over the 64 lanes; every lane gets the same value (each butterfly step
+// adds the same two numbers in both lanes)
+__device__ inline double wave_sum_d(double v) {
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+__device__ inline float lane_f(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+template <int VEC> struct LossVec;
+template <> struct LossVec<4> { using T = float4; static constexpr int EPL = 2, NA = 4; };
+template <> struct LossVec<2> { using T = float2; static constexpr int EPL = 1, NA = 2; };
+template <> struct LossVec<1> { using T = float; static constexpr int EPL = 1, NA = 2; };
+
+template <int VEC>
 __global__ __launch_bounds__(256) void k_loss_csr(const int32_t *__restrict__ rowptr,
                                                   const int32_t *__restrict__ colidx,
                                                   const float *__restrict__ vals, int64_t m,
                                                   const float *__restrict__ W,
                                                   const float *__restrict__ Ht, int r,
                                                   double *__restrict__ partial) {
-    __shared__ float wrow[4][NMF_MAX_RANK];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t i = (int64_t)blockIdx.x * 4 + wave;
+    using LV = LossVec<VEC>;
+    constexpr int EPL = LV::EPL;  // stored entries per load instruction
+    constexpr int NA = LV::NA;    // rank coordinates per lane
+    __shared__ double red[2][4];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    // the lane's part of an entry's row: coordinates ca[k], valid when < r
+    const int half = EPL == 2 ? lane >> 5 : 0;
+    const int sl = EPL == 2 ? lane & 31 : lane;
+    int ca[NA];
+#pragma unroll
+    for (int k = 0; k < NA; k++) ca[k] = VEC == 1 ? lane + 64 * k : VEC * sl + k;
+    const bool ok = VEC == 1 ? true : ca[0] < r;  // whole vector in range (r % VEC == 0)
     double cross = 0.0, vv = 0.0;
-    if (i < m) {
-        for (int a = lane; a < r; a += 64) wrow[wave][a] = W[i * r + a];
+    for (int64_t i = (int64_t)blockIdx.x * 4 + wave; i < m; i += (int64_t)gridDim.x * 4) {
+        const int t0 = rowptr[i], t1 = rowptr[i + 1];
+        double acc[NA];
+#pragma unroll
+        for (int k = 0; k < NA; k++) acc[k] = 0.0;
+        for (int tb = t0; tb < t1; tb += 64) {
+            const int cnt = min(64, t1 - tb);
+            int jl = 0;
+            float vl = 0.f;
+            if (lane < cnt) {
+                jl = colidx[tb + lane];
+                vl = vals[tb + lane];
+                vv = fma((double)vl, (double)vl, vv);
+            }
+            // entry q + EPL u + half (past the end: no load, weight 0)
+            for (int q = 0; q < cnt; q += EPL * LOSS_CSR_UNROLL) {
+                float hv[LOSS_CSR_UNROLL][NA];
+                float w[LOSS_CSR_UNROLL];
+#pragma unroll
+                for (int u = 0; u < LOSS_CSR_UNROLL; u++) {
+                    const int t = q + EPL * u + half;
+                    const bool in = t < cnt;
+                    const int src = in ? t : 0;
+                    int j;
+                    if (EPL == 2) {
+                        j = __shfl(jl, src);
+                        w[u] = __shfl(vl, src);
+                    } else {
+                        j = __builtin_amdgcn_readlane(jl, src);
+                        w[u] = lane_f(vl, src);
+                    }
+                    w[u] = in ? w[u] : 0.f;
+                    const float *hr = Ht + (int64_t)j * r;
+                    if (VEC == 4) {
+                        float4 x = (ok && in) ? *(const float4 *)(hr + ca[0]) : make_float4(0.f, 0.f, 0.f, 0.f);
+                        hv[u][0] = x.x; hv[u][1] = x.y; hv[u][2 % NA] = x.z; hv[u][3 % NA] = x.w;
+                    } else if (VEC == 2) {
+                        float2 x = (ok && in) ? *(const float2 *)(hr + ca[0]) : make_float2(0.f, 0.f);
+                        hv[u][0] = x.x; hv[u][1] = x.y;
+                    } else {
+                        hv[u][0] = (in && ca[0] < r) ? hr[ca[0]] : 0.f;
+                        hv[u][1 % NA] = (in && ca[1 % NA] < r) ? hr[ca[1 % NA]] : 0.f;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < LOSS_CSR_UNROLL; u++) {
+                    const double v = (double)w[u];
+#pragma unroll
+                    for (int k = 0; k < NA; k++) acc[k] = fma(v, (double)hv[u][k], acc[k]);
+                }
+            }
+        }
+        // both half-waves hold partial sums over their entries for the same
+        // coordinates: each adds its own W_ia acc_a, the wave sum adds both
+        const float *wr = W + i * r;
+#pragma unroll
+        for (int k = 0; k < NA; k++)
+            if (ca[k] < r && (VEC == 1 || ok)) cross = fma((double)wr[ca[k]], acc[k], cross);
+    }
+    cross = wave_sum_d(cross);
+    vv = wave_sum_d(vv);
+    if (lane == 0) {
+        red[0][wave] = cross;
+        red[1][wave] = vv;
     }
     __syncthreads();
-    if (i < m) {
-        for (int t = rowptr[i] + lane; t < rowptr[i + 1]; t += 64) {
-            const float *h = Ht + (int64_t)colidx[t] * r;
-            double d = 0.0;
-            for (int a = 0; a < r; a++) d = fma((double)wrow[wave][a], (double)h[a], d);
-            const double v = vals[t];
-            cross = fma(v, d, cross);
-            vv = fma(v, v, vv);
-        }
-    }
-    for (int off = 32; off >= 1; off >>= 1) {
-        cross += __shfl_xor(cross, off);
-        vv += __shfl_xor(vv, off);
-    }
-    if (lane == 0 && i < m) {
-        partial[2 * i] = cross;
-        partial[2 * i + 1] = vv;
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
+        partial[2 * blockIdx.x + 1] = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
     }
 }
 
 // ------------------------------------------------------------ double Gram
-// block b sums rows [b*rpb, ...) of A'A in double, entries e = tid + 256 q
-constexpr int G64_MAXQ = (NMF_MAX_RANK * NMF_MAX_RANK + 255) / 256;
+// Block b sums rows [b * rpb, min(k, (b + 1) * rpb)) of A'A in double.
+// Thread (ta, tb) = (tid / 16, tid % 16) holds the 8 x 8 output tile at rows
+// [8 ta, 8 ta + 8) and columns [8 tb, 8 tb + 8) (a 16 x 16 grid of tiles
+// covers r <= 128); the staged rows are converted to double once.
+constexpr int G64_ROWS = 32;   // rows of A staged per pass
+constexpr int G64_MAXB = 512;  // blocks (and partial Grams) at most
+constexpr int G64_GROUP = 16;  // partials summed per group in the first reduce pass
 
 __global__ __launch_bounds__(256) void k_gram64(const float *__restrict__ A, int64_t k, int r,
                                                 int64_t rpb, double *__restrict__ partial) {
-    __shared__ float rows[16][NMF_MAX_RANK];
-    const int tid = threadIdx.x;
-    const int nq = (r * r + 255) / 256;
-    double acc[G64_MAXQ];
+    __shared__ __attribute__((aligned(16))) double rows[G64_ROWS][NMF_MAX_RANK];
+    const int tid = threadIdx.x, ta = tid >> 4, tb = tid & 15;
+    const int nt = (r + 7) >> 3, rp = nt * 8;
+    const bool act = ta < nt && tb < nt;
+    double acc[8][8];
 #pragma unroll
-    for (int q = 0; q < G64_MAXQ; q++) acc[q] = 0.0;
+    for (int p = 0; p < 8; p++)
+#pragma unroll
+        for (int q = 0; q < 8; q++) acc[p][q] = 0.0;
     const int64_t b0 = (int64_t)blockIdx.x * rpb, b1 = min(k, b0 + rpb);
-    for (int64_t t0 = b0; t0 < b1; t0 += 16) {
-        for (int e = tid; e < 16 * r; e += 256) {
-            const int rr = e / r, a = e - rr * r;
-            rows[rr][a] = (t0 + rr < b1) ? A[(t0 + rr) * r + a] : 0.f;
+    for (int64_t t0 = b0; t0 < b1; t0 += G64_ROWS) {
+        for (int e = tid; e < G64_ROWS * rp; e += 256) {
+            const int rr = e / rp, a = e - rr * rp;
+            rows[rr][a] = (t0 + rr < b1 && a < r) ? (double)A[(t0 + rr) * r + a] : 0.0;
         }
         __syncthreads();
+        if (act) {
+            for (int rr = 0; rr < G64_ROWS; rr++) {
+                double x[8], y[8];
 #pragma unroll
-        for (int q = 0; q < G64_MAXQ; q++) {
-            if (q < nq) {
-                const int e = tid + 256 * q;
-                if (e < r * r) {
-                    const int a = e / r, b = e - (e / r) * r;
-#pragma unroll 4
-                    for (int rr = 0; rr < 16; rr++)
-                        acc[q] = fma((double)rows[rr][a], (double)rows[rr][b], acc[q]);
+                for (int p = 0; p < 8; p++) {
+                    x[p] = rows[rr][8 * ta + p];
+                    y[p] = rows[rr][8 * tb + p];
                 }
+#pragma unroll
+                for (int p = 0; p < 8; p++)
+#pragma unroll
+                    for (int q = 0; q < 8; q++) acc[p][q] = fma(x[p], y[q], acc[p][q]);
             }
         }
         __syncthreads();
     }
+    if (act) {
+        double *out = partial + (int64_t)blockIdx.x * r * r;
 #pragma unroll
-    for (int q = 0; q < G64_MAXQ; q++) {
-        const int e = tid + 256 * q;
-        if (q < nq && e < r * r) partial[(int64_t)blockIdx.x * r * r + e] = acc[q];
+        for (int p = 0; p < 8; p++)
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                const int a = 8 * ta + p, b = 8 * tb + q;
+                if (a < r && b < r) out[a * r + b] = acc[p][q];
+            }
     }
+}
+
+// out[g * width + o] = sum of in[i * width + o] over i in group g
+// ([g * G, min(count, (g + 1) * G)), in order); grid (width / 256, groups)
+__global__ __launch_bounds__(256) void k_reduce_groups(const double *__restrict__ in, int64_t count,
+                                                       int width, int G, double *__restrict__ out) {
+    const int o = blockIdx.x * 256 + threadIdx.x;
+    if (o >= width) return;
+    const int64_t i0 = (int64_t)blockIdx.y * G, i1 = min(count, i0 + G);
+    double s = 0.0;
+    for (int64_t i = i0; i < i1; i++) s += in[i * width + o];
+    out[(int64_t)blockIdx.y * width + o] = s;
 }
 
 // ------------------------------------------------------------ sums
@@ -227,32 +342,89 @@ __global__ void k_finish(const double *__restrict__ t, int csr, double l1w, doub
 }
 
 // ------------------------------------------------------------ KKT residual
-// one wave per row j: g = G x_j + hsign P_j + hadd (double); partial[j] =
-// max_a |min(x_a, g_a)|
+// Groups of KKT_ROWS rows j are dealt to the waves of a fixed grid; lanes run
+// over the coordinate a.  Gamma sits in LDS (float, transposed so that a wave
+// reads a row of it without bank conflicts) and each entry read serves the
+// group's rows; x_j reaches every lane through lane reads.  g = Gamma x_j +
+// hsign P_j + hadd in double; one max of |min(x_a, g_a)| per block.
+constexpr int KKT_GRID = 2048;
+constexpr int KKT_ROWS = 4;
+
 __global__ __launch_bounds__(256) void k_kkt(const float *__restrict__ G, int r,
                                              const float *__restrict__ P, float hsign, float hadd,
                                              const float *__restrict__ X, int64_t c,
                                              double *__restrict__ partial) {
-    __shared__ float xs[4][NMF_MAX_RANK];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t j = (int64_t)blockIdx.x * 4 + wave;
-    if (j < c)
-        for (int a = lane; a < r; a += 64) xs[wave][a] = X[j * r + a];
+    extern __shared__ float gt[];  // gt[b * r + a] = Gamma[a][b]
+    __shared__ double red[4];
+    for (int e = threadIdx.x; e < r * r; e += 256) {
+        const int a = e / r, b = e - a * r;
+        gt[b * r + a] = G[e];
+    }
     __syncthreads();
-    if (j >= c) return;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const bool has0 = lane < r, has1 = lane + 64 < r;
+    // LDS columns read by this lane (clamped into the matrix; unused when the
+    // lane has no coordinate)
+    const int c0 = has0 ? lane : r - 1, c1 = has1 ? lane + 64 : r - 1;
+    const int r0 = r < 64 ? r : 64;
     double mx = 0.0;
-    for (int a = lane; a < r; a += 64) {
-        double g = (double)hsign * (double)P[j * r + a] + (double)hadd;
-        for (int b = 0; b < r; b++) g = fma((double)G[(int64_t)a * r + b], (double)xs[wave][b], g);
-        const double x = xs[wave][a];
-        const double v = fabs(x < g ? x : g);
-        mx = v > mx ? v : mx;
+    const int64_t step = (int64_t)gridDim.x * 4 * KKT_ROWS;
+    for (int64_t j0 = ((int64_t)blockIdx.x * 4 + wave) * KKT_ROWS; j0 < c; j0 += step) {
+        float x0[KKT_ROWS], x1[KKT_ROWS];
+        double g0[KKT_ROWS], g1[KKT_ROWS];
+#pragma unroll
+        for (int k = 0; k < KKT_ROWS; k++) {
+            const int64_t j = j0 + k;
+            const bool in = j < c;
+            const float *xr = X + j * r, *pr = P + j * r;
+            x0[k] = (in && has0) ? xr[lane] : 0.f;
+            x1[k] = (in && has1) ? xr[lane + 64] : 0.f;
+            g0[k] = (in && has0) ? (double)hsign * (double)pr[lane] + (double)hadd : 0.0;
+            g1[k] = (in && has1) ? (double)hsign * (double)pr[lane + 64] + (double)hadd : 0.0;
+        }
+        for (int b = 0; b < r0; b++) {
+            const double ga = (double)gt[b * r + c0];
+            const double gb = r > 64 ? (double)gt[b * r + c1] : 0.0;
+#pragma unroll
+            for (int k = 0; k < KKT_ROWS; k++) {
+                const double xb = (double)lane_f(x0[k], b);
+                g0[k] = fma(ga, xb, g0[k]);
+                g1[k] = fma(gb, xb, g1[k]);
+            }
+        }
+        for (int b = 64; b < r; b++) {
+            const double ga = (double)gt[b * r + c0], gb = (double)gt[b * r + c1];
+#pragma unroll
+            for (int k = 0; k < KKT_ROWS; k++) {
+                const double xb = (double)lane_f(x1[k], b - 64);
+                g0[k] = fma(ga, xb, g0[k]);
+                g1[k] = fma(gb, xb, g1[k]);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < KKT_ROWS; k++) {
+            if (j0 + k >= c) break;
+            if (has0) {
+                const double x = x0[k], v = fabs(x < g0[k] ? x : g0[k]);
+                mx = v > mx ? v : mx;
+            }
+            if (has1) {
+                const double x = x1[k], v = fabs(x < g1[k] ? x : g1[k]);
+                mx = v > mx ? v : mx;
+            }
+        }
     }
     for (int off = 32; off >= 1; off >>= 1) {
         const double o = __shfl_xor(mx, off);
         mx = o > mx ? o : mx;
     }
-    if (lane == 0) partial[j] = mx;
+    if (lane == 0) red[wave] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double v = red[0];
+        for (int w = 1; w < 4; w++) v = red[w] > v ? red[w] : v;
+        partial[blockIdx.x] = v;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_max_ordered(const double *__restrict__ in, int64_t n,
@@ -278,9 +450,10 @@ size_t objective_scratch_bytes(const nmf_matrix *V, int r) {
     if (V->kind == NMF_DENSE) {
         b += align256((size_t)((n + LD_T - 1) / LD_T) * ((m + LD_T - 1) / LD_T) * sizeof(double));
     } else {
-        b += align256((size_t)2 * m * sizeof(double));
-        b += 2 * align256((size_t)256 * r * r * sizeof(double));  // Gram partials (reused)
-        b += 2 * align256((size_t)r * r * sizeof(double));        // GW, GH
+        b += align256((size_t)2 * LOSS_CSR_GRID * sizeof(double));
+        b += align256((size_t)G64_MAXB * r * r * sizeof(double));  // Gram partials (reused)
+        b += align256((size_t)(G64_MAXB / G64_GROUP) * r * r * sizeof(double));  // group sums
+        b += 2 * align256((size_t)r * r * sizeof(double));         // GW, GH
     }
     b += align256(2 * 4096 * sizeof(double)) * 2;  // sums of W and H
     b += align256(16 * sizeof(double));           // terms
@@ -288,17 +461,21 @@ size_t objective_scratch_bytes(const nmf_matrix *V, int r) {
     return b + 1024;
 }
 
-static hipError_t gram64(const float *A, int64_t k, int r, double *partial, double *G,
-                         hipStream_t s) {
-    int64_t nb = (k + 255) / 256;
-    if (nb > 256) nb = 256;
+static hipError_t gram64(const float *A, int64_t k, int r, double *partial, double *groups,
+                         double *G, hipStream_t s) {
+    // about 64 rows per block at least, G64_MAXB blocks at most
+    int64_t nb = (k + 63) / 64;
+    if (nb > G64_MAXB) nb = G64_MAXB;
     if (nb < 1) nb = 1;
-    int64_t rpb = (k + nb - 1) / nb;
-    nb = (k + rpb - 1) / rpb;
-    if (nb < 1) nb = 1;
+    const int64_t rpb = (k + nb - 1) / nb;
+    nb = k > 0 ? (k + rpb - 1) / rpb : 1;
     hipLaunchKernelGGL(k_gram64, dim3((unsigned)nb), dim3(256), 0, s, A, k, r, rpb, partial);
-    hipLaunchKernelGGL(k_reduce_ordered, dim3((unsigned)((r * r + 255) / 256)), dim3(256), 0, s,
-                       partial, nb, r * r, G);
+    const int width = r * r;
+    const int ng = (int)((nb + G64_GROUP - 1) / G64_GROUP);
+    hipLaunchKernelGGL(k_reduce_groups, dim3((unsigned)((width + 255) / 256), (unsigned)ng), dim3(256), 0,
+                       s, partial, nb, width, G64_GROUP, groups);
+    hipLaunchKernelGGL(k_reduce_ordered, dim3((unsigned)((width + 255) / 256)), dim3(256), 0, s,
+                       groups, (int64_t)ng, width, G);
     return hipGetLastError();
 }
 
@@ -321,18 +498,28 @@ hipError_t launch_objective(const nmf_matrix *V, int r, const nmf_reg *reg, cons
         hipLaunchKernelGGL(k_sum_ordered, dim3(1), dim3(256), 0, s, part, (int64_t)gx * gy,
                            (int64_t)1, (int64_t)0, terms + 0);
     } else {
-        double *part = (double *)take((size_t)2 * m * sizeof(double));
-        hipLaunchKernelGGL(k_loss_csr, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, V->rowptr,
-                           V->colidx, V->vals, m, W, Ht, r, part);
-        hipLaunchKernelGGL(k_sum_ordered, dim3(1), dim3(256), 0, s, part, m, (int64_t)2,
+        double *part = (double *)take((size_t)2 * LOSS_CSR_GRID * sizeof(double));
+        int64_t nb = (m + 3) / 4;
+        nb = nb > LOSS_CSR_GRID ? LOSS_CSR_GRID : (nb < 1 ? 1 : nb);
+        if (r % 4 == 0)
+            hipLaunchKernelGGL(k_loss_csr<4>, dim3((unsigned)nb), dim3(256), 0, s, V->rowptr, V->colidx,
+                               V->vals, m, W, Ht, r, part);
+        else if (r % 2 == 0)
+            hipLaunchKernelGGL(k_loss_csr<2>, dim3((unsigned)nb), dim3(256), 0, s, V->rowptr, V->colidx,
+                               V->vals, m, W, Ht, r, part);
+        else
+            hipLaunchKernelGGL(k_loss_csr<1>, dim3((unsigned)nb), dim3(256), 0, s, V->rowptr, V->colidx,
+                               V->vals, m, W, Ht, r, part);
+        hipLaunchKernelGGL(k_sum_ordered, dim3(1), dim3(256), 0, s, part, nb, (int64_t)2,
                            (int64_t)1, terms + 1);
-        hipLaunchKernelGGL(k_sum_ordered, dim3(1), dim3(256), 0, s, part, m, (int64_t)2,
+        hipLaunchKernelGGL(k_sum_ordered, dim3(1), dim3(256), 0, s, part, nb, (int64_t)2,
                            (int64_t)0, terms + 2);
-        double *gp = (double *)take((size_t)256 * r * r * sizeof(double));
+        double *gp = (double *)take((size_t)G64_MAXB * r * r * sizeof(double));
+        double *gg = (double *)take((size_t)(G64_MAXB / G64_GROUP) * r * r * sizeof(double));
         double *gw = (double *)take((size_t)r * r * sizeof(double));
         double *gh = (double *)take((size_t)r * r * sizeof(double));
-        hipError_t e = gram64(W, m, r, gp, gw, s);
-        if (e == hipSuccess) e = gram64(Ht, n, r, gp, gh, s);
+        hipError_t e = gram64(W, m, r, gp, gg, gw, s);
+        if (e == hipSuccess) e = gram64(Ht, n, r, gp, gg, gh, s);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_dot_ordered, dim3(1), dim3(256), 0, s, gw, gh, (int64_t)r * r,
                            terms + 3);
@@ -354,13 +541,16 @@ hipError_t launch_objective(const nmf_matrix *V, int r, const nmf_reg *reg, cons
     return hipGetLastError();
 }
 
-// KKT residual of one half into *dev_out; partial needs c doubles.
+// KKT residual of one half into *dev_out; partial needs min(ceil(c / 16),
+// KKT_GRID) doubles (c always suffice).
 hipError_t launch_kkt(const float *G, int r, const float *P, float hsign, float hadd,
                       const float *X, int64_t c, double *partial, double *dev_out, hipStream_t s) {
     if (c <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_kkt, dim3((unsigned)((c + 3) / 4)), dim3(256), 0, s, G, r, P, hsign, hadd,
-                       X, c, partial);
-    hipLaunchKernelGGL(k_max_ordered, dim3(1), dim3(256), 0, s, partial, c, dev_out);
+    int64_t nb = (c + 4 * KKT_ROWS - 1) / (4 * KKT_ROWS);
+    if (nb > KKT_GRID) nb = KKT_GRID;
+    hipLaunchKernelGGL(k_kkt, dim3((unsigned)nb), dim3(256), (size_t)r * r * sizeof(float), s, G, r, P,
+                       hsign, hadd, X, c, partial);
+    hipLaunchKernelGGL(k_max_ordered, dim3(1), dim3(256), 0, s, partial, nb, dev_out);
     return hipGetLastError();
 }
 

@@ -162,11 +162,11 @@ hipError_t launch_bnqp(const NqpVariant &v, const BSolveChunk *chunks, int nchun
 // columns per chunk of a batched solve launch: four trips of every lane
 // group of a block
 inline int bnqp_chunk_cols(int L) { return 4 * (64 / L) * 4; }
-// ... rounded up to whole fast-break units, so that a chunk's units are the
-// units a single launch over the same columns would form
+// ... with the fast-break: one unit for every lane group of a 512-thread
+// block (whole units, so a chunk's units are the units a single launch over
+// the same columns would form)
 inline int bnqp_chunk_cols(int L, int unit) {
-    const int c = bnqp_chunk_cols(L);
-    return unit > 1 ? (c + unit - 1) / unit * unit : c;
+    return unit > 1 ? (512 / L) * unit : bnqp_chunk_cols(L);
 }
 hipError_t launch_zero_u32(unsigned int *p, int n, hipStream_t s);
 
