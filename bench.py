@@ -388,6 +388,66 @@ def bench_batched(args, native, synth, torch, np):
     print(json.dumps(out), flush=True)
 
 
+def bench_streamed(args, native, synth, torch, np):
+    """Limited internal memory: workload 2 (V 20000x10000 FP32, 800 MB) kept in page-locked host
+    memory and streamed to the device in panels of instances, one read of V per outer iteration
+    (nmf_fit_streamed); against the host-to-device copy rate and the resident FP32 fit."""
+    K, Wm = args.steps, args.warmup
+    panel = args.panel_cols
+    log("[bench] generating the dense workload")
+    wl = synth.workload2()
+    m, n = wl["V"].shape
+    r = wl["r"]
+    Vh = torch.from_numpy(wl["V"]).pin_memory()
+    reg = native.reg(*wl["reg"])
+    vbytes = 4 * m * n
+    # the host-to-device rate of one whole copy of V (median of 3)
+    dst = torch.empty((m, n), dtype=torch.float32, device="cuda")
+    s = torch.cuda.current_stream()
+    ts = []
+    for _ in range(3):
+        a = torch.cuda.Event(enable_timing=True); b = torch.cuda.Event(enable_timing=True)
+        a.record(s); dst.copy_(Vh, non_blocking=True); b.record(s); b.synchronize()
+        ts.append(a.elapsed_time(b))
+    copy_ms = sorted(ts)[1]
+    h2d = vbytes / (copy_ms / 1e3)
+    log(f"[bench] host-to-device copy of V: {copy_ms:.2f} ms ({h2d / 1e9:.1f} GB/s)")
+    # resident FP32 fit for comparison (V already on the device)
+    W0 = torch.from_numpy(wl["W0"]).cuda(); H0 = torch.from_numpy(wl["Ht0"]).cuda()
+    res_ms, _, _, _ = timed_plan(native, torch, native.DeviceMatrix(dst), r, reg,
+                                 native.opts(max_inner=100, eps=1e-3), W0, H0, K, Wm)
+    del dst
+    torch.cuda.empty_cache()
+    opt_w = native.opts(max_outer=Wm, max_inner=100, eps=1e-3)
+    opt = native.opts(max_outer=K, max_inner=100, eps=1e-3)
+    W = W0.clone(); Ht = H0.clone()
+    if Wm:
+        native.fit_streamed(Vh, r, reg, opt_w, W, Ht, panel, want_trace=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st = native.fit_streamed(Vh, r, reg, opt, W, Ht, panel, want_trace=False)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms = el * 1e3 / K
+    # device buffers beyond W and Ht: two panels, P_W and its per-panel addend, the panel product
+    ldp = (min(panel, n) + 3) // 4 * 4
+    dev_bytes = 4 * (2 * m * ldp + 2 * m * r + min(panel, n) * r)
+    log(f"[bench] streamed: {ms:.2f} ms/step (copy floor {copy_ms * (K + 1) / K:.2f} ms), resident {res_ms:.2f} ms")
+    out = base_line(
+        "limited-memory dense NMF: column NNLS solves/s with V streamed from host memory",
+        (m + n) * K / el, "column NNLS solves/s", K, Wm, ms, "f32",
+        {"workload": "dense V 20000x10000 = W0 H0 + |N(0,0.05)|, Gamma(2,0.5) factors of inner dimension "
+                     "64, FP32 in page-locked host memory; r=64, L2=0.01 on W and H; eps=1e-3, "
+                     f"max_inner=100; panels of {panel} instances (columns of V); one step = one outer "
+                     "iteration (one read of V); the run's statistics add one more read",
+         "m": m, "n": n, "r": r, "panel_cols": panel},
+        V_bytes=vbytes, device_buffer_bytes=dev_bytes, h2d_copy_GBps=h2d / 1e9,
+        copy_floor_ms_per_step=copy_ms * (K + 1) / K, frac_of_copy_floor=copy_ms * (K + 1) / K / ms,
+        resident_fp32_ms_per_step=res_ms, kbar=st["kbar"], loss_after=st["loss"],
+    )
+    print(json.dumps(out), flush=True)
+
+
 def bench_serving(args, native, synth, torch, np):
     """The serving configuration at several offered loads."""
     loads = (0.3, 0.6, 0.9)
@@ -411,8 +471,10 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-load", type=float, default=0.5,
                     help="Poisson arrival rate as a fraction of the saturated request rate")
-    ap.add_argument("--workload", default="sparse", choices=["sparse", "dense", "batched", "serving"],
+    ap.add_argument("--workload", default="sparse", choices=["sparse", "dense", "batched", "serving", "streamed"],
                     help="sparse: the headline line (default); the others print supplementary lines")
+    ap.add_argument("--panel-cols", type=int, default=2048,
+                    help="instances per streamed panel (--workload streamed)")
     ap.add_argument("--fast-break", type=int, default=0,
                     help="Algorithm 3's fast-break over runs of this many columns (0: off)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -445,6 +507,8 @@ def main():
         return bench_batched(args, native, synth, torch, np)
     if args.workload == "serving":
         return bench_serving(args, native, synth, torch, np)
+    if args.workload == "streamed":
+        return bench_streamed(args, native, synth, torch, np)
     log("[bench] generating the sparse workload")
     t_gen = time.perf_counter()
     wl = synth.workload3()

@@ -209,6 +209,32 @@ NMF_API int nmf_plan_timers(const nmf_plan *p, double *ms, int64_t *calls);
 NMF_API int nmf_fit(const nmf_matrix *V, int32_t r, const nmf_reg *reg, const nmf_opts *opt, float *W,
             float *Ht, double *trace, nmf_stats *stats, void *stream);
 
+/* ---------------------------------------------------------------- limited internal memory
+ * Algorithm 2 in the limited-internal-memory form of Section 3.3 (the
+ * memory row of Table 1): V stays in HOST memory and each outer iteration
+ * reads it once, a panel of panel_cols instances (columns of V) at a time.
+ * Per panel J: the E-step's product (W'V_J)' and the NQPs of its columns of
+ * Ht against W'W + 2 l2_h I, then the panel's share V_J Ht_J of the M-step's
+ * product (the paper's sum of F_i V_i'), added in panel order.  The M-step
+ * reads no V: W <- NQP(Ht'Ht + 2 l2_w I, -V Ht + l1_w, W).  Same iteration as
+ * nmf_fit (H-update, then W-update from the new H); the products' sums are
+ * grouped by panel, so results agree with nmf_fit to FP32 rounding.
+ *   V_host   m x n row-major FP32 in host memory, leading dimension ld >= n.
+ *            Page-locked memory (hipHostMalloc, torch pin_memory) lets the
+ *            copy of the next panel overlap the work on the current one;
+ *            pageable memory works, with copies that block the host.
+ *   panel_cols >= 1 (capped at n); device memory beyond W and Ht is about
+ *            4 * (2 * m * panel_cols + 2 * m * r + panel_cols * r) bytes plus
+ *            scratch, whatever n is.
+ *   W, Ht    device, as in nmf_fit; trace, stats as in nmf_fit.
+ * opt->precision must be NMF_FP32 (NMF_E_UNSUPPORTED otherwise);
+ * fast_break_cols runs are formed within each panel; check_finite also scans
+ * each panel of V (for NaN/Inf and negatives) during the first pass.  The call
+ * synchronises `stream` before returning (it frees its buffers). */
+NMF_API int nmf_fit_streamed(const float *V_host, int64_t m, int64_t n, int64_t ld, int32_t r,
+                             const nmf_reg *reg, const nmf_opts *opt, int64_t panel_cols, float *W,
+                             float *Ht, double *trace, nmf_stats *stats, void *stream);
+
 /* Loss and objective of (V, W, Ht) in double precision (host outputs). */
 NMF_API int nmf_objective(const nmf_matrix *V, int32_t r, const nmf_reg *reg, const float *W,
                   const float *Ht, double *loss_host, double *objective_host, void *stream);

@@ -443,6 +443,7 @@ __global__ __launch_bounds__(256) void k_max_ordered(const double *__restrict__ 
 
 // ------------------------------------------------------------ host side
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+static size_t finish_scratch_bytes() { return 2 * align256(2 * 4096 * sizeof(double)); }
 
 size_t objective_scratch_bytes(const nmf_matrix *V, int r) {
     const int64_t m = V->rows, n = V->cols;
@@ -455,7 +456,7 @@ size_t objective_scratch_bytes(const nmf_matrix *V, int r) {
         b += align256((size_t)(G64_MAXB / G64_GROUP) * r * r * sizeof(double));  // group sums
         b += 2 * align256((size_t)r * r * sizeof(double));         // GW, GH
     }
-    b += align256(2 * 4096 * sizeof(double)) * 2;  // sums of W and H
+    b += finish_scratch_bytes();                  // sums of W and H
     b += align256(16 * sizeof(double));           // terms
     b += align256(2 * sizeof(double));            // out
     return b + 1024;
@@ -478,6 +479,10 @@ static hipError_t gram64(const float *A, int64_t k, int r, double *partial, doub
                        groups, (int64_t)ng, width, G);
     return hipGetLastError();
 }
+
+static hipError_t finish_objective(double *terms, int csr, const nmf_reg *reg, const float *W, int64_t m,
+                                   const float *Ht, int64_t n, int r, char *p, double *dev_out,
+                                   hipStream_t s);
 
 // Loss and J into dev_out[0..1] (device doubles); scratch of
 // objective_scratch_bytes().
@@ -524,6 +529,14 @@ hipError_t launch_objective(const nmf_matrix *V, int r, const nmf_reg *reg, cons
         hipLaunchKernelGGL(k_dot_ordered, dim3(1), dim3(256), 0, s, gw, gh, (int64_t)r * r,
                            terms + 3);
     }
+    return finish_objective(terms, V->kind == NMF_CSR ? 1 : 0, reg, W, m, Ht, n, r, p, dev_out, s);
+}
+
+// The regularisation sums of W and Ht into terms[4..7]; scratch of
+// finish_scratch_bytes().
+static hipError_t objective_sums(double *terms, const float *W, int64_t m, const float *Ht, int64_t n, int r,
+                                 char *p, hipStream_t s) {
+    auto take = [&](size_t bytes) { char *q = p; p += align256(bytes); return q; };
     double *sw = (double *)take(2 * 4096 * sizeof(double));
     double *sh = (double *)take(2 * 4096 * sizeof(double));
     int64_t bw = (m * r + 255) / 256, bh = (n * r + 255) / 256;
@@ -535,9 +548,67 @@ hipError_t launch_objective(const nmf_matrix *V, int r, const nmf_reg *reg, cons
     hipLaunchKernelGGL(k_sum_ordered, dim3(1), dim3(256), 0, s, sw, bw, (int64_t)2, (int64_t)1, terms + 5);
     hipLaunchKernelGGL(k_sum_ordered, dim3(1), dim3(256), 0, s, sh, bh, (int64_t)2, (int64_t)0, terms + 6);
     hipLaunchKernelGGL(k_sum_ordered, dim3(1), dim3(256), 0, s, sh, bh, (int64_t)2, (int64_t)1, terms + 7);
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1), 0, s, terms, V->kind == NMF_CSR ? 1 : 0,
-                       (double)reg->l1_w, (double)reg->l2_w, (double)reg->l1_h, (double)reg->l2_h,
-                       dev_out);
+    return hipGetLastError();
+}
+
+static hipError_t launch_finish(const double *terms, int csr, const nmf_reg *reg, double *dev_out,
+                                hipStream_t s) {
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1), 0, s, terms, csr, (double)reg->l1_w,
+                       (double)reg->l2_w, (double)reg->l1_h, (double)reg->l2_h, dev_out);
+    return hipGetLastError();
+}
+
+// The regularisation sums, then loss and J from terms[] (the loss terms
+// already in place); scratch of finish_scratch_bytes().
+static hipError_t finish_objective(double *terms, int csr, const nmf_reg *reg, const float *W, int64_t m,
+                                   const float *Ht, int64_t n, int r, char *p, double *dev_out,
+                                   hipStream_t s) {
+    hipError_t e = objective_sums(terms, W, m, Ht, n, r, p, s);
+    return e == hipSuccess ? launch_finish(terms, csr, reg, dev_out, s) : e;
+}
+
+// ------------------------------------------------------------ V in row or column panels
+// Streamed fits see V one panel at a time: each panel's sum of squared
+// errors goes to a slot, and the slots are summed in panel order.
+size_t loss_panel_scratch_bytes(int64_t rows, int64_t cols) {
+    return align256((size_t)((cols + LD_T - 1) / LD_T) * ((rows + LD_T - 1) / LD_T) * sizeof(double));
+}
+
+hipError_t launch_loss_panel(const float *V, int64_t ld, int64_t rows, int64_t cols, const float *W,
+                             const float *Ht, int r, double *scratch, double *slot, hipStream_t s) {
+    if (rows <= 0 || cols <= 0) {
+        hipLaunchKernelGGL(k_reduce_ordered, dim3(1), dim3(256), 0, s, (const double *)nullptr,
+                           (int64_t)0, 1, slot);  // an empty panel adds zero
+        return hipGetLastError();
+    }
+    const unsigned gx = (unsigned)((cols + LD_T - 1) / LD_T), gy = (unsigned)((rows + LD_T - 1) / LD_T);
+    const size_t lds = (size_t)2 * LD_T * r * sizeof(float);
+    hipLaunchKernelGGL(k_loss_dense, dim3(gx, gy), dim3(256), lds, s, V, ld, rows, cols, W, Ht, r, scratch);
+    hipLaunchKernelGGL(k_sum_ordered, dim3(1), dim3(256), 0, s, scratch, (int64_t)gx * gy, (int64_t)1,
+                       (int64_t)0, slot);
+    return hipGetLastError();
+}
+
+size_t objective_slots_scratch_bytes() { return align256(16 * sizeof(double)) + finish_scratch_bytes(); }
+
+hipError_t launch_objective_regs(const float *W, int64_t m, const float *Ht, int64_t n, int r, char *scratch,
+                                 hipStream_t s) {
+    double *terms = (double *)scratch;
+    hipLaunchKernelGGL(k_reduce_ordered, dim3(1), dim3(256), 0, s, (const double *)nullptr, (int64_t)0, 16,
+                       terms);  // zero the terms
+    return objective_sums(terms, W, m, Ht, n, r, scratch + align256(16 * sizeof(double)), s);
+}
+
+hipError_t launch_objective_slots(const double *slots, int64_t nslots, const nmf_reg *reg, char *scratch,
+                                  double *dev_out, hipStream_t s) {
+    double *terms = (double *)scratch;
+    hipLaunchKernelGGL(k_sum_ordered, dim3(1), dim3(256), 0, s, slots, nslots, (int64_t)1, (int64_t)0,
+                       terms + 0);
+    return launch_finish(terms, 0, reg, dev_out, s);
+}
+
+hipError_t launch_max_ordered(const double *in, int64_t n, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_max_ordered, dim3(1), dim3(256), 0, s, in, n, out);
     return hipGetLastError();
 }
 

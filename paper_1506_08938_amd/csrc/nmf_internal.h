@@ -176,6 +176,24 @@ hipError_t launch_objective(const nmf_matrix *V, int r, const nmf_reg *reg, cons
                             const float *Ht, char *scratch, double *dev_out, hipStream_t s);
 hipError_t launch_kkt(const float *G, int r, const float *P, float hsign, float hadd,
                       const float *X, int64_t c, double *partial, double *dev_out, hipStream_t s);
+// V seen one panel at a time: a panel's sum of squared errors (rows x cols
+// block of V at V with leading dimension ld, against W's rows and Ht's rows
+// of the panel) into *slot; scratch of loss_panel_scratch_bytes(rows, cols)
+size_t loss_panel_scratch_bytes(int64_t rows, int64_t cols);
+hipError_t launch_loss_panel(const float *V, int64_t ld, int64_t rows, int64_t cols, const float *W,
+                             const float *Ht, int r, double *scratch, double *slot, hipStream_t s);
+// Objective from panel sums, in two steps on one scratch (of
+// objective_slots_scratch_bytes()): launch_objective_regs takes the
+// regularisation sums of (W, Ht) as they are when it runs;
+// launch_objective_slots later adds the nslots panel sums in slot order and
+// writes loss and J (dev_out[0..1]).
+size_t objective_slots_scratch_bytes();
+hipError_t launch_objective_regs(const float *W, int64_t m, const float *Ht, int64_t n, int r, char *scratch,
+                                 hipStream_t s);
+hipError_t launch_objective_slots(const double *slots, int64_t nslots, const nmf_reg *reg, char *scratch,
+                                  double *dev_out, hipStream_t s);
+// *out = max of in[0..n) (single block)
+hipError_t launch_max_ordered(const double *in, int64_t n, double *out, hipStream_t s);
 
 // ------------------------------------------------------------------ fold-in basis
 }  // namespace nmfi
