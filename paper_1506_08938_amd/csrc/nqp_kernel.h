@@ -256,15 +256,38 @@ __device__ __forceinline__ float relu(float a) {
 #ifndef NMF_NQP_WPE
 #define NMF_NQP_WPE 0  // 0: occupancy from the table below
 #endif
+// The y update of a CD step changes one entry, y_p -= m.  Either a compare
+// and select per entry (0), or an FMA per entry with the lane's segment of
+// the unit vector e_p read from LDS (1): fma(-m, 1, y) = y - m at p, and
+// fma(-m, 0, y) = y elsewhere, bitwise the same result.  The LDS form costs
+// one FMA instead of three instructions per entry plus a few for the address
+// and 128-bit reads; measured faster from E = 12 on, slower below.
 #ifndef NMF_NQP_ONEHOT_LDS
-#define NMF_NQP_ONEHOT_LDS 0  // 0: compare/select (measured faster); 1: y update through the LDS unit vector
+#define NMF_NQP_ONEHOT_LDS -1  // -1: by E as measured; 0 or 1 forces a form
 #endif
+template <int E>
+constexpr int nqp_oh_mode() {
+    return NMF_NQP_ONEHOT_LDS >= 0 ? NMF_NQP_ONEHOT_LDS : (E >= 12 ? 1 : 0);
+}
 
-// LDS of one block: Q (R x SQ), sqrt-diagonal (R), unit-vector window (2R),
+// Unit-vector windows (form 1): four copies of nqp_oh_lw() floats, copy k
+// with its 1 at index R + k.  The lane's segment of e_p starts at offset
+// R + k + base - p of copy k = (p - base - R) mod 4, a multiple of 4, so it
+// is read with 16-byte-aligned loads.
+template <int E, int L>
+constexpr int nqp_oh_lw() {
+    return (2 * E * L + 8 + 3) / 4 * 4;
+}
+template <int E, int L>
+constexpr int nqp_oh_floats() {
+    return nqp_oh_mode<E>() == 1 ? 4 * nqp_oh_lw<E, L>() : 4;
+}
+
+// LDS of one block: Q (R x SQ), sqrt-diagonal (R), unit-vector windows,
 // and a few counters
 template <int E, int L>
 constexpr int nqp_lds_bytes() {
-    return (E * L * QLayout<E, L>::SQ + 3 * E * L) * 4 + 64;
+    return (E * L * QLayout<E, L>::SQ + E * L + nqp_oh_floats<E, L>()) * 4 + 64;
 }
 
 template <int E>
@@ -328,9 +351,7 @@ struct LdsFetch {
 // R x SQ) and its sqrt-diagonal sD (LDS): every group of L lanes solves
 // columns taken from `fetch` until none are left.  Adds the iterations of the
 // columns it finished (counted once per group) to my_inner.
-// sZ (LDS, 2R floats) holds a single 1 at index R: sZ + R + base - p is this
-// lane's segment of the unit vector e_p, so the coordinate-descent update of y
-// is one FMA per entry, fma(-m, 1, y) = y - m at p and y elsewhere.
+// sZ (LDS) holds the unit-vector windows of the y update (nqp_oh_mode).
 template <int E, int L, class Fetch>
 __device__ __forceinline__ void nqp_columns(const float *__restrict__ sQ,
                                             const float *__restrict__ sD,
@@ -492,18 +513,27 @@ __device__ __forceinline__ void nqp_columns(const float *__restrict__ sQ,
                 if (go) {
                     float row[E];
                     load_seg<E, L>(qseg + bi * QL::SQ, row);
-                    const float *onehot = sZ + (E * L) + base - bi;
+                    if constexpr (nqp_oh_mode<E>() == 1) {
+                        constexpr int R = E * L, E4 = (E + 3) / 4;
+                        const int k4 = (bi - base - R) & 3;
+                        const float *oh = sZ + k4 * nqp_oh_lw<E, L>() + (R + k4 + base - bi);
+                        float ohv[4 * E4];
 #pragma unroll
-                    for (int e = 0; e < E; e++) g[e] = fmaf(-bm, row[e], g[e]);
-#if NMF_NQP_ONEHOT_LDS
+                        for (int q = 0; q < E4; q++) {
+                            const float4 v = *(const float4 *)(oh + 4 * q);
+                            ohv[4 * q] = v.x; ohv[4 * q + 1] = v.y; ohv[4 * q + 2] = v.z; ohv[4 * q + 3] = v.w;
+                        }
 #pragma unroll
-                    for (int e = 0; e < E; e++) y[e] = fmaf(-bm, onehot[e], y[e]);
-#else
-                    (void)onehot;
-                    const int el = bi - base;  // the step's coordinate in this lane's segment, if any
+                        for (int e = 0; e < E; e++) g[e] = fmaf(-bm, row[e], g[e]);
 #pragma unroll
-                    for (int e = 0; e < E; e++) y[e] = (el == e) ? y[e] - bm : y[e];
-#endif
+                        for (int e = 0; e < E; e++) y[e] = fmaf(-bm, ohv[e], y[e]);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < E; e++) g[e] = fmaf(-bm, row[e], g[e]);
+                        const int el = bi - base;  // the step's coordinate in this lane's segment, if any
+#pragma unroll
+                        for (int e = 0; e < E; e++) y[e] = (el == e) ? y[e] - bm : y[e];
+                    }
                 }
             }
             // ------------------------------------------------ stopping rule
@@ -546,7 +576,10 @@ __device__ __forceinline__ void stage_q(const float *__restrict__ gram, int r, f
                                         float *sD, float *sZ) {
     using QL = QLayout<E, L>;
     constexpr int R = E * L;
-    for (int t = threadIdx.x; t < 2 * R; t += blockDim.x) sZ[t] = t == R ? 1.f : 0.f;
+    if constexpr (nqp_oh_mode<E>() == 1) {
+        constexpr int LW = nqp_oh_lw<E, L>();
+        for (int t = threadIdx.x; t < 4 * LW; t += blockDim.x) sZ[t] = (t % LW) == R + t / LW ? 1.f : 0.f;
+    }
     for (int i = threadIdx.x; i < R; i += blockDim.x) {
         const float d = i < r ? gram[(size_t)i * r + i] : 0.f;
         sD[i] = d > 0.f ? sqrtf(d) : 0.f;
@@ -574,7 +607,7 @@ __attribute__((amdgpu_waves_per_eu(nqp_waves_per_eu<E, L>(), 8))) void k_nqp(con
     constexpr int R = E * L;
     __shared__ __attribute__((aligned(16))) float sQ[R * QLayout<E, L>::SQ];
     __shared__ float sD[R];
-    __shared__ float sZ[2 * R];
+    __shared__ __attribute__((aligned(16))) float sZ[nqp_oh_floats<E, L>()];
     stage_q<E, L>(a.gram, a.r, sQ, sD, sZ);
     __syncthreads();
     const int unit = a.unit > 1 ? a.unit : 1;
@@ -598,7 +631,7 @@ __attribute__((amdgpu_waves_per_eu(nqp_waves_per_eu<E, L>(), 8))) void k_bnqp(
     constexpr int R = E * L;
     __shared__ __attribute__((aligned(16))) float sQ[R * QLayout<E, L>::SQ];
     __shared__ float sD[R];
-    __shared__ float sZ[2 * R];
+    __shared__ __attribute__((aligned(16))) float sZ[nqp_oh_floats<E, L>()];
     __shared__ unsigned int s_task, s_ctr;
     for (;;) {
         if (threadIdx.x == 0) {
