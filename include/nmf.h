@@ -195,15 +195,17 @@ NMF_API int nmf_plan_run(nmf_plan *p, float *W, float *Ht, int32_t outer, double
                  void *stream);
 NMF_API void nmf_plan_destroy(nmf_plan *p);
 
-/* Per-phase device time of nmf_plan_run, from HIP events recorded on the
- * run's stream around each phase's launches.  nmf_plan_profile(p, 1) clears
- * the totals and starts recording, (p, 0) stops.  nmf_plan_timers fills
- * ms[NMF_PHASES] (accumulated milliseconds) and calls[NMF_PHASES] (number of
- * timed phases) for the phases below; a phase covers all of its kernels in
- * one half-iteration. */
+/* Per-phase device time of nmf_plan_run.  nmf_plan_profile(p, mode) clears
+ * the totals and sets the mode: 0 stops; 1 records HIP events on the run's
+ * stream around each phase's launches (a phase covers all of its kernels in
+ * one half-iteration); 2 times the solve phase only, with the event pair
+ * attached to the solve kernel's own dispatch, so nothing is added to the
+ * stream between kernels.  nmf_plan_timers fills ms[NMF_PHASES]
+ * (accumulated milliseconds) and calls[NMF_PHASES] (number of timed
+ * phases) for the phases below. */
 #define NMF_PHASES 4
 enum { NMF_PHASE_GRAM = 0, NMF_PHASE_RESCALE = 1, NMF_PHASE_PRODUCT = 2, NMF_PHASE_SOLVE = 3 };
-NMF_API int nmf_plan_profile(nmf_plan *p, int32_t enable);
+NMF_API int nmf_plan_profile(nmf_plan *p, int32_t mode);
 NMF_API int nmf_plan_timers(const nmf_plan *p, double *ms, int64_t *calls);
 
 NMF_API int nmf_fit(const nmf_matrix *V, int32_t r, const nmf_reg *reg, const nmf_opts *opt, float *W,

@@ -219,7 +219,7 @@ struct nmf_plan {
     char *obj_scratch = nullptr;
     double *obj_out = nullptr, *kkt_partial = nullptr, *kkt_out = nullptr;
     // per-phase HIP-event timers
-    bool prof = false;
+    int prof = 0;  // 0 off; 1 events around every phase; 2 the solve's dispatch only
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
     size_t ev_used = 0;
@@ -442,7 +442,7 @@ struct PhaseMark {
     hipStream_t s;
     hipEvent_t a = nullptr;
     PhaseMark(nmf_plan *p_, int ph, hipStream_t s_) : p(p_), phase(ph), s(s_) {
-        if (p->prof && (a = next_event(p))) (void)hipEventRecord(a, s);
+        if (p->prof == 1 && (a = next_event(p))) (void)hipEventRecord(a, s);
     }
     ~PhaseMark() {
         if (!a) return;
@@ -508,6 +508,14 @@ static hipError_t half_update(nmf_plan *p, bool h_update, const float *A, float 
     q.max_inner = p->opt.max_inner; q.eps = p->opt.eps; q.ls_guard = p->opt.ls_guard ? 1 : 0;
     q.cold = 0; q.iters = nullptr; q.counter = p->counter; q.inner_total = p->inner_total;
     q.unit = p->opt.fast_break_cols;
+    if (p->prof == 2) {  // the solve's own dispatch records the pair
+        hipEvent_t a = next_event(p), b = a ? next_event(p) : nullptr;
+        if (a && b) {
+            q.ev_start = a;
+            q.ev_stop = b;
+            p->pending.push_back({NMF_PHASE_SOLVE, {a, b}});
+        }
+    }
     PhaseMark pm(p, NMF_PHASE_SOLVE, s);
     return launch_nqp(h_update ? p->var_h : p->var_w, q, s);
 }
@@ -713,9 +721,10 @@ extern "C" int nmf_foldin(const nmf_basis *B, const nmf_matrix *Vnew, float *Ht_
     return st;
 }
 
-extern "C" int nmf_plan_profile(nmf_plan *p, int32_t enable) {
+extern "C" int nmf_plan_profile(nmf_plan *p, int32_t mode) {
     if (!p) return fail(NMF_E_INVAL, "plan is NULL");
-    p->prof = enable != 0;
+    if (mode < 0 || mode > 2) return fail(NMF_E_INVAL, "profile mode must be 0, 1 or 2 (got %d)", mode);
+    p->prof = mode;
     for (int i = 0; i < NMF_PHASES; i++) { p->ms[i] = 0.0; p->calls[i] = 0; }
     p->pending.clear();
     p->ev_used = 0;

@@ -39,6 +39,9 @@ struct NqpParams {
     unsigned long long *counter;       // work counter; must be zero at launch
     unsigned long long *inner_total;   // optional accumulator of iterations
     int unit;  // columns per fast-break thread of computation (<= 1: off)
+    // host side (unused by the kernel): when set, the launch records these
+    // events with its own dispatch (start and end of the kernel)
+    hipEvent_t ev_start, ev_stop;
 };
 
 // Kernel variant (entries per lane E, lanes per column L).

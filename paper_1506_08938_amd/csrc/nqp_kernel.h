@@ -23,6 +23,7 @@
 // the other coordinates.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -696,7 +697,10 @@ hipError_t launch_nqp_t(const NqpParams &p, hipStream_t s) {
     const int64_t want = (p.ncols + cols_per_block - 1) / cols_per_block;
     const int64_t cap = (int64_t)nqp_blocks_per_cu(k_nqp<E, L>, block, cache) * device_cu_count();
     const int grid = (int)(want < cap ? want : cap);
-    hipLaunchKernelGGL((k_nqp<E, L>), dim3(grid), dim3(block), 0, s, p);
+    if (p.ev_start || p.ev_stop)
+        hipExtLaunchKernelGGL((k_nqp<E, L>), dim3(grid), dim3(block), 0, s, p.ev_start, p.ev_stop, 0u, p);
+    else
+        hipLaunchKernelGGL((k_nqp<E, L>), dim3(grid), dim3(block), 0, s, p);
     return hipGetLastError();
 }
 

@@ -317,7 +317,10 @@ class Plan:
     PHASES = ("gram", "rescale", "product", "solve")
 
     def profile(self, enable=True):
-        check(lib().nmf_plan_profile(self.h, 1 if enable else 0))
+        """True/1: events around every phase; 2: the solve kernel's own
+        dispatch only (nothing added between kernels); False/0: off."""
+        mode = 1 if enable is True else (0 if enable is False else int(enable))
+        check(lib().nmf_plan_profile(self.h, mode))
 
     def timers(self):
         ms = (ctypes.c_double * 4)(); calls = (ctypes.c_int64 * 4)()

@@ -254,6 +254,31 @@ def test_plan_runs_compose_and_are_deterministic():
     plan.close()
 
 
+def test_plan_profile_modes_time_without_changing_results():
+    nat = native()
+    wl = synth.workload1()
+    Vd = nat.DeviceMatrix(T(wl["V"]))
+    plan = nat.Plan(Vd, wl["r"], nat.reg(*wl["reg"]), nat.opts())
+    out = []
+    for mode in (0, 1, 2):
+        W, Ht = T(wl["W0"]), T(wl["Ht0"])
+        plan.profile(mode)
+        plan.run(W, Ht, 3)
+        tm = plan.timers()
+        plan.profile(False)
+        out.append((H(W), H(Ht), tm))
+    for W, Ht, _ in out[1:]:
+        assert np.array_equal(W, out[0][0]) and np.array_equal(Ht, out[0][1])
+    t1, t2 = out[1][2], out[2][2]
+    assert all(t1[k][1] == 6 for k in ("gram", "product", "solve"))
+    # mode 2: the solve only, timed by the kernel's own dispatch
+    assert t2["solve"][1] == 6 and t2["solve"][0] > 0
+    assert t2["gram"][1] == 0 and t2["product"][1] == 0
+    with pytest.raises(nat.NmfError):
+        plan.profile(3)
+    plan.close()
+
+
 # --------------------------------------------------------------------------- fold-in
 @pytest.mark.parametrize("r", [16, 128])
 def test_foldin_matches_oracle(r):
