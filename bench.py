@@ -265,6 +265,16 @@ def bench_dense(args, native, synth, torch, np):
         }
         log(f"[bench] dense {name}: {ms:.3f} ms/step, product {prod_ms:.3f} ms")
     del Vd, V
+    if args.skip_accuracy:
+        out = base_line(
+            "dense NMF column NNLS solves/s (FP32 and BF16 products)",
+            modes["bf16"]["solves_per_s"], "column NNLS solves/s", K, Wm, modes["bf16"]["ms_per_step"], "bf16",
+            {"workload": "dense V 20000x10000 = W0 H0 + |N(0,0.05)|, W0, H0 ~ Gamma(2,0.5) of inner dimension 64; "
+                         "r=64, L2=0.01 on W and H; eps=1e-3, max_inner=100; one step = one outer iteration; "
+                         "value = the BF16-product mode", "m": m, "n": n, "r": r},
+            modes=modes)
+        print(json.dumps(out), flush=True)
+        return
     # equal accuracy on the slice
     import oracle
     sl = synth.workload2_slice()
@@ -473,6 +483,8 @@ def main():
                     help="Poisson arrival rate as a fraction of the saturated request rate")
     ap.add_argument("--workload", default="sparse", choices=["sparse", "dense", "batched", "serving", "streamed"],
                     help="sparse: the headline line (default); the others print supplementary lines")
+    ap.add_argument("--skip-accuracy", action="store_true",
+                    help="--workload dense: skip the equal-accuracy leg on the slice")
     ap.add_argument("--panel-cols", type=int, default=2048,
                     help="instances per streamed panel (--workload streamed)")
     ap.add_argument("--fast-break", type=int, default=0,
