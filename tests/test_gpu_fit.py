@@ -94,19 +94,48 @@ def test_csr_product_matches_oracle_including_split_rows(m, n, per_row, r):
 
 
 # --------------------------------------------------------------------------- objective
-def test_objective_matches_oracle_dense_and_csr():
+# r covers the three gather widths of the CSR cross term (r % 4 == 0, r % 2
+# == 0, odd), one and two rank halves (r <= 64 < r) and the largest rank; the
+# row count covers many rows per wave of the fixed grid and a ragged tail
+@pytest.mark.parametrize("r", [1, 3, 6, 16, 65, 100, 128])
+def test_objective_matches_oracle_dense_and_csr(r):
     nat = native()
-    g = np.random.default_rng(0)
-    S = small_text(800, 500, 12, seed=1)
-    W = g.random((800, 16), dtype=np.float32) * 0.3; Ht = g.random((500, 16), dtype=np.float32) * 0.3
+    g = np.random.default_rng(r)
+    m, n = (9001, 500) if r in (16, 100) else (800, 500)
+    S = small_text(m, n, 12, seed=1)
+    W = g.random((m, r), dtype=np.float32) * 0.3; Ht = g.random((n, r), dtype=np.float32) * 0.3
     reg = (0.1, 0.2, 0.3, 0.4)
     for V in (S, S.toarray().astype(np.float32)):
         Vd = nat.DeviceMatrix(V if sp.issparse(V) else T(V))
-        loss, J = nat.objective(Vd, 16, nat.reg(*reg), T(W), T(Ht))
+        loss, J = nat.objective(Vd, r, nat.reg(*reg), T(W), T(Ht))
         lo = oracle.loss(V, W, Ht); Jo = oracle.objective(V, W, Ht, f32(reg))
-        print(f"objective {'csr' if sp.issparse(V) else 'dense'}: loss {loss:.10e} vs {lo:.10e}")
+        print(f"objective r={r} {'csr' if sp.issparse(V) else 'dense'}: loss {loss:.10e} vs {lo:.10e}")
         assert loss == pytest.approx(lo, rel=1e-12)
         assert J == pytest.approx(Jo, rel=1e-12)
+
+
+# The KKT residuals a fit reports against the oracle's, from the GPU's own
+# Gram and product of the last half-iterations (FP32 inputs, FP64 residual):
+# ranks with one and two rank halves in the KKT kernel, and column counts
+# that leave a ragged group of rows per wave.
+@pytest.mark.parametrize("r,m,n", [(7, 301, 203), (64, 1000, 333), (100, 1203, 517), (128, 777, 1029)])
+def test_fit_kkt_matches_oracle(r, m, n):
+    nat = native()
+    V = synth.dense_lowrank(m, n, r, 91 + r, "uniform", 0.01)
+    W0, Ht0 = synth.start_point(m, n, r, 92 + r)
+    reg = f32((0.01, 0.02, 0.03, 0.04))
+    Wd, Hd = T(W0), T(Ht0)
+    Vd = nat.DeviceMatrix(T(V))
+    _, st = nat.fit(Vd, r, nat.reg(*reg), nat.opts(max_outer=1, max_inner=5), Wd, Hd, want_trace=False)
+    # H-update: Gram of the start W, product with the start W, the new Ht
+    Gw = H(nat.gram(T(W0), reg[3])); Pw = H(nat.product(Vd, T(W0), 0))
+    kh = oracle.kkt(Gw, Pw, reg[2], H(Hd))[0]
+    # W-update: Gram of the new Ht, product with it, the new W
+    Gh = H(nat.gram(Hd, reg[1])); Ph = H(nat.product(Vd, Hd, 1))
+    kw = oracle.kkt(Gh, Ph, reg[0], H(Wd))[0]
+    print(f"kkt r={r}: H {st['kkt_h']:.6e} vs {kh:.6e}, W {st['kkt_w']:.6e} vs {kw:.6e}")
+    assert st["kkt_h"] == pytest.approx(kh, rel=1e-9)
+    assert st["kkt_w"] == pytest.approx(kw, rel=1e-9)
 
 
 # --------------------------------------------------------------------------- fit
