@@ -18,6 +18,8 @@
 // result is deterministic; a P entry's arithmetic depends only on its
 // slice's k range, never on the block that computes it.
 #include "kernels_common.h"
+#include <algorithm>
+
 #include "nmf_internal.h"
 
 namespace nmfi {
@@ -417,10 +419,13 @@ hipError_t launch_to_bf16(const float *x, int64_t rows, int64_t cols, int64_t ld
     return hipGetLastError();
 }
 
-// split-K factor: about 1024 blocks to fill the chip, at least 256 k per slice
-int dense_nsplit(int64_t C, int64_t K) {
+// split-K factor: enough blocks to fill the chip (measured: about 2048 for
+// the FP32 body, 1024 for the BF16 one, whose blocks stream twice the k per
+// stage), at least 256 k per slice
+int dense_nsplit(int64_t C, int64_t K, bool bf16) {
     const int64_t rb = (C + DENSE_BM - 1) / DENSE_BM;
-    int64_t ns = (1024 + rb - 1) / rb;
+    const int64_t target = bf16 ? 1024 : 2048;
+    int64_t ns = (target + rb - 1) / rb;
     const int64_t maxs = (K + 255) / 256;
     if (ns > maxs) ns = maxs;
     if (ns < 1) ns = 1;
@@ -429,8 +434,8 @@ int dense_nsplit(int64_t C, int64_t K) {
 }
 
 // slice length: a multiple of 64 (both stage depths)
-int64_t dense_kchunk(int64_t C, int64_t K) {
-    const int ns = dense_nsplit(C, K);
+int64_t dense_kchunk(int64_t C, int64_t K, bool bf16) {
+    const int ns = dense_nsplit(C, K, bf16);
     int64_t kchunk = (K + ns - 1) / ns;
     kchunk = ((kchunk + 63) / 64) * 64;
     return kchunk < 64 ? 64 : kchunk;
@@ -440,13 +445,14 @@ int64_t dense_kchunk(int64_t C, int64_t K) {
 // lda16 with lda16 = max(m, n) rounded up to 64).
 static size_t dense_partial_bytes(int64_t m, int64_t n, int r) {
     // slices actually used (a single slice writes P directly)
-    auto used = [](int64_t C, int64_t K) {
-        const int64_t kc = dense_kchunk(C, K);
+    auto used = [](int64_t C, int64_t K, bool bf16) {
+        const int64_t kc = dense_kchunk(C, K, bf16);
         const int64_t ns = K > 0 ? (K + kc - 1) / kc : 0;
         return ns > 1 ? ns * C : 0;
     };
-    const int64_t a = used(n, m), b = used(m, n);
-    return (((size_t)(a > b ? a : b) * r * sizeof(float)) + 255) & ~(size_t)255;
+    int64_t most = 0;
+    for (bool bf16 : {false, true}) most = std::max(most, std::max(used(n, m, bf16), used(m, n, bf16)));
+    return (((size_t)most * r * sizeof(float)) + 255) & ~(size_t)255;
 }
 static int64_t dense_lda16(int64_t m, int64_t n) {
     const int64_t k = m > n ? m : n;
@@ -485,7 +491,7 @@ hipError_t launch_dense_product(const void *V, int bf16, int64_t m, int64_t n, i
     const int64_t C = h_update ? n : m, K = h_update ? m : n;
     if (C == 0) return hipSuccess;
     if (K == 0) return hipErrorInvalidValue;  // callers reject empty V
-    const int64_t kchunk = dense_kchunk(C, K);
+    const int64_t kchunk = dense_kchunk(C, K, bf16 != 0);
     const int nsplit = (int)((K + kchunk - 1) / kchunk);
     float *out = nsplit > 1 ? scratch : P;
     const int NT = (r + 31) / 32;
