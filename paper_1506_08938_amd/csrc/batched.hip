@@ -124,8 +124,9 @@ extern "C" int nmf_fit_batched(int32_t count, const nmf_problem *probs, const nm
             const bool H = h == 0;
             const int64_t k = H ? m : n, C = H ? n : m;
             const float *A = H ? q.W : q.Ht;
+            const int64_t grows = gram_rows(k);
             BGramProb g{A, k, r, H ? q.reg.l2_h : q.reg.l2_w, (float *)dptr(slot[p].part),
-                        (float *)dptr(slot[p].G), (int)((k + BGRAM_ROWS - 1) / BGRAM_ROWS)};
+                        (float *)dptr(slot[p].G), (int)((k + grows - 1) / grows), grows};
             hl[h].gram.push_back(g);
             for (int c = 0; c < g.nchunks; c++) hl[h].gram_items.push_back({p, c});
             // BF16 reads the copy along k: V16t (n x m) for the H-update, V16 for the W-update

@@ -112,15 +112,17 @@ hipError_t launch_to_bf16(const float *x, int64_t rows, int64_t cols, int64_t ld
 struct BItem {
     int32_t prob, idx;
 };
-constexpr int BGRAM_ROWS = 512;  // rows of A per Gram work item (solo and batched)
+constexpr int BGRAM_ROWS = 512;  // rows of A per Gram work item (at least; solo and batched)
+int64_t gram_rows(int64_t k);     // rows per Gram work item for k rows of A
 struct BGramProb {
     const float *A;
     int64_t k;
     int r;
     float l2;
-    float *partial;  // ceil(k / BGRAM_ROWS) partials of NTILE * 1024 floats
+    float *partial;  // ceil(k / rows) partials of NTILE * 1024 floats
     float *G;        // r x r
     int nchunks;
+    int64_t rows;    // rows of A per work item: gram_rows(k)
 };
 struct BProdProb {
     const void *V;  // FP32: V (m x n, ld); BF16: the copy read along k (V16 for

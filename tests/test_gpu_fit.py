@@ -50,6 +50,19 @@ def test_gram_matches_oracle(r, k):
     assert errb < 1e-2
 
 
+# tall A: blocks of about k / 256 rows (one round of blocks), ragged last block
+@pytest.mark.parametrize("r,k", [(100, 150001), (128, 200000), (7, 131073)])
+def test_gram_tall_matches_oracle(r, k):
+    nat = native()
+    A = np.random.default_rng(r + k).random((k, r), dtype=np.float32)
+    Go = oracle.gram(A, 0.01)
+    Gg = H(nat.gram(T(A), 0.01))
+    err = np.abs(Gg - Go).max() / np.abs(Go).max()
+    print(f"gram r={r} k={k}: fp32 {err:.2e}")
+    assert np.array_equal(Gg, Gg.T)
+    assert err < 2e-6 * np.sqrt(k / 256), err
+
+
 # --------------------------------------------------------------------------- products
 @pytest.mark.parametrize("m,n,r", [(1, 1, 1), (37, 23, 5), (200, 150, 10), (1000, 777, 64),
                                    (300, 5000, 100), (129, 65, 128), (2048, 1536, 64),
