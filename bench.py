@@ -247,7 +247,8 @@ def bench_dense(args, native, synth, torch, np):
     modes = {}
     for prec, name in ((0, "fp32"), (1, "bf16")):
         ms, ph, tm, st = timed_plan(native, torch, Vd, r, reg,
-                                    native.opts(max_inner=100, eps=1e-3, precision=prec), W0, H0, K, Wm)
+                                    native.opts(max_inner=100, eps=1e-3, precision=prec, lanes=args.lanes),
+                                    W0, H0, K, Wm)
         vbytes = (4 if prec == 0 else 2) * m * n
         # per product launch: V once, the fixed factor once, the output once
         prod_bytes = vbytes + 4 * (m + n) * r // 2 + 4 * (m + n) * r // 2
@@ -483,6 +484,8 @@ def main():
                     help="Poisson arrival rate as a fraction of the saturated request rate")
     ap.add_argument("--workload", default="sparse", choices=["sparse", "dense", "batched", "serving", "streamed"],
                     help="sparse: the headline line (default); the others print supplementary lines")
+    ap.add_argument("--lanes", type=int, default=0,
+                    help="solve layout: lanes per column (0: the tuned table)")
     ap.add_argument("--skip-accuracy", action="store_true",
                     help="--workload dense: skip the equal-accuracy leg on the slice")
     ap.add_argument("--panel-cols", type=int, default=2048,
@@ -531,7 +534,7 @@ def main():
 
     Vd = native.DeviceMatrix(V, with_transpose=False)  # CSR(V') is built on the device
     reg = native.reg(*wl["reg"])
-    opt = native.opts(max_inner=100, eps=1e-3, ls_guard=1, fast_break_cols=args.fast_break)
+    opt = native.opts(max_inner=100, eps=1e-3, ls_guard=1, fast_break_cols=args.fast_break, lanes=args.lanes)
     plan = native.Plan(Vd, r, reg, opt)
     W = torch.from_numpy(wl["W0"]).cuda()
     Ht = torch.from_numpy(wl["Ht0"]).cuda()
