@@ -8,8 +8,11 @@ measurement, and stays a fixed function of (r, ncols), so results are
 reproducible run to run.
 
 The instances are shaped like the alternating fit's subproblems: Gamma =
-A'A + 2*l2*I with A ~ U[0,1) of 4r rows, h = -A'B + l1, a warm start near
-the solution (the previous outer iteration's), max_inner 100, eps 1e-3.
+A'A + 2*l2*I with A ~ U[0,1) of 4r rows, h = -A'B + l1, max_inner 100, eps
+1e-3, from two start points: near the solution (1% off, as late in a fit:
+about one iteration per column) and mid-fit (each entry scaled by U[0.5,
+1.5) plus 10% of the mean, several iterations per column and a longer tail
+of slow columns).  A layout's score is the sum of its two times.
 
 Usage (on the GPU):  python -m paper_1506_08938_amd.autotune OUT_DIR
 writes OUT_DIR/nqp_tuned.h and OUT_DIR/nqp_tuned.json;
@@ -43,8 +46,10 @@ def _instance(r, ncols, torch, native, synth):
     g = torch.Generator(device="cuda")
     g.manual_seed(r * 7919 + ncols)
     Xw = (X + 0.01 * torch.rand(X.shape, device="cuda", generator=g)).contiguous()
+    scale = torch.rand(X.shape, device="cuda", generator=g) + 0.5
+    Xm = (X * scale + 0.1 * X.mean() * torch.rand(X.shape, device="cuda", generator=g)).contiguous()
     torch.cuda.synchronize()
-    return G, h, Xw
+    return G, h, Xw, Xm
 
 
 def _time(G, h, X0, lanes, torch, native):
@@ -81,18 +86,21 @@ def sweep(log=print):
     table = {}
     for r in RANKS:
         for c in COLS:
-            G, h, X0 = _instance(r, c, torch, native, synth)
-            times = {}
+            G, h, Xw, Xm = _instance(r, c, torch, native, synth)
+            times, parts = {}, {}
             for L in LANES:
                 try:
                     native.layout(r, c, L)
                 except native.NmfError:
                     continue
-                times[L] = _time(G, h, X0, L, torch, native)
+                tn = _time(G, h, Xw, L, torch, native)
+                tm = _time(G, h, Xm, L, torch, native)
+                times[L] = tn + tm
+                parts[L] = (tn, tm)
             best = choose(times)
-            table[(r, c)] = (best, times)
+            table[(r, c)] = (best, times, parts)
             log(f"r={r:4d} ncols={c:7d} " +
-                " ".join(f"L{L}={t:.3f}ms" for L, t in times.items()) + f"  -> L={best}")
+                " ".join(f"L{L}={a:.3f}+{b:.3f}ms" for L, (a, b) in parts.items()) + f"  -> L={best}")
     return table
 
 
@@ -116,8 +124,9 @@ def write(table, out_dir, command):
     with open(os.path.join(out_dir, "nqp_tuned.h"), "w") as f:
         f.write("\n".join(lines))
     with open(os.path.join(out_dir, "nqp_tuned.json"), "w") as f:
-        json.dump({f"{r},{c}": {"best": b, "ms": {str(L): t for L, t in ts.items()}}
-                   for (r, c), (b, ts) in table.items()}, f, indent=1)
+        json.dump({f"{r},{c}": {"best": v[0], "ms": {str(L): t for L, t in v[1].items()},
+                                "ms_near_mid": {str(L): list(p) for L, p in (v[2] if len(v) > 2 else {}).items()}}
+                   for (r, c), v in table.items()}, f, indent=1)
 
 
 def from_json(path):
@@ -128,7 +137,8 @@ def from_json(path):
     for key, v in raw.items():
         r, c = (int(x) for x in key.split(","))
         times = {int(L): t for L, t in v["ms"].items()}
-        table[(r, c)] = (choose(times), times)
+        parts = {int(L): tuple(p) for L, p in v.get("ms_near_mid", {}).items()}
+        table[(r, c)] = (choose(times), times, parts)
     return table
 
 
