@@ -28,7 +28,10 @@ __device__ __forceinline__ void spmm_range(int start, int end, const int32_t *__
                                            float (&acc)[NV][VEC]) {
     const int lane = threadIdx.x & 63;
     constexpr int NPW = 64 / LPN;
-    constexpr int U = NPW >= 16 ? 1 : 16 / NPW;  // entries per slot per trip
+#ifndef NMF_SPMM_TRIP
+#define NMF_SPMM_TRIP 16
+#endif
+    constexpr int U = NPW >= NMF_SPMM_TRIP ? 1 : NMF_SPMM_TRIP / NPW;  // entries per slot per trip
     const int slot = lane / LPN, part = lane % LPN;
     for (int b = start; b < end; b += 64) {
         const int nb = min(64, end - b);
@@ -45,28 +48,37 @@ __device__ __forceinline__ void spmm_range(int start, int end, const int32_t *__
                     float, __builtin_amdgcn_ds_bpermute(j << 2, __builtin_bit_cast(int, my_cv)));
                 if (j >= nb) cv[u] = 0.f, ci[u] = -1;
             }
+            // every gather of the trip is issued before the first FMA: entries
+            // past the chunk's end read row 0 with weight 0, and lanes past r
+            // read column 0 into sums that are never written (they add
+            // exactly nothing to the written ones)
+            float av[U][NV][VEC];
 #pragma unroll
             for (int u = 0; u < U; u++) {
-                if (ci[u] < 0) continue;
-                const float *arow = A + (int64_t)ci[u] * r;
+                const float *arow = A + (int64_t)(ci[u] < 0 ? 0 : ci[u]) * r;
 #pragma unroll
                 for (int q = 0; q < NV; q++) {
                     const int col0 = (q * LPN + part) * VEC;
-                    if (col0 < r) {
-                        if constexpr (VEC == 4) {
-                            const f32x4 a4 = *(const f32x4 *)(arow + col0);
+                    const int cc = col0 < r ? col0 : 0;
+                    if constexpr (VEC == 4) {
+                        const f32x4 a4 = *(const f32x4 *)(arow + cc);
 #pragma unroll
-                            for (int v = 0; v < 4; v++) acc[q][v] = fmaf(cv[u], a4[v], acc[q][v]);
-                        } else if constexpr (VEC == 2) {
-                            const f32x2 a2 = *(const f32x2 *)(arow + col0);
-                            acc[q][0] = fmaf(cv[u], a2[0], acc[q][0]);
-                            acc[q][1] = fmaf(cv[u], a2[1], acc[q][1]);
-                        } else {
-                            acc[q][0] = fmaf(cv[u], arow[col0], acc[q][0]);
-                        }
+                        for (int v = 0; v < 4; v++) av[u][q][v] = a4[v];
+                    } else if constexpr (VEC == 2) {
+                        const f32x2 a2 = *(const f32x2 *)(arow + cc);
+                        av[u][q][0] = a2[0];
+                        av[u][q][1] = a2[1];
+                    } else {
+                        av[u][q][0] = arow[cc];
                     }
                 }
             }
+#pragma unroll
+            for (int u = 0; u < U; u++)
+#pragma unroll
+                for (int q = 0; q < NV; q++)
+#pragma unroll
+                    for (int v = 0; v < VEC; v++) acc[q][v] = fmaf(cv[u], av[u][q][v], acc[q][v]);
         }
     }
 }
