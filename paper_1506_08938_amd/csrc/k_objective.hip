@@ -137,7 +137,7 @@ __global__ __launch_bounds__(256) void k_loss_csr(const int32_t *__restrict__ ro
                 vl = vals[tb + lane];
                 vv = fma((double)vl, (double)vl, vv);
             }
-            // entry q + EPL u + half (past the end: no load, weight 0)
+            // entry q + EPL u + half
             for (int q = 0; q < cnt; q += EPL * LOSS_CSR_UNROLL) {
                 float hv[LOSS_CSR_UNROLL][NA];
                 float w[LOSS_CSR_UNROLL];
@@ -155,16 +155,20 @@ __global__ __launch_bounds__(256) void k_loss_csr(const int32_t *__restrict__ ro
                         w[u] = lane_f(vl, src);
                     }
                     w[u] = in ? w[u] : 0.f;
+                    // unconditional loads, so that all of the trip's are in
+                    // flight at once: past the row's end the weight is 0 (on a
+                    // valid row), and lanes past r read column 0 into sums
+                    // that are never used
                     const float *hr = Ht + (int64_t)j * r;
                     if (VEC == 4) {
-                        float4 x = (ok && in) ? *(const float4 *)(hr + ca[0]) : make_float4(0.f, 0.f, 0.f, 0.f);
+                        const float4 x = *(const float4 *)(hr + (ok ? ca[0] : 0));
                         hv[u][0] = x.x; hv[u][1] = x.y; hv[u][2 % NA] = x.z; hv[u][3 % NA] = x.w;
                     } else if (VEC == 2) {
-                        float2 x = (ok && in) ? *(const float2 *)(hr + ca[0]) : make_float2(0.f, 0.f);
+                        const float2 x = *(const float2 *)(hr + (ok ? ca[0] : 0));
                         hv[u][0] = x.x; hv[u][1] = x.y;
                     } else {
-                        hv[u][0] = (in && ca[0] < r) ? hr[ca[0]] : 0.f;
-                        hv[u][1 % NA] = (in && ca[1 % NA] < r) ? hr[ca[1 % NA]] : 0.f;
+                        hv[u][0] = hr[ca[0] < r ? ca[0] : 0];
+                        hv[u][1 % NA] = hr[ca[1 % NA] < r ? ca[1 % NA] : 0];
                     }
                 }
 #pragma unroll
