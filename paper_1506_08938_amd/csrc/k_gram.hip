@@ -54,16 +54,27 @@ __device__ __forceinline__ void gram_partial_rows(const float *__restrict__ A, i
     if constexpr (PREC == NMF_BF16) {
         for (int64_t t = s0; t < s1; t += 16) {
             bf16x8 v[NT];
+            // loads from clamped (valid) addresses, zeroed after: all of the
+            // step's loads are in flight together
+            float f[NT][8];
 #pragma unroll
             for (int c = 0; c < NT; c++) {
                 const int a = c * 32 + col;
-                float f[8];
 #pragma unroll
                 for (int q = 0; q < 8; q++) {
                     const int64_t row = t + half * 8 + q;
-                    f[q] = (row < s1 && a < r) ? A[row * r + a] : 0.f;
+                    f[c][q] = A[(row < s1 ? row : s0) * r + (a < r ? a : 0)];
                 }
-                v[c] = pack_bf16x8(f);
+            }
+#pragma unroll
+            for (int c = 0; c < NT; c++) {
+                const int a = c * 32 + col;
+#pragma unroll
+                for (int q = 0; q < 8; q++) {
+                    const int64_t row = t + half * 8 + q;
+                    if (!(row < s1 && a < r)) f[c][q] = 0.f;
+                }
+                v[c] = pack_bf16x8(f[c]);
             }
             int ti = 0;
 #pragma unroll

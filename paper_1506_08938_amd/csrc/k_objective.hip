@@ -29,10 +29,14 @@ __global__ __launch_bounds__(256) void k_loss_dense(const float *__restrict__ V,
     __shared__ double red[256];
     const int tid = threadIdx.x;
     const int64_t i0 = (int64_t)blockIdx.y * LD_T, j0 = (int64_t)blockIdx.x * LD_T;
+    // loads from clamped (valid) rows, zeroed after, so that they overlap
+#pragma unroll 4
     for (int e = tid; e < LD_T * r; e += 256) {
         const int row = e / r, a = e - row * r;
-        Ws[e] = (i0 + row < m) ? W[(i0 + row) * r + a] : 0.f;
-        Hs[e] = (j0 + row < n) ? Ht[(j0 + row) * r + a] : 0.f;
+        const float w = W[(i0 + row < m ? i0 + row : i0) * r + a];
+        const float h = Ht[(j0 + row < n ? j0 + row : j0) * r + a];
+        Ws[e] = (i0 + row < m) ? w : 0.f;
+        Hs[e] = (j0 + row < n) ? h : 0.f;
     }
     __syncthreads();
     const int ty = tid >> 4, tx = tid & 15;
@@ -52,6 +56,15 @@ __global__ __launch_bounds__(256) void k_loss_dense(const float *__restrict__ V,
 #pragma unroll
             for (int q = 0; q < 4; q++) acc[p][q] = fma(wv[p], hv[q], acc[p][q]);
     }
+    // the sixteen loads of V first (clamped rows and columns), then the sums
+    float vv[4][4];
+#pragma unroll
+    for (int p = 0; p < 4; p++)
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const int64_t i = i0 + 4 * ty + p, j = j0 + 4 * tx + q;
+            vv[p][q] = V[(i < m ? i : i0) * ld + (j < n ? j : j0)];
+        }
     double s = 0.0;
 #pragma unroll
     for (int p = 0; p < 4; p++)
@@ -59,7 +72,7 @@ __global__ __launch_bounds__(256) void k_loss_dense(const float *__restrict__ V,
         for (int q = 0; q < 4; q++) {
             const int64_t i = i0 + 4 * ty + p, j = j0 + 4 * tx + q;
             if (i < m && j < n) {
-                const double e = (double)V[i * ld + j] - acc[p][q];
+                const double e = (double)vv[p][q] - acc[p][q];
                 s = fma(e, e, s);
             }
         }
@@ -376,15 +389,21 @@ __global__ __launch_bounds__(256) void k_kkt(const float *__restrict__ G, int r,
     for (int64_t j0 = ((int64_t)blockIdx.x * 4 + wave) * KKT_ROWS; j0 < c; j0 += step) {
         float x0[KKT_ROWS], x1[KKT_ROWS];
         double g0[KKT_ROWS], g1[KKT_ROWS];
+        // the group's loads from clamped (valid) rows and columns first
+        float xa[KKT_ROWS], xb[KKT_ROWS], pa[KKT_ROWS], pb[KKT_ROWS];
 #pragma unroll
         for (int k = 0; k < KKT_ROWS; k++) {
-            const int64_t j = j0 + k;
-            const bool in = j < c;
+            const int64_t j = j0 + k < c ? j0 + k : j0;
             const float *xr = X + j * r, *pr = P + j * r;
-            x0[k] = (in && has0) ? xr[lane] : 0.f;
-            x1[k] = (in && has1) ? xr[lane + 64] : 0.f;
-            g0[k] = (in && has0) ? (double)hsign * (double)pr[lane] + (double)hadd : 0.0;
-            g1[k] = (in && has1) ? (double)hsign * (double)pr[lane + 64] + (double)hadd : 0.0;
+            xa[k] = xr[c0]; xb[k] = xr[c1]; pa[k] = pr[c0]; pb[k] = pr[c1];
+        }
+#pragma unroll
+        for (int k = 0; k < KKT_ROWS; k++) {
+            const bool in = j0 + k < c;
+            x0[k] = (in && has0) ? xa[k] : 0.f;
+            x1[k] = (in && has1) ? xb[k] : 0.f;
+            g0[k] = (in && has0) ? (double)hsign * (double)pa[k] + (double)hadd : 0.0;
+            g1[k] = (in && has1) ? (double)hsign * (double)pb[k] + (double)hadd : 0.0;
         }
         for (int b = 0; b < r0; b++) {
             const double ga = (double)gt[b * r + c0];
