@@ -599,13 +599,29 @@ __device__ __forceinline__ void stage_q(const float *__restrict__ gram, int r, f
         sD[i] = d > 0.f ? sqrtf(d) : 0.f;
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < R * R; t += blockDim.x) {
-        const int i = t / R, j = t - (t / R) * R;
-        float v;
-        if (i == j) v = 1.f;
-        else if (i >= r || j >= r || sD[i] == 0.f || sD[j] == 0.f) v = 0.f;
-        else v = gram[(size_t)i * r + j] / (sD[i] * sD[j]);
-        sQ[i * QL::SQ + QL::col(j)] = v;
+    // four entries per thread per trip, their loads (from clamped, valid
+    // addresses) issued together
+    constexpr int UN = 4;
+    for (int t0 = threadIdx.x; t0 < R * R; t0 += UN * blockDim.x) {
+        float gv[UN];
+#pragma unroll
+        for (int u = 0; u < UN; u++) {
+            const int t = t0 + u * blockDim.x;
+            const int i = t / R, j = t - (t / R) * R;
+            const bool ok = t < R * R && i < r && j < r;
+            gv[u] = gram[ok ? (size_t)i * r + j : 0];
+        }
+#pragma unroll
+        for (int u = 0; u < UN; u++) {
+            const int t = t0 + u * blockDim.x;
+            if (t >= R * R) break;
+            const int i = t / R, j = t - (t / R) * R;
+            float v;
+            if (i == j) v = 1.f;
+            else if (i >= r || j >= r || sD[i] == 0.f || sD[j] == 0.f) v = 0.f;
+            else v = gv[u] / (sD[i] * sD[j]);
+            sQ[i * QL::SQ + QL::col(j)] = v;
+        }
     }
 }
 
