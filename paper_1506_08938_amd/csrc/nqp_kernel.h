@@ -416,28 +416,24 @@ __device__ __forceinline__ void nqp_columns(const float *__restrict__ sQ,
                     float q[E];
                     const float *prow = a.P + col * (int64_t)a.ldp;
                     const float *xrow = a.X + col * (int64_t)a.ldx;
-                    // every load of the column issued before the first use
-                    // (a pad coordinate reads entry 0, then takes 0)
-                    float pv[E], xv0[E];
+                    // The loads of the P row are issued together (a pad
+                    // coordinate reads entry 0, then takes 0); those of the X
+                    // row one after another: issued together, they raised the
+                    // kernel's HBM reads and writes of X rows (measured: 2.3x
+                    // the fetched and 3x the written bytes), at the same speed.
+                    float pv[E];
 #pragma unroll
                     for (int e = 0; e < E; e++) {
                         const int i = base + e;
                         pv[e] = prow[i < r ? i : 0];
-                        xv0[e] = 0.f;
-                    }
-                    if (!a.cold) {
-#pragma unroll
-                        for (int e = 0; e < E; e++) {
-                            const int i = base + e;
-                            xv0[e] = xrow[i < r ? i : 0];
-                        }
                     }
 #pragma unroll
                     for (int e = 0; e < E; e++) {
                         const int i = base + e;
                         const float ds = sD[i];
+                        float xv = 0.f;
+                        if (i < r && !a.cold) xv = xrow[i];
                         const float hv = i < r ? fmaf(a.hsign, pv[e], a.hadd) : 0.f;
-                        const float xv = i < r ? xv0[e] : 0.f;
                         y[e] = ds > 0.f ? xv * ds : 0.f;
                         q[e] = ds > 0.f ? hv / ds : 1.f;
                     }
