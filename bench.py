@@ -492,6 +492,8 @@ def main():
                     help="instances per streamed panel (--workload streamed)")
     ap.add_argument("--fast-break", type=int, default=0,
                     help="Algorithm 3's fast-break over runs of this many columns (0: off)")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"],
+                    help="sparse workload: float32 products, or BF16 gathers and Gram (the solve stays float32)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 1 GiB device buffer (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -534,7 +536,9 @@ def main():
 
     Vd = native.DeviceMatrix(V, with_transpose=False)  # CSR(V') is built on the device
     reg = native.reg(*wl["reg"])
-    opt = native.opts(max_inner=100, eps=1e-3, ls_guard=1, fast_break_cols=args.fast_break, lanes=args.lanes)
+    bf16 = args.precision == "bf16"
+    opt = native.opts(max_inner=100, eps=1e-3, ls_guard=1, fast_break_cols=args.fast_break, lanes=args.lanes,
+                      precision=native.NMF_BF16 if bf16 else native.NMF_FP32)
     plan = native.Plan(Vd, r, reg, opt)
     W = torch.from_numpy(wl["W0"]).cuda()
     Ht = torch.from_numpy(wl["Ht0"]).cuda()
@@ -591,13 +595,16 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "bf16" if bf16 else "f32",
         "data": "synthetic",
         "config": {
             "workload": "sparse text-like CSR V 200000x100000, 100 Zipf(1.1) columns per row "
                         "(0.1% density), values log(1+Poisson(3)), r=100, L1=0.1 on H, L2=0.01 "
                         "on W, eps=1e-3, max_inner=100; one step = one outer iteration"
-                        + (f"; fast-break over runs of {args.fast_break} columns" if args.fast_break > 1 else ""),
+                        + (f"; fast-break over runs of {args.fast_break} columns" if args.fast_break > 1 else "")
+                        + ("; BF16 products: row gathers from a BF16 copy of the fixed factor and a BF16 "
+                           "Gram, float32 accumulation and solve (hot columns' dense product float32)"
+                           if bf16 else ""),
             "m": m, "n": n, "nnz": int(V.nnz), "r": r,
         },
         "roofline": {

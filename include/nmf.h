@@ -96,7 +96,11 @@ typedef struct {
  * 1 rejects a line-search step that would raise the objective (the literal
  * projected step of Algorithm 3 can), 0 keeps the literal step.  precision:
  * NMF_FP32 or NMF_BF16 for the Gram and data products (the solve is always
- * float32).  objective_every: compute the loss every s outer iterations
+ * float32, products are accumulated in float32).  BF16 with dense V: V and
+ * the fixed factor in BF16 on the matrix cores (BF16 copies of V made once
+ * per plan).  BF16 with CSR V: the row gathers read a BF16 copy of the fixed
+ * factor (values stay float32); the dense product of the hot columns stays
+ * float32.  objective_every: compute the loss every s outer iterations
  * (0 = only when a trace or stats are requested, at the end).  check_finite:
  * scan inputs for NaN/Inf (and V for negatives) before running.  lanes:
  * lanes of a wavefront that cooperate on one column in the solve kernel
@@ -270,7 +274,9 @@ NMF_API int nmf_fit_batched(int32_t count, const nmf_problem *probs, const nmf_o
  * v of Vnew (m x c), x = argmin_{x>=0} 0.5||v - W x||^2 + l1 1'x + l2||x||^2,
  * started from x0 = 0.
  * nmf_basis_create copies W (m x r, device) and computes Gamma = W'W + 2 l2 I
- * and its rescale once.  nmf_foldin takes Vnew dense (m x c) or sparse given
+ * and its rescale once; with opt->precision = NMF_BF16 the Gram is formed in
+ * BF16 and sparse requests gather from a BF16 copy of W (dense requests'
+ * products stay float32).  nmf_foldin takes Vnew dense (m x c) or sparse given
  * as CSR(Vnew') (the t_* arrays, c rows over m columns) and writes
  * Ht_new (c x r, device); iters optional device int32[c]. */
 typedef struct nmf_basis nmf_basis;

@@ -173,17 +173,27 @@ extern "C" int nmf_product(const nmf_matrix *V, int32_t trans, int32_t r, const 
     SpmmPlan pl{};
     if (!st) st = build_spmm_plan(h, &pl, s);
     float *partial = nullptr;
+    __bf16 *a16 = nullptr;  // BF16: the factor's BF16 copy the gathers read
+    const int lda16 = spmm_lda16(r);
     if (!st && pl.nslots > 0) {
         hipError_t e = hipMalloc((void **)&partial, (size_t)pl.nslots * r * sizeof(float));
         if (e != hipSuccess) st = hip_fail(e, "hipMalloc");
     }
+    if (!st && precision == NMF_BF16) {
+        const int64_t k = trans ? n : m;
+        hipError_t e = hipMalloc((void **)&a16, (size_t)(k > 0 ? k : 1) * lda16 * sizeof(__bf16));
+        if (e == hipSuccess) e = launch_rows_to_bf16(A, k, r, lda16, a16, s);
+        if (e != hipSuccess) st = hip_fail(e, "BF16 copy of the factor");
+    }
     if (!st) {
-        hipError_t e = launch_spmm(pl, ci, vv, A, r, P, partial, s);
+        hipError_t e = a16 ? launch_spmm16(pl, ci, vv, a16, lda16, r, P, partial, s)
+                           : launch_spmm(pl, ci, vv, A, r, P, partial, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) st = hip_fail(e, "nmf_product");
     }
     free_spmm_plan(&pl);
     if (partial) (void)hipFree(partial);
+    if (a16) (void)hipFree(a16);
     if (trp) { (void)hipFree(trp); (void)hipFree(tci); (void)hipFree(tvv); }
     return st;
 }
@@ -209,6 +219,10 @@ struct nmf_plan {
     float *V_hot = nullptr;       // m x ld_hot
     float *P_hot = nullptr;       // T x r
     float *hot_scratch = nullptr; // dense_scratch_bytes(m, T, r)
+    // BF16 mode: the fixed factor's BF16 copy (max(m, n) x lda16) that the
+    // row gathers read; the hot columns' dense product stays float32
+    __bf16 *A16 = nullptr;
+    int lda16 = 0;
     // dense
     __bf16 *V16 = nullptr, *V16t = nullptr;  // BF16 copies of V and V'
     float *dense_scratch = nullptr;
@@ -238,6 +252,7 @@ static void plan_free(nmf_plan *p) {
     if (p->V_hot) (void)hipFree(p->V_hot);
     if (p->P_hot) (void)hipFree(p->P_hot);
     if (p->hot_scratch) (void)hipFree(p->hot_scratch);
+    if (p->A16) (void)hipFree(p->A16);
     if (p->V16) (void)hipFree(p->V16);
     if (p->V16t) (void)hipFree(p->V16t);
     if (p->dense_scratch) (void)hipFree(p->dense_scratch);
@@ -345,6 +360,12 @@ extern "C" int nmf_plan_create(const nmf_matrix *V, int32_t r, const nmf_reg *re
                 if (e != hipSuccess) st = hip_fail(e, "hipMalloc");
             }
         }
+        if (!st && opt->precision == NMF_BF16) {
+            const int64_t kmax = std::max<int64_t>(std::max(p->m, p->n), 1);
+            p->lda16 = spmm_lda16(r);
+            hipError_t e = hipMalloc((void **)&p->A16, (size_t)kmax * p->lda16 * sizeof(__bf16));
+            if (e != hipSuccess) st = hip_fail(e, "hipMalloc");
+        }
     } else {
         if (opt->precision == NMF_BF16) {
             hipError_t e = hipMalloc((void **)&p->V16, (size_t)p->m * p->n * sizeof(__bf16));
@@ -413,6 +434,7 @@ size_t plan_footprint(const nmf_matrix *V, int r, const nmf_opts *opt) {
         b += 3 * al256((size_t)(V->nnz + n + 1) * 4);  // CSR(V') when built here
         b += al256((size_t)m * 256 * 4) + al256(dense_scratch_bytes(m, 256, r));  // hot columns, at most
         b += al256((size_t)(V->nnz / SPMM_CHUNK + m + n + 2) * (sizeof(SpChunk) + sizeof(SpSplit)));
+        if (opt->precision == NMF_BF16) b += al256((size_t)cmax * spmm_lda16(r) * 2);  // A16
     }
     return b + 65536;
 }
@@ -484,15 +506,19 @@ static hipError_t half_update(nmf_plan *p, bool h_update, const float *A, float 
     {
         PhaseMark pm(p, NMF_PHASE_PRODUCT, s);
         if (p->V.kind == NMF_CSR) {
-            if (h_update) {
-                e = launch_spmm(p->sp_h, p->t_colidx, p->t_vals, A, p->r, p->P, p->sp_partial, s);
-                if (e == hipSuccess && p->T_hot) {  // the hot rows: (V_hot' W), then into P
-                    e = launch_dense_product(p->V_hot, 0, p->m, p->T_hot, p->ld_hot, nullptr, 0, A, p->r,
-                                             p->P_hot, p->hot_scratch, s);
-                    if (e == hipSuccess) e = launch_hot_rows_out(p->P_hot, p->hot_idx, p->T_hot, p->r, p->P, s);
-                }
+            const SpmmPlan &pl = h_update ? p->sp_h : p->sp_w;
+            const int32_t *ci = h_update ? p->t_colidx : p->V.colidx;
+            const float *vv = h_update ? p->t_vals : p->V.vals;
+            if (p->A16) {
+                e = launch_rows_to_bf16(A, k, p->r, p->lda16, p->A16, s);
+                if (e == hipSuccess) e = launch_spmm16(pl, ci, vv, p->A16, p->lda16, p->r, p->P, p->sp_partial, s);
             } else {
-                e = launch_spmm(p->sp_w, p->V.colidx, p->V.vals, A, p->r, p->P, p->sp_partial, s);
+                e = launch_spmm(pl, ci, vv, A, p->r, p->P, p->sp_partial, s);
+            }
+            if (e == hipSuccess && h_update && p->T_hot) {  // the hot rows: (V_hot' W), then into P
+                e = launch_dense_product(p->V_hot, 0, p->m, p->T_hot, p->ld_hot, nullptr, 0, A, p->r,
+                                         p->P_hot, p->hot_scratch, s);
+                if (e == hipSuccess) e = launch_hot_rows_out(p->P_hot, p->hot_idx, p->T_hot, p->r, p->P, s);
             }
         } else {
             const bool bf = p->V16 != nullptr;
@@ -647,9 +673,15 @@ extern "C" int nmf_basis_create(const float *W, int64_t m, int32_t r, float l1, 
         e = hipMemcpyAsync(b->W, W, (size_t)m * r * sizeof(float), hipMemcpyDeviceToDevice, s);
     }
     if (e == hipSuccess) e = launch_gram(b->W, m, r, l2, opt->precision, b->G, (float *)(b->ws + oS), s);
+    if (e == hipSuccess && opt->precision == NMF_BF16) {
+        b->lda16 = spmm_lda16(r);
+        e = hipMalloc((void **)&b->W16, (size_t)m * b->lda16 * sizeof(__bf16));
+        if (e == hipSuccess) e = launch_rows_to_bf16(b->W, m, r, b->lda16, b->W16, s);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         if (b->W) (void)hipFree(b->W);
+        if (b->W16) (void)hipFree(b->W16);
         if (b->ws) (void)hipFree(b->ws);
         delete b;
         return hip_fail(e, "nmf_basis_create");
@@ -662,6 +694,7 @@ extern "C" void nmf_basis_destroy(nmf_basis *b) {
     if (!b) return;
     (void)hipDeviceSynchronize();
     (void)hipFree(b->W);
+    if (b->W16) (void)hipFree(b->W16);
     (void)hipFree(b->ws);
     delete b;
 }
@@ -712,6 +745,8 @@ extern "C" int nmf_foldin(const nmf_basis *B, const nmf_matrix *Vnew, float *Ht_
     if (Vnew->kind == NMF_DENSE)
         e = launch_dense_product(Vnew->dense, 0, B->m, c, Vnew->ld, nullptr, 0, B->W, r, P,
                                  (float *)(ws + 256 + pbytes), s);
+    else if (B->W16)
+        e = launch_spmm_rows16(Vnew->t_rowptr, c, Vnew->t_colidx, Vnew->t_vals, B->W16, B->lda16, r, P, s);
     else
         e = launch_spmm_rows(Vnew->t_rowptr, c, Vnew->t_colidx, Vnew->t_vals, B->W, r, P, s);
     int st = NMF_OK;

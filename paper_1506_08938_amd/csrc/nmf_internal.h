@@ -88,6 +88,18 @@ hipError_t launch_spmm(const SpmmPlan &pl, const int32_t *colidx, const float *v
 // one wave per row straight from the row pointers (no split); for short rows
 hipError_t launch_spmm_rows(const int32_t *rowptr, int64_t nrows, const int32_t *colidx,
                             const float *vals, const float *A, int r, float *P, hipStream_t s);
+// BF16 mode: the same products gathering from A16 (k x lda16 BF16, rows of r
+// values padded with zeros to spmm_lda16(r)), accumulated in float32
+#ifndef NMF_SPMM_VEC16
+#define NMF_SPMM_VEC16 8  // BF16 values per lane and piece (8: 16-byte loads, 4: 8-byte)
+#endif
+inline int spmm_lda16(int r) { return (r + NMF_SPMM_VEC16 - 1) / NMF_SPMM_VEC16 * NMF_SPMM_VEC16; }
+hipError_t launch_rows_to_bf16(const float *A, int64_t k, int r, int lda16, __bf16 *A16, hipStream_t s);
+hipError_t launch_spmm16(const SpmmPlan &pl, const int32_t *colidx, const float *vals,
+                         const __bf16 *A16, int lda16, int r, float *P, float *partial, hipStream_t s);
+hipError_t launch_spmm_rows16(const int32_t *rowptr, int64_t nrows, const int32_t *colidx,
+                              const float *vals, const __bf16 *A16, int lda16, int r, float *P,
+                              hipStream_t s);
 
 size_t gram_scratch_bytes(int r, int64_t k);
 // Also zeroes *counter (when non-NULL) so that a solve can follow on the stream.
@@ -204,6 +216,8 @@ hipError_t launch_max_ordered(const double *in, int64_t n, double *out, hipStrea
 }  // namespace nmfi
 struct nmf_basis {
     float *W = nullptr;  // m x r copy
+    __bf16 *W16 = nullptr;  // BF16 mode: m x lda16 copy for the sparse fold-in gathers
+    int lda16 = 0;
     int64_t m = 0;
     int r = 0;
     float l1 = 0.f, l2 = 0.f;

@@ -113,6 +113,8 @@ int run_foldin_batch(nmf_server *S, std::vector<std::shared_ptr<Req>> &batch, hi
         probs[j].P = Pj;
         if (q.V.kind == NMF_DENSE)
             e = launch_dense_product(q.V.dense, 0, B->m, q.V.cols, q.V.ld, nullptr, 0, B->W, r, Pj, dscr, s);
+        else if (B->W16)
+            e = launch_spmm_rows16(q.V.t_rowptr, q.V.cols, q.V.t_colidx, q.V.t_vals, B->W16, B->lda16, r, Pj, s);
         else
             e = launch_spmm_rows(q.V.t_rowptr, q.V.cols, q.V.t_colidx, q.V.t_vals, B->W, r, Pj, s);
         off += q.V.cols;

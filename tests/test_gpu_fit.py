@@ -87,6 +87,12 @@ def small_text(m, n, per_row, seed=3):
     return synth.sparse_text(m, n, per_row, seed)
 
 
+def bf16_round(a):
+    """float32 -> nearest BF16 (ties to even) -> float32, for finite a."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32)
+    return ((u + np.uint32(0x7FFF) + ((u >> 16) & np.uint32(1))) & np.uint32(0xFFFF0000)).view(np.float32)
+
+
 @pytest.mark.parametrize("m,n,per_row,r", [(3000, 2000, 40, 100), (1000, 600, 7, 33),
                                            (500, 300, 3, 1), (2500, 1200, 30, 64)])
 def test_csr_product_matches_oracle_including_split_rows(m, n, per_row, r):
@@ -104,6 +110,17 @@ def test_csr_product_matches_oracle_including_split_rows(m, n, per_row, r):
         e1 = np.abs(P1 - R1).max() / max(np.abs(R1).max(), 1e-30)
         print(f"csr {m}x{n} r={r} t={with_t}: {e0:.2e} {e1:.2e}")
         assert e0 < 5e-6 and e1 < 5e-6
+        # BF16 gathers: exactly the product with the factor rounded to BF16
+        # (accumulated in float32), and within BF16's half-ulp of the FP32 one
+        B0 = H(nat.product(Vd, T(W), 0, precision=nat.NMF_BF16))
+        B1 = H(nat.product(Vd, T(Ht), 1, precision=nat.NMF_BF16))
+        Q0 = oracle.product_csr(V, bf16_round(W), 0); Q1 = oracle.product_csr(V, bf16_round(Ht), 1)
+        b0 = np.abs(B0 - Q0).max() / max(np.abs(Q0).max(), 1e-30)
+        b1 = np.abs(B1 - Q1).max() / max(np.abs(Q1).max(), 1e-30)
+        d0 = np.abs(B0 - R0).max() / max(np.abs(R0).max(), 1e-30)
+        print(f"csr bf16 {m}x{n} r={r} t={with_t}: vs rounded factor {b0:.2e} {b1:.2e}; vs fp32 {d0:.2e}")
+        assert b0 < 5e-6 and b1 < 5e-6
+        assert d0 < 2.0 ** -8
 
 
 # --------------------------------------------------------------------------- objective
@@ -273,6 +290,48 @@ def test_fit_sparse_trajectory():
     assert abs(st["kbar"] - kbar_o) < 0.02 * kbar_o
 
 
+# BF16 products (dense: V and the factor in BF16 on MFMA; CSR: gathers from a
+# BF16 copy of the factor) with the Gram in BF16, the solve in float32.  One
+# outer iteration from a converging state (the oracle's after 10) against the
+# oracle's float64 iteration.  The factor's rounding (up to 2^-9 of each
+# value, averaging out over the k terms of each sum) moves the solved
+# columns, but the objective is flat at their optimum: 1e-4.  Dense BF16
+# also fits BF16(V) instead of V: the fit absorbs the part of the rounding
+# error dV that lies in the model's r(m+n)-dimensional tangent space, about
+# r(m+n)/(mn) of 0.5||dV||^2 (measured 7.0e-4 of J here against that
+# estimate's 8.4e-4), so twice that estimate is added to the bound.
+# From the random start an NMF trajectory amplifies
+# any perturbation (BF16 runs of the dense workload differ from the float32
+# ones by a few percent after 5 iterations and meet them again near
+# convergence), so only the converging-state step is compared.  Runs are
+# reproducible bit for bit.
+@pytest.mark.parametrize("kind", ["dense", "csr"])
+def test_outer_iteration_parity_bf16_products(kind):
+    if kind == "csr":
+        V = small_text(2000, 1500, 25, seed=11)
+        r, reg = 100, f32((0.0, 0.01, 0.1, 0.0))
+        W0, Ht0 = synth.start_point(2000, 1500, r, 12)
+    else:
+        V = synth.dense_lowrank(400, 300, 16, 77, "gamma", 0.05)
+        r, reg = 16, f32((0.0, 0.01, 0.0, 0.01))
+        W0, Ht0 = synth.start_point(400, 300, 16, 78)
+    st = oracle.nmf_fit(V, r, reg, W0, Ht0, T=10, want_trace=False, **FIXED)
+    W0, Ht0 = st["W"].astype(np.float32), st["Ht"].astype(np.float32)
+    Wg, Hg, tr, _ = run_fit(V, r, reg, W0, Ht0, 1, precision=1, **FIXED)
+    Wb, Hb, _, _ = run_fit(V, r, reg, W0, Ht0, 1, precision=1, **FIXED)
+    o = oracle.nmf_fit(V, r, reg, W0, Ht0, T=1, **FIXED)
+    Jg, Jo = oracle.objective(V, Wg, Hg, reg), oracle.objective(V, o["W"], o["Ht"], reg)
+    J = abs(Jg - Jo) / Jo
+    m, n = V.shape
+    dv = 0.0 if kind == "csr" else 0.5 * np.sum((V.astype(np.float64) - bf16_round(V)) ** 2)
+    bound = 1e-4 + 2 * r * (m + n) / (m * n) * dv / Jo
+    print(f"{kind} bf16 step after 10: J rel {J:.2e} (bound {bound:.2e}); "
+          f"W {rel_fro(Wg, o['W']):.2e} Ht {rel_fro(Hg, o['Ht']):.2e}")
+    assert tr[0] == pytest.approx(oracle.loss(V, W0, Ht0), rel=1e-12)
+    assert J < bound
+    assert np.array_equal(Wg, Wb) and np.array_equal(Hg, Hb)
+
+
 def test_fit_stats_and_trace_every():
     wl = synth.workload1()
     Wg, Hg, tr, st = run_fit(wl["V"], wl["r"], wl["reg"], wl["W0"], wl["Ht0"], 6, objective_every=3)
@@ -348,6 +407,18 @@ def test_foldin_matches_oracle(r):
     out2 = H(B.foldin(Vdn))
     assert np.abs(out2 - out).max() <= 1e-3 * np.abs(out).max()
     B.close()
+    # a BF16 basis: the Gram and the sparse request's gathers from BF16(W);
+    # the oracle solves with the same rounded factor
+    Wb = bf16_round(W)
+    B16 = nat.Basis(T(W), l1, l2, nat.opts(max_inner=100, eps=1e-3, precision=nat.NMF_BF16))
+    xb, _ = oracle.nqp_batch(oracle.gram(Wb, l2).astype(np.float32),
+                             (-oracle.product_csr(req, Wb, 1) + l1).astype(np.float32),
+                             np.zeros((300, r)), max_inner=100, eps=1e-3)
+    out16 = H(B16.foldin(foldin_matrix(nat, req, m)))
+    eb = np.linalg.norm(out16 - xb, axis=1) / np.maximum(np.linalg.norm(xb, axis=1), 1e-30)
+    print(f"foldin bf16 r={r}: x rel to the rounded-factor oracle median {np.median(eb):.2e}")
+    assert np.median(eb) < 1e-3
+    B16.close()
 
 
 def foldin_matrix(nat, req_t, m):
