@@ -492,6 +492,7 @@ def main():
                     help="instances per streamed panel (--workload streamed)")
     ap.add_argument("--fast-break", type=int, default=0,
                     help="Algorithm 3's fast-break over runs of this many columns (0: off)")
+    ap.add_argument("--no-bf16", action="store_true", help="skip the BF16-products leg of the sparse workload")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"],
                     help="sparse workload: float32 products, or BF16 gathers and Gram (the solve stays float32)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -537,39 +538,40 @@ def main():
     Vd = native.DeviceMatrix(V, with_transpose=False)  # CSR(V') is built on the device
     reg = native.reg(*wl["reg"])
     bf16 = args.precision == "bf16"
-    opt = native.opts(max_inner=100, eps=1e-3, ls_guard=1, fast_break_cols=args.fast_break, lanes=args.lanes,
-                      precision=native.NMF_BF16 if bf16 else native.NMF_FP32)
-    plan = native.Plan(Vd, r, reg, opt)
-    W = torch.from_numpy(wl["W0"]).cuda()
-    Ht = torch.from_numpy(wl["Ht0"]).cuda()
-    torch.cuda.synchronize()
-    log("[bench] plan ready")
 
-    for _ in range(args.warmup):
-        plan.run(W, Ht, 1)
-    torch.cuda.synchronize()
-    log(f"[bench] warmup {args.warmup} done")
+    def timed_run(precision):
+        """Plan, warm-up, the timed steps (events on the solve's own dispatches:
+        nothing is added to the stream between kernels), then a separate untimed
+        run with events around every phase."""
+        opt = native.opts(max_inner=100, eps=1e-3, ls_guard=1, fast_break_cols=args.fast_break,
+                          lanes=args.lanes, precision=precision)
+        plan = native.Plan(Vd, r, reg, opt)
+        W = torch.from_numpy(wl["W0"]).cuda()
+        Ht = torch.from_numpy(wl["Ht0"]).cuda()
+        torch.cuda.synchronize()
+        for _ in range(args.warmup):
+            plan.run(W, Ht, 1)
+        torch.cuda.synchronize()
+        plan.profile(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = plan.run(W, Ht, args.steps, want_stats=True)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        timers = plan.timers()
+        plan.profile(False)
+        Kp = min(args.steps, 5)
+        plan.profile(True)
+        plan.run(W.clone(), Ht.clone(), Kp)
+        torch.cuda.synchronize()
+        phases = {k: v[0] / Kp for k, v in plan.timers().items()}
+        plan.profile(False)
+        plan.close()
+        return elapsed, st, timers, phases
 
-    # the solve kernel's own dispatches carry the timing events: nothing is
-    # added to the stream between kernels in the timed region
-    plan.profile(2)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    _, st = plan.run(W, Ht, args.steps, want_stats=True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    timers = plan.timers()
-    plan.profile(False)
-    elapsed = t1 - t0
+    elapsed, st, timers, phases = timed_run(native.NMF_BF16 if bf16 else native.NMF_FP32)
     K = args.steps
     log(f"[bench] timed {K} steps in {elapsed:.3f}s")
-    # per-phase breakdown from a separate, untimed run with events around every phase
-    Kp = min(K, 5)
-    plan.profile(True)
-    plan.run(W.clone(), Ht.clone(), Kp)
-    torch.cuda.synchronize()
-    phases = {k: v[0] / Kp for k, v in plan.timers().items()}
-    plan.profile(False)
 
     E_h, L_h = native.layout(r, n)
     E_w, L_w = native.layout(r, m)
@@ -623,7 +625,17 @@ def main():
         "loss_after": st["loss"],
     }
 
-    plan.close()
+    if not bf16 and not args.no_bf16:
+        # the same steps with BF16 products (gathers from BF16 copies of the fixed
+        # factor, BF16 Gram; the solve stays float32): speed and the loss reached
+        # after the same number of iterations from the same start point
+        el16, st16, _, ph16 = timed_run(native.NMF_BF16)
+        out["bf16_products"] = {
+            "value": (m + n) * K / el16, "unit": "column NNLS solves/s", "ms_per_step": el16 * 1e3 / K,
+            "phases_ms_per_step": ph16, "kbar": st16["kbar"], "loss_after": st16["loss"],
+            "loss_rel_to_fp32": st16["loss"] / st["loss"] - 1.0,
+        }
+        log(f"[bench] BF16 products: {el16 * 1e3 / K:.3f} ms/step")
     if not args.no_serve:
         out["serving"] = serving_leg(native, synth, torch, args.serve_requests, (args.serve_load,))
 

@@ -83,6 +83,42 @@ def test_alone_equals_mix_equals_direct(basis):
     assert np.median(e) < 1e-3
 
 
+def test_bf16_basis_alone_equals_mix_equals_direct():
+    """A BF16 basis (Gram in BF16, sparse requests gathered from a BF16 copy
+    of W): the batched server path gives the direct nmf_foldin result
+    bitwise, alone and in a mix, and matches the oracle fed the rounded W."""
+    import torch
+    from paper_1506_08938_amd import native as nat
+    m, r = 3000, 40
+    W = np.random.default_rng(6).gamma(2.0, 0.5, (m, r)).astype(np.float32)
+    B = nat.Basis(T(W), l1=0.05, l2=0.0, opt=nat.opts(max_inner=100, eps=1e-3, precision=nat.NMF_BF16))
+    req = synth.foldin_columns(m, 200, 60, seed=2)
+    R = nat.sparse_request(req, m)
+    direct = H(B.foldin(R))
+    S = nat.Server(B, hbm_budget=1 << 30, max_slots=2, max_batch_cols=4096)
+    out_alone = torch.empty((200, r), device="cuda")
+    S.wait(S.submit_foldin(R, out_alone))
+    outs = []
+    for i, c in enumerate(synth.request_sizes(12, seed=19, cmax=1500)):
+        o = torch.empty((int(c), r), device="cuda")
+        S.submit_foldin(nat.sparse_request(synth.foldin_columns(m, int(c), 60, seed=300 + i), m), o)
+        if i == 6:
+            out_mix = torch.empty((200, r), device="cuda")
+            S.submit_foldin(R, out_mix)
+    S.wait()
+    S.close()
+    assert np.array_equal(H(out_alone), direct) and np.array_equal(H(out_mix), direct)
+    u = W.view(np.uint32)
+    Wb = ((u + np.uint32(0x7FFF) + ((u >> 16) & np.uint32(1))) & np.uint32(0xFFFF0000)).view(np.float32)
+    xo, _ = oracle.nqp_batch(oracle.gram(Wb, 0.0).astype(np.float32),
+                             (-oracle.product_csr(req, Wb, 1) + np.float32(0.05)).astype(np.float32),
+                             np.zeros((200, r)), max_inner=100, eps=1e-3)
+    e = np.linalg.norm(direct - xo, axis=1) / np.maximum(np.linalg.norm(xo, axis=1), 1e-30)
+    print(f"bf16 basis fold-in vs rounded-W oracle: median {np.median(e):.2e}")
+    assert np.median(e) < 1e-3
+    B.close()
+
+
 def test_budget_refusal_and_latency(basis):
     import torch
     from paper_1506_08938_amd import native as nat
