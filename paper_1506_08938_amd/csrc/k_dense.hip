@@ -433,8 +433,7 @@ hipError_t launch_to_bf16(const float *x, int64_t rows, int64_t cols, int64_t ld
 // r = 64: 5-8% faster than double-buffered LDS with a 2048 (FP32) or 1024
 // (BF16) block target rounded up; the same rule serves both precisions.
 constexpr int64_t DENSE_SPLIT_BLOCKS = 1024;
-int dense_nsplit(int64_t C, int64_t K, bool bf16) {
-    (void)bf16;
+int dense_nsplit(int64_t C, int64_t K) {
     const int64_t rb = (C + DENSE_BM - 1) / DENSE_BM;
     int64_t ns = DENSE_SPLIT_BLOCKS / rb;
     const int64_t maxs = (K + 255) / 256;
@@ -445,8 +444,8 @@ int dense_nsplit(int64_t C, int64_t K, bool bf16) {
 }
 
 // slice length: a multiple of 64 (both stage depths)
-int64_t dense_kchunk(int64_t C, int64_t K, bool bf16) {
-    const int ns = dense_nsplit(C, K, bf16);
+int64_t dense_kchunk(int64_t C, int64_t K) {
+    const int ns = dense_nsplit(C, K);
     int64_t kchunk = (K + ns - 1) / ns;
     kchunk = ((kchunk + 63) / 64) * 64;
     return kchunk < 64 ? 64 : kchunk;
@@ -456,13 +455,12 @@ int64_t dense_kchunk(int64_t C, int64_t K, bool bf16) {
 // lda16 with lda16 = max(m, n) rounded up to 64).
 static size_t dense_partial_bytes(int64_t m, int64_t n, int r) {
     // slices actually used (a single slice writes P directly)
-    auto used = [](int64_t C, int64_t K, bool bf16) {
-        const int64_t kc = dense_kchunk(C, K, bf16);
+    auto used = [](int64_t C, int64_t K) {
+        const int64_t kc = dense_kchunk(C, K);
         const int64_t ns = K > 0 ? (K + kc - 1) / kc : 0;
         return ns > 1 ? ns * C : 0;
     };
-    int64_t most = 0;
-    for (bool bf16 : {false, true}) most = std::max(most, std::max(used(n, m, bf16), used(m, n, bf16)));
+    const int64_t most = std::max(used(n, m), used(m, n));
     return (((size_t)most * r * sizeof(float)) + 255) & ~(size_t)255;
 }
 static int64_t dense_lda16(int64_t m, int64_t n) {
@@ -502,7 +500,7 @@ hipError_t launch_dense_product(const void *V, int bf16, int64_t m, int64_t n, i
     const int64_t C = h_update ? n : m, K = h_update ? m : n;
     if (C == 0) return hipSuccess;
     if (K == 0) return hipErrorInvalidValue;  // callers reject empty V
-    const int64_t kchunk = dense_kchunk(C, K, bf16 != 0);
+    const int64_t kchunk = dense_kchunk(C, K);
     const int nsplit = (int)((K + kchunk - 1) / kchunk);
     float *out = nsplit > 1 ? scratch : P;
     const int NT = (r + 31) / 32;

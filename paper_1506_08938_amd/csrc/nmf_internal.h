@@ -108,9 +108,10 @@ hipError_t launch_gram(const float *A, int64_t k, int r, float l2, int precision
 
 size_t dense_scratch_bytes(int64_t m, int64_t n, int r);
 // split-K decomposition of P (C x r) = X (C x K) A shared by the single and
-// batched products: nsplit slices of kchunk (a multiple of 32) each
-int dense_nsplit(int64_t C, int64_t K, bool bf16);
-int64_t dense_kchunk(int64_t C, int64_t K, bool bf16);
+// batched products, both precisions: nsplit slices of kchunk (a multiple of
+// 64) each
+int dense_nsplit(int64_t C, int64_t K);
+int64_t dense_kchunk(int64_t C, int64_t K);
 hipError_t launch_dense_product(const void *V, int bf16, int64_t m, int64_t n, int64_t ld,
                                 const __bf16 *V16t, int trans, const float *A, int r, float *P,
                                 float *scratch, hipStream_t s);
