@@ -83,7 +83,7 @@ def measured_traffic(kernel, L):
     return float(fields["traffic_bytes_per_launch"])
 
 
-def serving_leg(native, synth, torch, n_req, loads=(0.5,), seed=5005, n_warm=None):
+def serving_leg(native, synth, torch, n_req, loads=(0.5,), seed=5005, n_warm=None, batch_cols=16384):
     """Saturated throughput and Poisson-arrival latency of nmf_server_* at each offered load
     (a fraction of the saturated request rate)."""
     import numpy as np
@@ -134,7 +134,7 @@ def serving_leg(native, synth, torch, n_req, loads=(0.5,), seed=5005, n_warm=Non
         """All requests at once (arrivals None) or at the given times; returns the elapsed
         time of the measured requests and their latencies."""
         reset_fits()
-        S = native.Server(basis, hbm_budget=8 << 30, max_slots=4, max_batch_cols=16384)
+        S = native.Server(basis, hbm_budget=8 << 30, max_slots=4, max_batch_cols=batch_cols)
         tickets = []
         t0 = time.perf_counter()
         t_first = None
@@ -190,7 +190,7 @@ def serving_leg(native, synth, torch, n_req, loads=(0.5,), seed=5005, n_warm=Non
                     "Gamma(2,0.5)-factor data), L1=0.05, eps=1e-3; fold-in requests of "
                     "c~logU[1,8192] columns at 0.5% density, values log(1+Poisson(3)); 5% small "
                     "full fits (m,n~logU[64,2048], r~U{4..32}, 30 outer iterations); 4 slots, "
-                    "batches of up to 16384 columns",
+                    f"batches of up to {batch_cols} columns",
         "requests": n_req, "warmup_requests": n_warm,
         "fold_in_columns": cols,
         "saturated_solves_per_s": cols / el_sat,
@@ -462,7 +462,7 @@ def bench_streamed(args, native, synth, torch, np):
 def bench_serving(args, native, synth, torch, np):
     """The serving configuration at several offered loads."""
     loads = (0.3, 0.6, 0.9)
-    res = serving_leg(native, synth, torch, args.serve_requests, loads, n_warm=1000)
+    res = serving_leg(native, synth, torch, args.serve_requests, loads, n_warm=1000, batch_cols=args.serve_batch_cols)
     out = base_line(
         "fold-in serving: column NNLS solves/s and p50/p99 latency at offered loads",
         res["saturated_solves_per_s"], "column NNLS solves/s", args.serve_requests, 0,
@@ -480,6 +480,8 @@ def main():
                     help="outer iterations of the CPU-oracle sample")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-batch-cols", type=int, default=16384,
+                    help="largest fold-in batch (columns) the server forms")
     ap.add_argument("--serve-load", type=float, default=0.5,
                     help="Poisson arrival rate as a fraction of the saturated request rate")
     ap.add_argument("--workload", default="sparse", choices=["sparse", "dense", "batched", "serving", "streamed"],
@@ -637,7 +639,8 @@ def main():
         }
         log(f"[bench] BF16 products: {el16 * 1e3 / K:.3f} ms/step")
     if not args.no_serve:
-        out["serving"] = serving_leg(native, synth, torch, args.serve_requests, (args.serve_load,))
+        out["serving"] = serving_leg(native, synth, torch, args.serve_requests, (args.serve_load,),
+                                     batch_cols=args.serve_batch_cols)
 
     if not args.no_cpu:
         import oracle
