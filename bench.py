@@ -606,8 +606,8 @@ def main():
                         "(0.1% density), values log(1+Poisson(3)), r=100, L1=0.1 on H, L2=0.01 "
                         "on W, eps=1e-3, max_inner=100; one step = one outer iteration"
                         + (f"; fast-break over runs of {args.fast_break} columns" if args.fast_break > 1 else "")
-                        + ("; BF16 products: row gathers from a BF16 copy of the fixed factor and a BF16 "
-                           "Gram, float32 accumulation and solve (hot columns' dense product float32)"
+                        + ("; BF16 products: row gathers from a BF16 copy of the fixed factor, the hot "
+                           "columns' product and the Gram on BF16 MFMA, float32 accumulation and solve"
                            if bf16 else ""),
             "m": m, "n": n, "nnz": int(V.nnz), "r": r,
         },
@@ -629,8 +629,9 @@ def main():
 
     if not bf16 and not args.no_bf16:
         # the same steps with BF16 products (gathers from BF16 copies of the fixed
-        # factor, BF16 Gram; the solve stays float32): speed and the loss reached
-        # after the same number of iterations from the same start point
+        # factor, BF16 hot-column product and Gram; the solve stays float32): speed
+        # and the loss reached after the same number of iterations from the same
+        # start point
         el16, st16, _, ph16 = timed_run(native.NMF_BF16)
         out["bf16_products"] = {
             "value": (m + n) * K / el16, "unit": "column NNLS solves/s", "ms_per_step": el16 * 1e3 / K,

@@ -99,9 +99,10 @@ typedef struct {
  * float32, products are accumulated in float32).  BF16 with dense V: V and
  * the fixed factor in BF16 on the matrix cores (BF16 copies of V made once
  * per plan).  BF16 with CSR V: the row gathers read a BF16 copy of the fixed
- * factor (values stay float32); the dense product of the hot columns stays
- * float32.  objective_every: compute the loss every s outer iterations
- * (0 = only when a trace or stats are requested, at the end).  check_finite:
+ * factor (values stay float32), and the dense product of the hot columns
+ * runs on the matrix cores from BF16 copies.  objective_every: compute the
+ * loss every s outer iterations (0 = only when a trace or stats are
+ * requested, at the end).  check_finite:
  * scan inputs for NaN/Inf (and V for negatives) before running.  lanes:
  * lanes of a wavefront that cooperate on one column in the solve kernel
  * (1, 2, 4, 8 or 16; 0 = chosen from r and the launch's column count: few

@@ -217,10 +217,11 @@ struct nmf_plan {
     int T_hot = 0, ld_hot = 0;    // ld_hot: T rounded up to 4 (16-byte rows)
     int32_t *hot_idx = nullptr;   // T column indices (device)
     float *V_hot = nullptr;       // m x ld_hot
+    __bf16 *V_hot16t = nullptr;   // BF16 mode: T x m, V_hot' in BF16 (the product reads it along k)
     float *P_hot = nullptr;       // T x r
     float *hot_scratch = nullptr; // dense_scratch_bytes(m, T, r)
     // BF16 mode: the fixed factor's BF16 copy (max(m, n) x lda16) that the
-    // row gathers read; the hot columns' dense product stays float32
+    // row gathers read
     __bf16 *A16 = nullptr;
     int lda16 = 0;
     // dense
@@ -250,6 +251,7 @@ static void plan_free(nmf_plan *p) {
     if (p->sp_partial) (void)hipFree(p->sp_partial);
     if (p->hot_idx) (void)hipFree(p->hot_idx);
     if (p->V_hot) (void)hipFree(p->V_hot);
+    if (p->V_hot16t) (void)hipFree(p->V_hot16t);
     if (p->P_hot) (void)hipFree(p->P_hot);
     if (p->hot_scratch) (void)hipFree(p->hot_scratch);
     if (p->A16) (void)hipFree(p->A16);
@@ -364,7 +366,11 @@ extern "C" int nmf_plan_create(const nmf_matrix *V, int32_t r, const nmf_reg *re
             const int64_t kmax = std::max<int64_t>(std::max(p->m, p->n), 1);
             p->lda16 = spmm_lda16(r);
             hipError_t e = hipMalloc((void **)&p->A16, (size_t)kmax * p->lda16 * sizeof(__bf16));
-            if (e != hipSuccess) st = hip_fail(e, "hipMalloc");
+            if (e == hipSuccess && p->T_hot) {  // the hot columns' product on BF16 MFMA
+                e = hipMalloc((void **)&p->V_hot16t, (size_t)p->T_hot * p->m * sizeof(__bf16));
+                if (e == hipSuccess) e = launch_to_bf16_t(p->V_hot, p->m, p->T_hot, p->ld_hot, p->V_hot16t, s);
+            }
+            if (e != hipSuccess) st = hip_fail(e, "BF16 copies");
         }
     } else {
         if (opt->precision == NMF_BF16) {
@@ -434,7 +440,8 @@ size_t plan_footprint(const nmf_matrix *V, int r, const nmf_opts *opt) {
         b += 3 * al256((size_t)(V->nnz + n + 1) * 4);  // CSR(V') when built here
         b += al256((size_t)m * 256 * 4) + al256(dense_scratch_bytes(m, 256, r));  // hot columns, at most
         b += al256((size_t)(V->nnz / SPMM_CHUNK + m + n + 2) * (sizeof(SpChunk) + sizeof(SpSplit)));
-        if (opt->precision == NMF_BF16) b += al256((size_t)cmax * spmm_lda16(r) * 2);  // A16
+        if (opt->precision == NMF_BF16)  // A16 and the hot columns' BF16 copy
+            b += al256((size_t)cmax * spmm_lda16(r) * 2) + al256((size_t)m * 256 * 2);
     }
     return b + 65536;
 }
@@ -516,7 +523,8 @@ static hipError_t half_update(nmf_plan *p, bool h_update, const float *A, float 
                 e = launch_spmm(pl, ci, vv, A, p->r, p->P, p->sp_partial, s);
             }
             if (e == hipSuccess && h_update && p->T_hot) {  // the hot rows: (V_hot' W), then into P
-                e = launch_dense_product(p->V_hot, 0, p->m, p->T_hot, p->ld_hot, nullptr, 0, A, p->r,
+                const bool bf = p->V_hot16t != nullptr;
+                e = launch_dense_product(p->V_hot, bf, p->m, p->T_hot, p->ld_hot, p->V_hot16t, 0, A, p->r,
                                          p->P_hot, p->hot_scratch, s);
                 if (e == hipSuccess) e = launch_hot_rows_out(p->P_hot, p->hot_idx, p->T_hot, p->r, p->P, s);
             }
