@@ -51,6 +51,25 @@ def f_col(G, h, x):
     return 0.5 * np.einsum("ij,jk,ik->i", x, G, x) + np.einsum("ij,ij->i", h, x)
 
 
+def bf16_round(a):
+    """float32 -> nearest BF16 (ties to even) -> float32, for finite a."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32)
+    return ((u + np.uint32(0x7FFF) + ((u >> 16) & np.uint32(1))) & np.uint32(0xFFFF0000)).view(np.float32)
+
+
+def hot_columns(Vt, m):
+    """The columns the plan's H-update takes through the dense product: at
+    least max(m/16, 256) stored entries, the longest first (ties: lower index),
+    all of them up to 127, else whole slabs of 128 (at most 256)."""
+    cnt = np.diff(Vt.indptr)
+    thr = max((m + 15) // 16, 256)
+    cand = np.flatnonzero(cnt >= thr)
+    cand = cand[np.argsort(-cnt[cand], kind="stable")]
+    if len(cand) >= 128:
+        cand = cand[:min(len(cand), 256) // 128 * 128]
+    return set(cand.tolist()) if len(cand) >= 4 else set()
+
+
 def one_iteration(full, opts):
     from paper_1506_08938_amd import native as nat
     wl = full["wl"]
@@ -106,4 +125,46 @@ def test_fullsize_outer_iteration_on_sampled_columns_and_rows(full, mode):
     Pr = rows_product(V, rows, Hg)
     check_half(Gh, Pr, l1w, W0[rows], Wg[rows], opts["max_inner"], opts["eps"],
                f"full size {mode} W-update, {NSAMPLE} rows", mode == "fixed")
+    assert (Wg >= 0).all() and (Hg >= 0).all() and np.isfinite(Wg).all() and np.isfinite(Hg).all()
+
+
+def rows_product_bf16(csr, rows, A, round_values):
+    """FP64 rows of csr @ bf16(A); the stored values rounded to BF16 too for
+    the rows in round_values."""
+    Ab = bf16_round(A).astype(np.float64)
+    out = np.zeros((len(rows), A.shape[1]))
+    for k, i in enumerate(rows):
+        lo, hi = csr.indptr[i], csr.indptr[i + 1]
+        v = csr.data[lo:hi]
+        if i in round_values:
+            v = bf16_round(v)
+        out[k] = v.astype(np.float64) @ Ab[csr.indices[lo:hi]]
+    return out
+
+
+def test_fullsize_bf16_outer_iteration_on_sampled_columns_and_rows(full):
+    """BF16 products at full size, fixed-K: the oracle is fed exactly the
+    values the GPU rounds (the fixed factor in the Gram and the products; the
+    stored values of the hot columns, whose product runs on BF16 MFMA), so the
+    float32-accumulation bar of the float32 test applies.  The sample includes
+    hot columns."""
+    wl, V, Vt = full["wl"], full["V"], full["Vt"]
+    m, n = V.shape
+    opts = dict(max_inner=20, eps=0.0, precision=1)
+    Wg, Hg, (l1w, l2w, l1h, l2h) = one_iteration(full, opts)
+    hot = hot_columns(Vt, m)
+    assert len(hot) >= 4
+    g = np.random.default_rng(2025)
+    cols = np.sort(np.concatenate([g.choice(n, NSAMPLE - 16, replace=False),
+                                   np.array(sorted(hot))[g.choice(len(hot), 16, replace=False)]]))
+    rows = np.sort(g.choice(m, NSAMPLE, replace=False))
+    W0 = wl["W0"].astype(np.float64)
+    Ht0 = wl["Ht0"].astype(np.float64)
+    Gw = oracle.gram(bf16_round(wl["W0"]), l2h)
+    Pc = rows_product_bf16(Vt, cols, wl["W0"], hot)
+    check_half(Gw, Pc, l1h, Ht0[cols], Hg[cols], 20, 0.0, f"full size bf16 H-update, {NSAMPLE} columns", True)
+    Hg32 = Hg.astype(np.float32)
+    Gh = oracle.gram(bf16_round(Hg32), l2w)
+    Pr = rows_product_bf16(V, rows, Hg32, set())
+    check_half(Gh, Pr, l1w, W0[rows], Wg[rows], 20, 0.0, f"full size bf16 W-update, {NSAMPLE} rows", True)
     assert (Wg >= 0).all() and (Hg >= 0).all() and np.isfinite(Wg).all() and np.isfinite(Hg).all()
