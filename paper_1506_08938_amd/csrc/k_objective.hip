@@ -11,21 +11,34 @@
 // Work is dealt to a grid whose size depends only on the problem's shape,
 // and every reduction sums per-block partials in a fixed order (in fixed
 // groups first where there are many), so results are bitwise reproducible.
+#include "kernels_common.h"
 #include "nmf_internal.h"
 
 namespace nmfi {
 
 constexpr int LD_T = 64;  // dense loss tile
 
+// LDS pitch of a factor tile (floats per rank index): LD_T + 4 spreads the
+// staging stores over the banks; past r = 120 that would exceed 64 KB, and
+// the pitch is LD_T (the compute reads are conflict-free either way)
+__host__ __device__ inline int loss_dense_pitch(int r) { return r <= 120 ? LD_T + 4 : LD_T; }
+static size_t loss_dense_lds(int r) { return (size_t)2 * loss_dense_pitch(r) * r * sizeof(float); }
+
 // ------------------------------------------------------------ dense loss
+// The tiles of W and Ht sit in LDS rank-major (Ws[a][row]): a thread's four
+// rows of one rank index are one 16-byte read and the sixteen column threads
+// of a wave read 256 consecutive bytes (no bank conflicts); with pitch
+// LD_T + 4 the coalesced row-major staging stores hit banks 4a + row (4-way).
+// (Row-major tiles had put the sixteen column threads' reads in one bank.)
 __global__ __launch_bounds__(256) void k_loss_dense(const float *__restrict__ V, int64_t ld,
                                                     int64_t m, int64_t n,
                                                     const float *__restrict__ W,
                                                     const float *__restrict__ Ht, int r,
                                                     double *__restrict__ partial) {
-    extern __shared__ float sm[];
-    float *Ws = sm;               // LD_T x r
-    float *Hs = sm + LD_T * r;    // LD_T x r
+    extern __shared__ __attribute__((aligned(16))) float sm[];
+    const int lp = loss_dense_pitch(r);
+    float *Ws = sm;             // r x lp
+    float *Hs = sm + lp * r;    // r x lp
     __shared__ double red[256];
     const int tid = threadIdx.x;
     const int64_t i0 = (int64_t)blockIdx.y * LD_T, j0 = (int64_t)blockIdx.x * LD_T;
@@ -35,8 +48,8 @@ __global__ __launch_bounds__(256) void k_loss_dense(const float *__restrict__ V,
         const int row = e / r, a = e - row * r;
         const float w = W[(i0 + row < m ? i0 + row : i0) * r + a];
         const float h = Ht[(j0 + row < n ? j0 + row : j0) * r + a];
-        Ws[e] = (i0 + row < m) ? w : 0.f;
-        Hs[e] = (j0 + row < n) ? h : 0.f;
+        Ws[a * lp + row] = (i0 + row < m) ? w : 0.f;
+        Hs[a * lp + row] = (j0 + row < n) ? h : 0.f;
     }
     __syncthreads();
     const int ty = tid >> 4, tx = tid & 15;
@@ -46,11 +59,13 @@ __global__ __launch_bounds__(256) void k_loss_dense(const float *__restrict__ V,
 #pragma unroll
         for (int q = 0; q < 4; q++) acc[p][q] = 0.0;
     for (int a = 0; a < r; a++) {
+        const f32x4 w4 = *(const f32x4 *)(Ws + a * lp + 4 * ty);
+        const f32x4 h4 = *(const f32x4 *)(Hs + a * lp + 4 * tx);
         double wv[4], hv[4];
 #pragma unroll
-        for (int p = 0; p < 4; p++) wv[p] = (double)Ws[(4 * ty + p) * r + a];
+        for (int p = 0; p < 4; p++) wv[p] = (double)w4[p];
 #pragma unroll
-        for (int q = 0; q < 4; q++) hv[q] = (double)Hs[(4 * tx + q) * r + a];
+        for (int q = 0; q < 4; q++) hv[q] = (double)h4[q];
 #pragma unroll
         for (int p = 0; p < 4; p++)
 #pragma unroll
@@ -520,7 +535,7 @@ hipError_t launch_objective(const nmf_matrix *V, int r, const nmf_reg *reg, cons
     if (V->kind == NMF_DENSE) {
         const unsigned gx = (unsigned)((n + LD_T - 1) / LD_T), gy = (unsigned)((m + LD_T - 1) / LD_T);
         double *part = (double *)take((size_t)gx * gy * sizeof(double));
-        const size_t lds = (size_t)2 * LD_T * r * sizeof(float);
+        const size_t lds = loss_dense_lds(r);
         hipLaunchKernelGGL(k_loss_dense, dim3(gx, gy), dim3(256), lds, s, V->dense, V->ld, m, n, W,
                            Ht, r, part);
         hipLaunchKernelGGL(k_sum_ordered, dim3(1), dim3(256), 0, s, part, (int64_t)gx * gy,
@@ -605,7 +620,7 @@ hipError_t launch_loss_panel(const float *V, int64_t ld, int64_t rows, int64_t c
         return hipGetLastError();
     }
     const unsigned gx = (unsigned)((cols + LD_T - 1) / LD_T), gy = (unsigned)((rows + LD_T - 1) / LD_T);
-    const size_t lds = (size_t)2 * LD_T * r * sizeof(float);
+    const size_t lds = loss_dense_lds(r);
     hipLaunchKernelGGL(k_loss_dense, dim3(gx, gy), dim3(256), lds, s, V, ld, rows, cols, W, Ht, r, scratch);
     hipLaunchKernelGGL(k_sum_ordered, dim3(1), dim3(256), 0, s, scratch, (int64_t)gx * gy, (int64_t)1,
                        (int64_t)0, slot);
