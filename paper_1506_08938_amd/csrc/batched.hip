@@ -156,6 +156,15 @@ extern "C" int nmf_fit_batched(int32_t count, const nmf_problem *probs, const nm
                 lst.push_back({p, (int32_t)c0, (int32_t)std::min<int64_t>(C, c0 + chunk)});
         }
     }
+    // costliest chunks first (columns x r^2), so that the long ones do not
+    // start at the tail of the launch; order only, never a column's arithmetic
+    // (measured on 1024 uneven problems: 0.87 s against 0.93 s in problem order)
+    for (int h = 0; h < 2; h++)
+        for (auto &kv : hl[h].chunks)
+            std::stable_sort(kv.second.begin(), kv.second.end(), [&](const BSolveChunk &x, const BSolveChunk &y) {
+                const int64_t rx = probs[x.prob].r, ry = probs[y.prob].r;
+                return (int64_t)(x.c1 - x.c0) * rx * rx > (int64_t)(y.c1 - y.c0) * ry * ry;
+            });
     // device copies of the lists (one allocation)
     size_t list_bytes = 0;
     for (int h = 0; h < 2; h++) {
