@@ -123,6 +123,43 @@ def test_csr_product_matches_oracle_including_split_rows(m, n, per_row, r):
         assert d0 < 2.0 ** -8
 
 
+# empty rows and columns of V, a row longer than one chunk (split into partial
+# slots), ranks that are not multiples of 4 or 8: both precisions of the CSR
+# product, and a fit over such a matrix stays finite and matches the oracle
+@pytest.mark.parametrize("r", [5, 33, 127])
+def test_csr_product_and_fit_with_empty_rows_and_columns(r):
+    nat = native()
+    g = np.random.default_rng(300 + r)
+    m, n = 700, 600
+    V = sp.random(m, n, density=0.02, random_state=np.random.RandomState(r), format="lil", dtype=np.float32)
+    V[5, :] = g.random(n)     # one row longer than a chunk (585 > 512 entries)
+    V[10:20, :] = 0           # empty rows
+    V[:, 30:45] = 0           # empty columns
+    V = sp.csr_matrix(V, dtype=np.float32)
+    V.eliminate_zeros()
+    V.data = np.abs(V.data).astype(np.float32) + np.float32(0.01)
+    assert (np.diff(V.indptr) == 0).any() and (np.bincount(V.indices, minlength=n) == 0).any()
+    W = g.random((m, r), dtype=np.float32); Ht = g.random((n, r), dtype=np.float32)
+    Vd = nat.DeviceMatrix(V, with_transpose=True)
+    for trans, A in ((0, W), (1, Ht)):
+        R = oracle.product_csr(V, A, trans)
+        P = H(nat.product(Vd, T(A), trans))
+        Q = oracle.product_csr(V, bf16_round(A), trans)
+        B = H(nat.product(Vd, T(A), trans, precision=nat.NMF_BF16))
+        assert np.abs(P - R).max() <= 5e-6 * np.abs(R).max()
+        assert np.abs(B - Q).max() <= 5e-6 * np.abs(Q).max()
+        assert not P[np.diff(V.indptr if trans else sp.csc_matrix(V).indptr) == 0].any()
+    reg = f32((0.01, 0.02, 0.05, 0.01))
+    W0, Ht0 = synth.start_point(m, n, r, 301 + r)
+    for prec in (0, 1):
+        Wg, Hg, tr, st = run_fit(V, r, reg, W0, Ht0, 3, precision=prec, **FIXED)
+        assert np.isfinite(Wg).all() and np.isfinite(Hg).all() and (Wg >= 0).all() and (Hg >= 0).all()
+        assert np.isfinite(tr).all() and st["outer_done"] == 3
+    Wg, Hg, tr, _ = run_fit(V, r, reg, W0, Ht0, 1, **FIXED)
+    o = oracle.nmf_fit(V, r, reg, W0, Ht0, T=1, **FIXED)
+    assert abs(tr[1] - o["loss"][1]) / o["loss"][1] < 1e-4
+
+
 # --------------------------------------------------------------------------- objective
 # r covers the three gather widths of the CSR cross term (r % 4 == 0, r % 2
 # == 0, odd), one and two rank halves (r <= 64 < r) and the largest rank; the
