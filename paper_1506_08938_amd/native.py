@@ -231,11 +231,16 @@ class DeviceMatrix:
         self.keep = []
         m = NmfMatrix()
         if isinstance(V, torch.Tensor):
-            _dev(V, torch.float32, "V")
+            # row-major rows with a leading dimension >= cols (a column slice
+            # of a wider matrix is fine)
+            if not V.is_cuda or V.dtype != torch.float32:
+                raise TypeError("dense V must be a float32 CUDA (HIP) tensor")
+            if V.dim() != 2 or (V.shape[0] > 1 and V.stride(0) < V.shape[1]) or (V.shape[1] > 1 and V.stride(1) != 1):
+                raise ValueError("dense V must be 2-D with unit column stride and row stride >= its columns")
             m.kind = NMF_DENSE
             m.rows, m.cols = V.shape
             m.dense = V.data_ptr()
-            m.ld = V.shape[1]
+            m.ld = max(V.stride(0), V.shape[1]) if V.shape[0] > 1 else V.shape[1]
             self.keep.append(V)
         else:  # scipy CSR on the host, or a dict of device arrays
             import numpy as np

@@ -83,6 +83,39 @@ def test_dense_product_matches_oracle(m, n, r):
         assert errb < 1e-2
 
 
+# dense V as a column slice of a wider matrix (leading dimension > n, not a
+# multiple of 4): products, objective and a fit equal those of the compact copy
+@pytest.mark.parametrize("prec", [0, 1])
+def test_dense_leading_dimension(prec):
+    nat = native()
+    import torch
+    m, n, r, pad = 301, 203, 24, 5
+    V = synth.dense_lowrank(m, n, r, 71, "uniform", 0.01)
+    wide = np.zeros((m, n + pad), dtype=np.float32)
+    wide[:, :n] = V
+    Vs = T(wide)[:, :n]
+    assert not Vs.is_contiguous() and Vs.stride(0) == n + pad
+    Vw, Vc = nat.DeviceMatrix(Vs), nat.DeviceMatrix(T(V))
+    assert Vw.m.ld == n + pad
+    g = np.random.default_rng(72)
+    W = g.random((m, r), dtype=np.float32); Ht = g.random((n, r), dtype=np.float32)
+    for trans, A in ((0, W), (1, Ht)):
+        assert np.array_equal(H(nat.product(Vw, T(A), trans, precision=prec)),
+                              H(nat.product(Vc, T(A), trans, precision=prec)))
+    reg = nat.reg(0.01, 0.02, 0.0, 0.01)
+    assert nat.objective(Vw, r, reg, T(W), T(Ht)) == nat.objective(Vc, r, reg, T(W), T(Ht))
+    W0, Ht0 = synth.start_point(m, n, r, 73)
+    out = []
+    for Vd in (Vw, Vc):
+        Wd, Hd = T(W0), T(Ht0)
+        tr, _ = nat.fit(Vd, r, reg, nat.opts(max_outer=3, precision=prec), Wd, Hd)
+        out.append((H(Wd), H(Hd), tr))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    assert np.array_equal(out[0][2], out[1][2])
+    with pytest.raises(ValueError):
+        nat.DeviceMatrix(T(wide)[:, ::2])
+
+
 def small_text(m, n, per_row, seed=3):
     return synth.sparse_text(m, n, per_row, seed)
 
