@@ -170,8 +170,10 @@ NMF_API int nnls_layout(int32_t r, int64_t ncols, int32_t lanes, int32_t *E, int
  * nmf_gram:    G (r x r) = A'A + 2 l2 I for A (k x r).
  * nmf_product: trans = 0: P (n x r) = (W'V)' with A = W (m x r);
  *              trans = 1: P (m x r) = V Ht   with A = Ht (n x r).
- * precision as in nmf_opts.  Sparse V with trans = 0 needs CSR(V') (the
- * t_* arrays). */
+ * precision as in nmf_opts (BF16 makes temporary BF16 copies of what it
+ * reads).  Sparse V with trans = 0 reads CSR(V') (the t_* arrays) when
+ * given, else builds a temporary one; the CSR form plans its work on the
+ * host and synchronises the stream, the dense form is stream-ordered. */
 NMF_API int nmf_gram(const float *A, int64_t k, int32_t r, float l2, int32_t precision, float *G,
              void *stream);
 NMF_API int nmf_product(const nmf_matrix *V, int32_t trans, int32_t r, const float *A, int32_t precision,
