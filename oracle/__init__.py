@@ -61,6 +61,9 @@ def lib():
         L.oracle_nqp_trace.argtypes = [ctypes.c_int, _d, _d, _d, ctypes.c_int, ctypes.c_double,
                                        ctypes.c_int, _d]
         L.oracle_nqp_trace.restype = ctypes.c_int
+        L.oracle_nqp_batch_cdtrace.argtypes = [ctypes.c_int, ctypes.c_long, _d, _d, _d, ctypes.c_int,
+                                               ctypes.c_double, ctypes.c_int, ctypes.c_int, _i, _d]
+        L.oracle_nqp_batch_cdtrace.restype = ctypes.c_long
         L.oracle_nqp_batch_faststop.argtypes = [ctypes.c_int, ctypes.c_long, _d, _d, _d, ctypes.c_int,
                                                 ctypes.c_double, ctypes.c_int, ctypes.c_long, _i, _d]
         L.oracle_nqp_batch_faststop.restype = ctypes.c_long
@@ -139,6 +142,24 @@ def nqp_trace(H, h, x0, max_inner=100, eps=1e-3, ls_guard=1):
     k = lib().oracle_nqp_trace(r, _p(H), _p(h), _p(x), int(max_inner), float(eps), int(ls_guard),
                                _p(nk))
     return x, k, nk[:k + 1]
+
+
+def nqp_batch_cdtrace(H, h, x0, max_inner=100, eps=1e-3, ls_guard=1, trace_iters=None):
+    """Independent NQPs sharing H (the results of nqp_batch) with a record of
+    every greedy CD choice of the first trace_iters (default max_inner)
+    iterations.  Returns (x, iters, cd) with cd of shape (ncols, trace_iters,
+    r, 6): per CD step the chosen coordinate (-1: the sweep ended there; -2:
+    not reached), the decrease of that choice, the largest decrease among the
+    other coordinates (-1: none), |delta| of both, and the size of the terms
+    of the gradient, max_i (|q_i| + sum_j |Q_ij y_j|)."""
+    H = _f64(H); h = _f64(h); x = _f64(x0).copy()
+    ncols, r = h.shape
+    ti = int(max_inner if trace_iters is None else min(trace_iters, max_inner))
+    it = np.zeros(ncols, dtype=np.int32)
+    cd = np.full((ncols, ti, r, 6), -2.0)
+    lib().oracle_nqp_batch_cdtrace(r, ncols, _p(H), _p(h), _p(x), int(max_inner), float(eps),
+                                   int(ls_guard), ti, _p(it, _i), _p(cd))
+    return x, it, cd
 
 
 def nqp_batch_faststop(H, h, x0, chunk, max_inner=100, eps=1e-3, ls_guard=1):

@@ -35,6 +35,9 @@
 #define ORACLE_NO_CD      2 /* skip the greedy coordinate-descent sweep  */
 #define ORACLE_NO_LS      4 /* skip the exact line search                 */
 
+/* Doubles recorded per coordinate-descent step by oracle_nqp_cdtrace. */
+#define CD_TRACE_FIELDS 6
+
 int oracle_num_threads(void) {
 #ifdef _OPENMP
     return omp_get_max_threads();
@@ -119,16 +122,16 @@ static double quad_form_value(int r, const double *Q, const double *q, const dou
  * (optional, max_inner + 1 entries) gets ||f~_k||^2 for k = 0..iters. */
 static int nqp_core(int r, const double *H, const double *h, double *x, int max_inner, double eps,
                     int ls_guard, int flags, double *fk, double max_stop, double *nk_out,
-                    double *nk_trace);
+                    double *nk_trace, double *cd_trace, int trace_iters);
 
 int oracle_nqp_flags(int r, const double *H, const double *h, double *x, int max_inner, double eps,
                      int ls_guard, int flags, double *fk) {
-    return nqp_core(r, H, h, x, max_inner, eps, ls_guard, flags, fk, -1.0, NULL, NULL);
+    return nqp_core(r, H, h, x, max_inner, eps, ls_guard, flags, fk, -1.0, NULL, NULL, NULL, 0);
 }
 
 static int nqp_core(int r, const double *H, const double *h, double *x, int max_inner, double eps,
                     int ls_guard, int flags, double *fk, double max_stop, double *nk_out,
-                    double *nk_trace) {
+                    double *nk_trace, double *cd_trace, int trace_iters) {
     double *Q = (double *)malloc(sizeof(double) * (size_t)r * r);
     double *buf = (double *)malloc(sizeof(double) * (size_t)r * 8);
     int *frozen = (int *)malloc(sizeof(int) * (size_t)r);
@@ -199,14 +202,35 @@ static int nqp_core(int r, const double *H, const double *h, double *x, int max_
         if (!(flags & ORACLE_NO_CD)) {
             for (int t = 0; t < r; t++) {
                 int p = -1;
-                double best = 0.0, dp = 0.0;
+                double best = 0.0, dp = 0.0, second = -1.0, dsec = 0.0;
                 for (int i = 0; i < r; i++) {
                     if (frozen[i]) continue;
                     double qii = Q[(size_t)i * r + i];
                     double v = y[i] - g[i] / qii;
                     double delta = (v > 0.0 ? v : 0.0) - y[i];
                     double dec = fabs(g[i] * delta + 0.5 * qii * delta * delta);
-                    if (p < 0 || dec > best) { p = i; best = dec; dp = delta; }
+                    if (p < 0 || dec > best) {
+                        if (p >= 0) { second = best; dsec = dp; }
+                        p = i; best = dec; dp = delta;
+                    } else if (dec > second) {
+                        second = dec; dsec = delta;
+                    }
+                }
+                if (cd_trace && k <= trace_iters) { /* record only: the step is unchanged */
+                    double *e = cd_trace + CD_TRACE_FIELDS * ((size_t)(k - 1) * r + t);
+                    double gs = 0.0; /* magnitude of the terms that make up g */
+                    for (int i = 0; i < r; i++) {
+                        if (frozen[i]) continue;
+                        double a = fabs(q[i]);
+                        for (int j = 0; j < r; j++) a += fabs(Q[(size_t)i * r + j] * y[j]);
+                        if (a > gs) gs = a;
+                    }
+                    e[0] = (p < 0 || !(best > 0.0)) ? -1.0 : (double)p;
+                    e[1] = best;
+                    e[2] = second;
+                    e[3] = fabs(dp);
+                    e[4] = fabs(dsec);
+                    e[5] = gs;
                 }
                 if (p < 0 || !(best > 0.0)) break; /* every remaining step is a no-op */
                 for (int i = 0; i < r; i++) g[i] += Q[(size_t)i * r + p] * dp;
@@ -248,7 +272,39 @@ long oracle_nqp_batch(int r, long ncols, const double *H, const double *h, doubl
  * (k = 0..iters) written to nk_trace; no fast-break. */
 int oracle_nqp_trace(int r, const double *H, const double *h, double *x, int max_inner, double eps,
                      int ls_guard, double *nk_trace) {
-    return nqp_core(r, H, h, x, max_inner, eps, ls_guard, 0, NULL, -1.0, NULL, nk_trace);
+    return nqp_core(r, H, h, x, max_inner, eps, ls_guard, 0, NULL, -1.0, NULL, nk_trace, NULL, 0);
+}
+
+/* Independent NQPs sharing H (h, x: ncols x r; iters optional), with a
+ * record of every greedy coordinate-descent choice of the first trace_iters
+ * iterations, for telling rounding-sensitive columns apart: column j's block
+ * of cd_trace has trace_iters * r entries of CD_TRACE_FIELDS doubles, entry
+ * (k, t) for CD step t of iteration k + 1: the chosen coordinate p (-1 for the step at which the
+ * sweep ended because no coordinate decreases f), the decrease
+ * |f(y) - f(y + delta_p e_p)| of that choice, the largest decrease among the
+ * other coordinates (-1 when there is none), |delta| of the choice and of
+ * that runner-up, and max_i (|q_i| + sum_j |Q_ij y_j|), the size of the
+ * terms the gradient is made of (its rounding error in a lower precision
+ * scales with it).  A gap between the two decreases that is small against
+ * the rounding error of the decreases marks a near-tie, which a computation
+ * in lower precision may resolve the other way.  Steps after the end of a
+ * sweep and iterations not run are not written (the caller initialises
+ * them).  The arithmetic of the solve is that of oracle_nqp. */
+
+
+long oracle_nqp_batch_cdtrace(int r, long ncols, const double *H, const double *h, double *x,
+                              int max_inner, double eps, int ls_guard, int trace_iters, int *iters,
+                              double *cd_trace) {
+    long total = 0;
+    const size_t blk = (size_t)trace_iters * r * CD_TRACE_FIELDS;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : total)
+    for (long j = 0; j < ncols; j++) {
+        int k = nqp_core(r, H, h + (size_t)j * r, x + (size_t)j * r, max_inner, eps, ls_guard, 0,
+                         NULL, -1.0, NULL, NULL, cd_trace + (size_t)j * blk, trace_iters);
+        if (iters) iters[j] = k;
+        total += k;
+    }
+    return total;
 }
 
 /* Independent NQPs with the fast-break of Algorithm 3: the columns are cut
@@ -271,7 +327,7 @@ long oracle_nqp_batch_faststop(int r, long ncols, const double *H, const double 
         for (long j = c * chunk; j < j1; j++) {
             double fin = 0.0;
             int k = nqp_core(r, H, h + (size_t)j * r, x + (size_t)j * r, max_inner, eps, ls_guard, 0,
-                             NULL, max_stop, &fin, NULL);
+                             NULL, max_stop, &fin, NULL, NULL, 0);
             if (fin > max_stop) max_stop = fin;
             if (iters) iters[j] = k;
             if (nk) nk[j] = fin;

@@ -102,6 +102,78 @@ def test_worked_example_rescaled_method_needs_one_iteration():
     assert np.allclose(x, xs, rtol=1e-12)
 
 
+def _first_iteration_2d_decimal(H, h, x0):
+    """The first iteration of Algorithm 3 on a 2-variable NQP, written out for
+    two variables in 50-digit decimal arithmetic (independent of the oracle's
+    code): rescale to unit diagonal, the exact projected line search with the
+    guard, two greedy coordinate steps (lowest index on ties), the projected
+    gradient norms before and after, and the unscaled point."""
+    from decimal import Decimal, localcontext
+    with localcontext() as ctx:
+        ctx.prec = 50
+        Hd = [[Decimal(repr(float(v))) for v in row] for row in H]
+        hd = [Decimal(repr(float(v))) for v in h]
+        sq = [Hd[0][0].sqrt(), Hd[1][1].sqrt()]
+        off = Hd[0][1] / (sq[0] * sq[1])
+        Q = [[Decimal(1), off], [off, Decimal(1)]]
+        q = [hd[0] / sq[0], hd[1] / sq[1]]
+        y = [Decimal(repr(float(x0[0]))) * sq[0], Decimal(repr(float(x0[1]))) * sq[1]]
+
+        def mv(v):
+            return [Q[0][0] * v[0] + Q[0][1] * v[1], Q[1][0] * v[0] + Q[1][1] * v[1]]
+
+        def pgrad(y, g):
+            return [gi if (yi > 0 or gi < 0) else Decimal(0) for yi, gi in zip(y, g)]
+
+        g = [a + b for a, b in zip(mv(y), q)]
+        pg = pgrad(y, g)
+        n0 = pg[0] ** 2 + pg[1] ** 2
+        u = mv(pg)
+        alpha = n0 / (pg[0] * u[0] + pg[1] * u[1])
+        step = [max(Decimal(0), yi - alpha * gi) - yi for yi, gi in zip(y, pg)]
+        w = mv(step)
+        if g[0] * step[0] + g[1] * step[1] + (step[0] * w[0] + step[1] * w[1]) / 2 <= 0:
+            y = [a + b for a, b in zip(y, step)]
+            g = [a + b for a, b in zip(g, w)]
+        for _ in range(2):
+            cand = []
+            for i in range(2):
+                delta = max(Decimal(0), y[i] - g[i]) - y[i]
+                cand.append((abs(g[i] * delta + delta * delta / 2), i, delta))
+            dec, p, delta = max(cand, key=lambda c: (c[0], -c[1]))
+            if not dec > 0:
+                break
+            g = [g[0] + Q[0][p] * delta, g[1] + Q[1][p] * delta]
+            y[p] += delta
+        pg = pgrad(y, g)
+        n1 = pg[0] ** 2 + pg[1] ** 2
+        return [float(y[0] / sq[0]), float(y[1] / sq[1])], float(n1 / n0)
+
+
+def test_worked_example_first_iteration_point():
+    # Section 3.4's example: one iteration of Algorithm 3 (under the readings
+    # of the stopping quantity, the CD count and the tie rule) reaches
+    # x = (79.08014973, 9.19850272) with f - f* = 5.73e-4 and
+    # ||f~_1||^2 / ||f~_0||^2 = 7.0e-8, so it stops after one iteration for any
+    # eps >= 7.01e-8 -- the paper's "only one iteration".
+    ex = json.load(open(os.path.join(GOLD, "worked_example.json")))
+    H = np.array(ex["H"]); h = np.array(ex["h"])
+    xd, ratio_d = _first_iteration_2d_decimal(H, h, ex["x0"])
+    assert xd == pytest.approx([79.08014973, 9.19850272], rel=1e-9)
+    assert ratio_d == pytest.approx(7.008e-8, rel=1e-3)
+    x, k = oracle.nqp(H, h, ex["x0"], max_inner=1, eps=0.0)
+    assert k == 1
+    assert np.allclose(x, xd, rtol=1e-12)
+    assert np.allclose(x, [79.08014973, 9.19850272], rtol=1e-8)
+    assert f_val(H, h, x) - ex["f_star"] == pytest.approx(5.73e-4, rel=2e-3)
+    _, _, nk = oracle.nqp_trace(H, h, ex["x0"], max_inner=1, eps=0.0)
+    assert nk[1] / nk[0] == pytest.approx(ratio_d, rel=1e-9)
+    # the accelerated stopping rule: one iteration for eps just above the
+    # ratio, two just below it
+    assert oracle.nqp(H, h, ex["x0"], max_inner=100, eps=7.01e-8)[1] == 1
+    assert oracle.nqp(H, h, ex["x0"], max_inner=100, eps=6.99e-8)[1] == 2
+
+
 # --------------------------------------------------------------------------- closed forms
 @pytest.mark.parametrize("seed", range(6))
 def test_r1_closed_form_in_one_iteration(seed):
@@ -154,6 +226,36 @@ def test_kkt_residual_vanishes_at_convergence():
     assert np.abs(np.minimum(x, gr)).max() < 1e-10 * max(1.0, np.abs(h).max())
     res = oracle.kkt(H, (-h)[None, :], 0.0, x[None, :])
     assert res[0] == pytest.approx(np.abs(np.minimum(x, gr)).max(), abs=1e-12)
+
+
+def test_kkt_reports_each_condition_separately():
+    # With Gamma = I the gradient of column j is g = x - P_j + l1, so choosing
+    # P = x + l1 - g plants any gradient.  Values are dyadic (exact in FP64).
+    G = np.eye(3)
+    l1 = 0.25
+    X = np.array([[1.5, 0.0, -0.375],     # a negative entry (nonnegativity)
+                  [2.0, 0.0, 0.0],        # g = 0.5 on a positive entry (complementarity)
+                  [0.0, 0.0, 0.5]])       # g = -0.75 on a zero entry
+    g = np.array([[0.0, 0.125, 0.0],
+                  [0.5, 1.0, 0.0],
+                  [-0.75, 0.0, 0.0]])
+    P = X + l1 - g
+    res = oracle.kkt(G, P, l1, X)
+    assert res[0] == 0.75                  # max |min(x, g)|: the zero entry with g = -0.75
+    assert res[1] == 0.375                 # max(0, -min x)
+    assert res[2] == 1.0                   # max x |g| = 2.0 * 0.5
+    assert res[3] == 0.75                  # max(0, -min g over x == 0)
+    # at a converged solution every condition holds to rounding
+    A, b, H, h = random_nqp(30, 11, l1=0.05)
+    xs = lawson_hanson_nqp(H, h)
+    xs = np.maximum(xs, 0.0)
+    xo, _ = oracle.nqp(H, h, np.ones(30), max_inner=5000, eps=0.0)
+    for x in (xs, xo):
+        res = oracle.kkt(H, (-h)[None, :], 0.0, x[None, :])
+        scale = max(1.0, np.abs(h).max())
+        assert res[1] == 0.0
+        assert res[2] < 1e-9 * scale * max(1.0, x.max())
+        assert res[3] < 1e-9 * scale
 
 
 # --------------------------------------------------------------------------- invariants
