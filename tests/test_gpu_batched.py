@@ -5,6 +5,7 @@ oracle."""
 import numpy as np
 import pytest
 
+import fp32_sensitivity
 import oracle
 from paper_1506_08938_amd import synth
 
@@ -63,20 +64,22 @@ def test_batched_one_step_matches_oracle():
     batch = [dict(V=T(p["V"]), r=p["r"], reg=nat.reg(*p["reg"]), W=T(w), Ht=T(h))
              for p, (w, h) in zip(probs, states)]
     nat.fit_batched(batch, nat.opts(max_outer=1, **FIX), want_stats=False)
-    # These problems are exactly low rank plus 1% noise, so after a few
-    # iterations J is a small fraction of J(0) = ||V||^2 / 2 and FP32 rounding
-    # of the products (relative 1e-7 of ||V||^2) shows up amplified in J / J.
-    # The bound is on the error relative to J(0); J / J is printed.
-    worst = worst_rel = 0.0
-    for p, (w, h), b in zip(probs, states, batch):
+    # Each problem's objective within twice the FP64 oracle's own spread under
+    # float32-sized disturbances of the same step (fp32_sensitivity.py).  These
+    # problems are exactly low rank plus 1% noise, so J is a small fraction of
+    # ||V||^2 / 2 and float32 rounding of the products shows up amplified in
+    # |dJ| / J: the oracle's own spread here is 9e-6 .. 6e-2 of J.
+    worst = 0.0
+    for i, (p, (w, h), b) in enumerate(zip(probs, states, batch)):
         o = oracle.nmf_fit(p["V"], p["r"], p["reg"], w, h, T=1, want_trace=False, **FIX)
         Jg = oracle.objective(p["V"], H(b["W"]), H(b["Ht"]), p["reg"])
         Jo = oracle.objective(p["V"], o["W"], o["Ht"], p["reg"])
-        J0 = 0.5 * float(np.sum(np.asarray(p["V"], dtype=np.float64) ** 2))
-        worst = max(worst, abs(Jg - Jo) / J0)
-        worst_rel = max(worst_rel, abs(Jg - Jo) / Jo)
-    print(f"batched one step from oracle states: worst |dJ|/J(0) {worst:.2e}, |dJ|/J {worst_rel:.2e}")
-    assert worst < 1e-6
+        S = fp32_sensitivity.spread(p["V"], p["r"], p["reg"], w, h, 1, seeds=range(1, 6), **FIX)
+        rel = abs(Jg - Jo) / Jo
+        worst = max(worst, rel / S["dJ"])
+        print(f"problem {i} {p['V'].shape} r={p['r']}: |dJ|/J {rel:.2e}, oracle spread {S['dJ']:.2e}")
+        assert rel <= 2 * S["dJ"], i
+    print(f"batched one step from oracle states: largest |dJ|/J over the oracle's spread {worst:.2f}")
 
 
 def test_batched_edge_cases():

@@ -5,7 +5,9 @@ import numpy as np
 import pytest
 import scipy.sparse as sp
 
+import fp32_sensitivity
 import oracle
+from near_ties import near_tied
 from paper_1506_08938_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -229,13 +231,21 @@ def test_fit_kkt_matches_oracle(r, m, n):
     _, st = nat.fit(Vd, r, nat.reg(*reg), nat.opts(max_outer=1, max_inner=5), Wd, Hd, want_trace=False)
     # H-update: Gram of the start W, product with the start W, the new Ht
     Gw = H(nat.gram(T(W0), reg[3])); Pw = H(nat.product(Vd, T(W0), 0))
-    kh = oracle.kkt(Gw, Pw, reg[2], H(Hd))[0]
+    kh = oracle.kkt(Gw, Pw, reg[2], H(Hd))
     # W-update: Gram of the new Ht, product with it, the new W
     Gh = H(nat.gram(Hd, reg[1])); Ph = H(nat.product(Vd, Hd, 1))
-    kw = oracle.kkt(Gh, Ph, reg[0], H(Wd))[0]
-    print(f"kkt r={r}: H {st['kkt_h']:.6e} vs {kh:.6e}, W {st['kkt_w']:.6e} vs {kw:.6e}")
-    assert st["kkt_h"] == pytest.approx(kh, rel=1e-9)
-    assert st["kkt_w"] == pytest.approx(kw, rel=1e-9)
+    kw = oracle.kkt(Gh, Ph, reg[0], H(Wd))
+    print(f"kkt r={r}: H {st['kkt_h']:.6e} {st['kkt_h_cond']} vs {kh}, "
+          f"W {st['kkt_w']:.6e} {st['kkt_w_cond']} vs {kw}")
+    assert st["kkt_h"] == pytest.approx(kh[0], rel=1e-9)
+    assert st["kkt_w"] == pytest.approx(kw[0], rel=1e-9)
+    # the three conditions separately: the solve never leaves x >= 0 (so
+    # nonnegativity is exactly 0); complementarity and the gradient on zero
+    # entries as the oracle computes them from the same Gram and product
+    for got, ref in ((st["kkt_h_cond"], kh), (st["kkt_w_cond"], kw)):
+        assert got[0] == 0.0 and ref[1] == 0.0
+        assert got[1] == pytest.approx(ref[2], rel=1e-9)
+        assert got[2] == pytest.approx(ref[3], rel=1e-9, abs=1e-300)
 
 
 # --------------------------------------------------------------------------- fit
@@ -251,45 +261,94 @@ def rel_fro(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
-# Parity of an iterative method: one outer iteration from the same state must
-# agree with the oracle (the GPU iterates in float32, the oracle in float64).
-# Over many outer iterations the two trajectories separate: NMF's slow,
-# flat valleys do not contract a 1e-7 difference, so long runs are compared
-# on the objective they reach (and on kbar) at a looser tolerance.
+# Parity of an iterative method.  The GPU iterates in float32, the oracle in
+# float64, so the GPU's result may differ from the oracle's by as much as the
+# oracle's own result moves when its intermediate quantities are disturbed at
+# float32 size (fp32_sensitivity.py: Gram, product and factors rounded to
+# float32 between the calls; the start point nudged by one ulp; float32-sized
+# accumulation errors).  Each bound below is twice that spread, measured on the
+# same inputs with the same options; the printed lines give both numbers.
+# Where the GPU reaches the 1e-6 relative objective of a float32 computation
+# (one step from a converging state), that is asserted as well.
 # Fixed-K mode (eps = 0) keeps the accelerated stopping rule from flipping a
 # column's iteration count, which would move that column by O(sqrt(eps)).
 FIXED = dict(max_inner=10, eps=0.0)
 
 
-def step_parity(V, r, reg, W0, Ht0, t_before, opts):
-    """State after t_before oracle iterations, then one more on both sides."""
+def half_columns(V, A, trans, l1, l2, X0, Xg, opts):
+    """One half-iteration's NQPs recomputed by the oracle from the GPU's own
+    fixed factor A and start X0: per-column error of the GPU's solutions Xg,
+    relative to max(|x|, distance moved), and the oracle's near-tie flags."""
+    P = oracle.product_csr(V, A, trans) if sp.issparse(V) else oracle.product_dense(V, A, trans)
+    G = oracle.gram(A, l2)
+    X0 = np.asarray(X0, dtype=np.float64)
+    xo, _, cd = oracle.nqp_batch_cdtrace(G, -P + l1, X0, trace_iters=min(opts["max_inner"], 10), **opts)
+    e = np.linalg.norm(Xg - xo, axis=1) / np.maximum(
+        np.maximum(np.linalg.norm(xo, axis=1), np.linalg.norm(X0 - xo, axis=1)), 1e-30)
+    return e, near_tied(cd)
+
+
+def step_parity(V, r, reg, W0, Ht0, t_before, opts, T=1, seeds=(1, 2, 3)):
+    """State after t_before oracle iterations, then T more on both sides and
+    in the oracle's disturbed runs.  For T = 1 also each half's columns: the
+    H-update from the common start, the W-update from the GPU's new Ht."""
     if t_before:
         st = oracle.nmf_fit(V, r, reg, W0, Ht0, T=t_before, want_trace=False, **opts)
         W0, Ht0 = st["W"].astype(np.float32), st["Ht"].astype(np.float32)
-    Wg, Hg, tr, stg = run_fit(V, r, reg, W0, Ht0, 1, **opts)
-    o = oracle.nmf_fit(V, r, reg, W0, Ht0, T=1, **opts)
+    Wg, Hg, tr, stg = run_fit(V, r, reg, W0, Ht0, T, **opts)
+    o = oracle.nmf_fit(V, r, reg, W0, Ht0, T=T, **opts)
     Jg = oracle.objective(V, Wg, Hg, reg)
     Jo = oracle.objective(V, o["W"], o["Ht"], reg)
-    return abs(Jg - Jo) / Jo, rel_fro(Wg, o["W"]), rel_fro(Hg, o["Ht"]), abs(tr[1] - o["loss"][1]) / o["loss"][1]
+    sens = fp32_sensitivity.spread(V, r, reg, W0, Ht0, T, seeds=seeds, **opts)
+    m, n = V.shape
+    kbar_o = o["inner"].sum() / (T * (m + n))
+    d = dict(J=abs(Jg - Jo) / Jo, W=rel_fro(Wg, o["W"]), H=rel_fro(Hg, o["Ht"]),
+             loss=float(np.max(np.abs(tr[1:] - o["loss"][1:]) / o["loss"][1:])),
+             loss0=abs(tr[0] - o["loss"][0]) / o["loss"][0],
+             kbar=abs(stg["kbar"] - kbar_o) / kbar_o, S=sens, halves=None)
+    if T == 1:
+        l1w, l2w, l1h, l2h = reg
+        d["halves"] = (half_columns(V, np.asarray(W0, np.float64), 0, l1h, l2h, Ht0, Hg, opts),
+                       half_columns(V, Hg, 1, l1w, l2w, W0, Wg, opts))
+    return d
 
 
-# Tolerances.  From the random start the first W-update's NQPs are far from
-# converged after K = 10 iterations, so float32 differences (and near-tied
-# greedy choices) persist: J within 1e-4, factors within 1e-2.  From a
-# converging state the solve reaches its float32 floor, x within about
-# kappa(Q) * 2^-24 per column; the objective then agrees within 1e-6, except
-# on the low-rank workload whose loss is 5e-5 of ||V||^2 (a noise-floor fit,
-# where that floor shows as 1.2e-6 .. 1.4e-6): 2e-6 there.
+def report(label, d):
+    S = d["S"]
+    line = (f"{label}: J rel {d['J']:.2e} (oracle spread {S['dJ']:.2e}); W {d['W']:.2e} ({S['dW']:.2e}); "
+            f"Ht {d['H']:.2e} ({S['dH']:.2e}); loss {d['loss']:.2e} ({S['dloss']:.2e}); "
+            f"kbar {d['kbar']:.2e} ({S['dkbar']:.2e})")
+    if d["halves"]:
+        for name, (e, tie) in zip(("H", "W"), d["halves"]):
+            line += (f"; {name}-half columns: x max {e.max():.2e} p99 {np.quantile(e, .99):.2e}, "
+                     f"near-tied {tie.mean():.3f}, without x max {e[~tie].max() if (~tie).any() else 0:.2e}")
+    print(line)
+
+
+def assert_within_spread(d, loss=False):
+    """The objective (and over a trajectory the loss and kbar; after one step
+    the factors) within twice the oracle's own float32-sized spread; each
+    half's columns: any column off by more than 1e-4 had a near-tied greedy
+    choice in the oracle's path."""
+    S = d["S"]
+    assert d["J"] <= 2 * S["dJ"]
+    if d["halves"]:
+        assert d["W"] <= 2 * S["dW"] and d["H"] <= 2 * S["dH"]
+    if loss:
+        assert d["loss"] <= 2 * S["dloss"]
+        assert d["kbar"] <= 2 * S["dkbar"]
+    assert d["loss0"] < 1e-12
+    if d["halves"]:
+        for e, tie in d["halves"]:
+            assert not ((e > 1e-4) & ~tie).any()
+
+
 @pytest.mark.parametrize("t_before", [0, 5, 30])
 def test_outer_iteration_parity_dense_workload1(t_before):
     wl = synth.workload1()
-    J, w, h, l = step_parity(wl["V"], wl["r"], wl["reg"], wl["W0"], wl["Ht0"], t_before, FIXED)
-    print(f"workload1 step after {t_before}: J rel {J:.2e} loss rel {l:.2e} W {w:.2e} Ht {h:.2e}")
-    if t_before == 0:
-        assert J < 1e-4 and w < 1e-2 and h < 1e-2
-    else:
-        assert J < 2e-6 and l < 2e-6
-        assert w < 1e-4 and h < 1e-4
+    d = step_parity(wl["V"], wl["r"], wl["reg"], wl["W0"], wl["Ht0"], t_before, FIXED)
+    report(f"workload1 step after {t_before}", d)
+    assert_within_spread(d)
 
 
 @pytest.mark.parametrize("reg", [(0.0, 0.01, 0.0, 0.01), (0.05, 0.0, 0.1, 0.02)])
@@ -298,13 +357,11 @@ def test_outer_iteration_parity_dense_regularised(reg, t_before):
     reg = f32(reg)
     V = synth.dense_lowrank(400, 300, 16, 77, "gamma", 0.05)
     W0, Ht0 = synth.start_point(400, 300, 16, 78)
-    J, w, h, l = step_parity(V, 16, reg, W0, Ht0, t_before, FIXED)
-    print(f"dense reg {reg} step after {t_before}: J rel {J:.2e} W {w:.2e} Ht {h:.2e}")
-    if t_before == 0:
-        assert J < 1e-4 and w < 1e-2 and h < 1e-2
-    else:
-        assert J < 1e-6
-        assert w < 1e-4 and h < 1e-4
+    d = step_parity(V, 16, reg, W0, Ht0, t_before, FIXED)
+    report(f"dense reg {reg} step after {t_before}", d)
+    assert_within_spread(d)
+    if t_before:
+        assert d["J"] < 1e-6
 
 
 @pytest.mark.parametrize("t_before", [0, 3])
@@ -313,36 +370,32 @@ def test_outer_iteration_parity_sparse(t_before):
     r = 100
     W0, Ht0 = synth.start_point(2000, 1500, r, 12)
     reg = f32((0.0, 0.01, 0.1, 0.0))
-    J, w, h, l = step_parity(V, r, reg, W0, Ht0, t_before, FIXED)
-    print(f"sparse step after {t_before}: J rel {J:.2e} W {w:.2e} Ht {h:.2e}")
-    if t_before == 0:
-        assert J < 1e-4 and w < 1e-2 and h < 1e-2
-    else:
-        assert J < 1e-6
-        assert w < 1e-4 and h < 1e-4
+    d = step_parity(V, r, reg, W0, Ht0, t_before, FIXED)
+    report(f"sparse step after {t_before}", d)
+    assert_within_spread(d)
+    assert d["J"] < 1e-6
 
 
 def test_outer_iteration_parity_adaptive():
     wl = synth.workload1()
-    J, w, h, l = step_parity(wl["V"], wl["r"], wl["reg"], wl["W0"], wl["Ht0"], 10,
-                             dict(max_inner=100, eps=1e-3))
-    print(f"workload1 adaptive step: J rel {J:.2e} W {w:.2e} Ht {h:.2e}")
-    # one iteration-count flip moves a column by O(sqrt(eps))
-    assert J < 5e-5
+    d = step_parity(wl["V"], wl["r"], wl["reg"], wl["W0"], wl["Ht0"], 10, dict(max_inner=100, eps=1e-3))
+    report("workload1 adaptive step", d)
+    assert_within_spread(d)
 
 
+# Long runs: NMF's slow, flat valleys do not contract a float32-sized
+# difference, so the trajectories separate; the oracle's own disturbed runs
+# separate just as far (eight float32-sized accumulation-error draws, the
+# trajectory's spread being a distribution).  The loss over the whole
+# trajectory and kbar are held to twice that spread.  (The factors are not:
+# NMF is not unique, and two equally good trajectories can end at factors
+# that differ far more than their objectives.)
 def test_fit_dense_workload1_trajectory():
     wl = synth.workload1()
-    Wg, Hg, tr, st = run_fit(wl["V"], wl["r"], wl["reg"], wl["W0"], wl["Ht0"], wl["T"])
-    o = oracle.nmf_fit(wl["V"], wl["r"], wl["reg"], wl["W0"], wl["Ht0"], T=wl["T"])
-    kbar_o = o["inner"].sum() / (wl["T"] * sum(wl["V"].shape))
-    lr = np.abs(tr - o["loss"]) / o["loss"]
-    print(f"workload1 50 iterations: loss gpu {tr[-1]:.6e} oracle {o['loss'][-1]:.6e} "
-          f"(max rel {lr.max():.2e}); kbar gpu {st['kbar']:.4f} oracle {kbar_o:.4f}")
-    assert lr[0] < 1e-12
-    assert lr.max() < 1e-2
-    assert abs(st["kbar"] - kbar_o) < 0.02 * kbar_o
-    assert st["outer_done"] == wl["T"]
+    d = step_parity(wl["V"], wl["r"], wl["reg"], wl["W0"], wl["Ht0"], 0, dict(max_inner=100, eps=1e-3),
+                    T=wl["T"], seeds=range(1, 9))
+    report("workload1 50 iterations", d)
+    assert_within_spread(d, loss=True)
 
 
 def test_fit_sparse_trajectory():
@@ -350,14 +403,9 @@ def test_fit_sparse_trajectory():
     r = 100
     W0, Ht0 = synth.start_point(2000, 1500, r, 12)
     reg = f32((0.0, 0.01, 0.1, 0.0))
-    Wg, Hg, tr, st = run_fit(V, r, reg, W0, Ht0, 5)
-    o = oracle.nmf_fit(V, r, reg, W0, Ht0, T=5)
-    kbar_o = o["inner"].sum() / (5 * 3500)
-    lr = np.abs(tr - o["loss"]) / o["loss"]
-    print(f"sparse 5 iterations: loss max rel {lr.max():.2e} kbar gpu {st['kbar']:.4f} "
-          f"oracle {kbar_o:.4f}")
-    assert lr.max() < 1e-2
-    assert abs(st["kbar"] - kbar_o) < 0.02 * kbar_o
+    d = step_parity(V, r, reg, W0, Ht0, 0, dict(max_inner=100, eps=1e-3), T=5, seeds=range(1, 9))
+    report("sparse 5 iterations", d)
+    assert_within_spread(d, loss=True)
 
 
 # BF16 products (dense: V and the factor in BF16 on MFMA; CSR: gathers from a
@@ -462,16 +510,22 @@ def test_foldin_matches_oracle(r):
     req = synth.foldin_columns(m, 300, 50, seed=r)   # CSR of the request's transpose
     Gd = oracle.gram(W, l2)
     P = oracle.product_csr(req, W, 1)                # (c x r) = Vnew' W
-    xo, ito = oracle.nqp_batch(Gd.astype(np.float32), (-P + l1).astype(np.float32),
-                               np.zeros((300, r)), max_inner=100, eps=1e-3)
+    xo, ito, cd = oracle.nqp_batch_cdtrace(Gd.astype(np.float32), (-P + l1).astype(np.float32),
+                                           np.zeros((300, r)), max_inner=100, eps=1e-3, trace_iters=10)
     it = T(np.zeros(300), np.int32)
     # sparse request: CSR(Vnew') in the t_* arrays, rows = m, cols = c
     Vs = foldin_matrix(nat, req, m)
     out = H(B.foldin(Vs, iters=it))
     e = np.linalg.norm(out - xo, axis=1) / np.maximum(np.linalg.norm(xo, axis=1), 1e-30)
-    print(f"foldin r={r}: x rel median {np.median(e):.2e} p99 {np.quantile(e, .99):.2e}; "
-          f"iters gpu {H(it).mean():.3f} oracle {ito.mean():.3f}")
-    assert np.median(e) < 1e-3
+    tie = near_tied(cd) | (ito > 10)
+    print(f"foldin r={r}: x rel median {np.median(e):.2e} p99 {np.quantile(e, .99):.2e} max {e.max():.2e}; "
+          f"iters gpu {H(it).mean():.3f} oracle {ito.mean():.3f}; near-tied {tie.mean():.3f}, "
+          f"without x max {e[~tie].max():.2e}")
+    # measured on MI355X: median 5.5e-7 / 1.7e-6, p99 1.1e-6 / 3.1e-6 (r = 16 / 128);
+    # one column at r = 128 off by 4.8e-4
+    assert np.median(e) < 1e-5 and np.quantile(e, 0.99) < 2e-5
+    assert not ((e > 1e-4) & ~tie).any() and e[~tie].max() < 1e-4
+    assert (H(it) == ito).mean() > 0.98
     # dense request gives the same answer
     Vdn = nat.DeviceMatrix(T(req.toarray().T))
     out2 = H(B.foldin(Vdn))
@@ -486,8 +540,9 @@ def test_foldin_matches_oracle(r):
                              np.zeros((300, r)), max_inner=100, eps=1e-3)
     out16 = H(B16.foldin(foldin_matrix(nat, req, m)))
     eb = np.linalg.norm(out16 - xb, axis=1) / np.maximum(np.linalg.norm(xb, axis=1), 1e-30)
-    print(f"foldin bf16 r={r}: x rel to the rounded-factor oracle median {np.median(eb):.2e}")
-    assert np.median(eb) < 1e-3
+    print(f"foldin bf16 r={r}: x rel to the rounded-factor oracle median {np.median(eb):.2e} "
+          f"p99 {np.quantile(eb, .99):.2e} max {eb.max():.2e}")
+    assert np.median(eb) < 1e-5 and np.quantile(eb, 0.99) < 1e-4
     B16.close()
 
 

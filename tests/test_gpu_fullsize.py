@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
+from near_ties import near_tied
 from paper_1506_08938_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -85,22 +86,33 @@ def one_iteration(full, opts):
 def check_half(G, P, l1, x0, xg, max_inner, eps, label, tight):
     """x is compared relative to the distance it moved (from the random start
     the solutions are small against x0, so |x| itself is no scale), f
-    relative to the decrease achieved."""
+    relative to the decrease achieved.  Fixed-K mode (tight): a column off by
+    more than 1e-4 must have a near-tied greedy choice in the oracle's path
+    (near_ties.py), the others are bounded at max and p99.  Adaptive mode: a
+    column whose stopping test falls on the other side of eps n_0 in float32
+    stops one iteration earlier or later and moves by O(sqrt(eps))."""
     h = -P + l1
-    xo, ito = oracle.nqp_batch(G, h, x0, max_inner=max_inner, eps=eps)
+    xo, ito, cd = oracle.nqp_batch_cdtrace(G, h, x0, max_inner=max_inner, eps=eps,
+                                           trace_iters=min(max_inner, 20))
     e = np.linalg.norm(xg - xo, axis=1) / np.maximum(np.linalg.norm(x0 - xo, axis=1), 1e-30)
     f0, fg, fo = f_col(G, h, x0), f_col(G, h, xg), f_col(G, h, xo)
     gap = np.abs(fg - fo) / np.maximum(np.abs(f0 - fo), 1e-30)
-    print(f"{label}: x error / distance moved median {np.median(e):.2e} p99 {np.quantile(e, .99):.2e}; "
-          f"f gap / decrease median {np.median(gap):.2e} p99 {np.quantile(gap, .99):.2e} max {gap.max():.2e}; "
-          f"oracle iterations mean {ito.mean():.2f}")
+    tie = near_tied(cd)
+    clean = ~tie
+    print(f"{label}: x error / distance moved median {np.median(e):.2e} p99 {np.quantile(e, .99):.2e} "
+          f"max {e.max():.2e}; f gap / decrease median {np.median(gap):.2e} p99 {np.quantile(gap, .99):.2e} "
+          f"max {gap.max():.2e}; oracle iterations mean {ito.mean():.2f}; near-tied {tie.mean():.3f}, "
+          f"without a near-tie x max {e[clean].max() if clean.any() else 0:.2e}")
+    # measured on MI355X (float32 and BF16 products): fixed K = 20, x p99
+    # 2.8e-5 .. 4.9e-5, max 6.5e-5, gap p99 <= 1.8e-11; adaptive, x p99
+    # 3.8e-5 .. 8.1e-5, max 1.2e-3 (an iteration-count flip), gap p99 3.5e-8
     if tight:
-        assert np.median(e) < 1e-3 and np.quantile(e, 0.99) < 1e-1
-        assert np.quantile(gap, 0.99) < 2e-5 and gap.max() < 5e-4
+        assert not ((e > 1e-4) & clean).any()
+        assert np.median(e) < 3e-5 and np.quantile(e, 0.99) < 1e-4 and e.max() < 2e-4
+        assert np.quantile(gap, 0.99) < 1e-10 and gap.max() < 1e-9
     else:
-        # a flipped iteration count moves a column by O(sqrt(eps))
-        assert np.median(e) < 1e-2
-        assert np.quantile(gap, 0.95) < 1e-2
+        assert np.median(e) < 3e-5 and np.quantile(e, 0.99) < 2e-4
+        assert np.quantile(gap, 0.99) < 1e-6 and gap.max() < 1e-5
     return ito
 
 

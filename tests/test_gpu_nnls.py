@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 
 import oracle
+from near_ties import near_tied
 from paper_1506_08938_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -75,6 +76,18 @@ def throughput_lanes(r):
     return 1 if r <= 32 else (2 if r <= 64 else 4)
 
 
+# Fixed K (few iterations, far from converged): a column whose oracle path
+# has a near-tied greedy choice (near_ties.py: a lead below 16 times the
+# float32 rounding of the two decreases) may go down another path on the GPU;
+# every other column must follow the oracle's.  Measured on MI355X (K = 1, 3;
+# r = 2 .. 128; both layouts): every column off by more than 1e-4 had such a
+# near-tie (the largest lead among them 6.1 units); the columns without one
+# are within 5.4e-5 on x and 4.0e-6 on the objective gap relative to the
+# decrease (4.7e-7 for r >= 10; at r = 2 some decreases are tiny); over all
+# columns that gap is at most 7.8e-6 at the 99th percentile and 7.1e-5 at
+# worst.  The share of columns with a near-tie grows with r and
+# K (at K = 3 and r >= 64 nearly every column has one), so there the
+# objective carries the comparison.
 @pytest.mark.parametrize("r", [2, 10, 32, 64, 100, 128])
 @pytest.mark.parametrize("K", [1, 3])
 @pytest.mark.parametrize("layout", ["auto", "throughput"])
@@ -83,18 +96,25 @@ def test_fixed_iterations_match_oracle(r, K, layout):
     G, h, x0 = make_batch(r, ncols, seed=1000 + r, l1=0.05)
     lanes = 0 if layout == "auto" else throughput_lanes(r)
     Xg, itg = gpu_solve(G, h, x0, max_inner=K, eps=0.0, lanes=lanes)
-    Xo, ito = oracle.nqp_batch(G, h, x0, max_inner=K, eps=0.0)
+    Xo, ito, cd = oracle.nqp_batch_cdtrace(G, h, x0, max_inner=K, eps=0.0)
     assert (itg <= K).all() and (np.mean(itg == K) > 0.9 or r <= 2)
     e = rel_err_rows(Xg, Xo)
     fg, fo = fvals(G, h, Xg), fvals(G, h, Xo)
     f0 = fvals(G, h, x0.astype(np.float64))
     # objective gap relative to the decrease achieved
     fr = np.abs(fg - fo) / np.maximum(np.abs(f0 - fo), 1e-30)
+    tie = near_tied(cd)
+    off = e > 1e-4
+    clean = ~tie
     print(f"r={r} K={K} x rel err: median {np.median(e):.2e} p99 {np.quantile(e, .99):.2e} "
-          f"max {e.max():.2e}; f gap/decrease max {fr.max():.2e} p99 {np.quantile(fr, .99):.2e}")
-    # a float32 near-tie can flip one greedy choice; the objective barely moves
-    assert np.median(e) < 2e-4
-    assert np.quantile(fr, 0.99) < 2e-5 and fr.max() < 5e-4
+          f"max {e.max():.2e}; f gap/decrease max {fr.max():.2e} p99 {np.quantile(fr, .99):.2e}; "
+          f"near-tied columns {tie.mean():.3f}, off by > 1e-4: {off.sum()}; without a near-tie: "
+          f"x max {e[clean].max() if clean.any() else 0:.2e}, f gap max "
+          f"{fr[clean].max() if clean.any() else 0:.2e}")
+    assert not (off & clean).any(), np.flatnonzero(off & clean)
+    if clean.any():
+        assert e[clean].max() < 1e-4 and fr[clean].max() < 1e-5
+    assert np.quantile(fr, 0.99) < 2e-5 and fr.max() < 2e-4
 
 
 # every compiled lanes-per-column layout against the oracle (converged mode)
@@ -234,17 +254,24 @@ def test_fast_break_matches_oracle(r, chunk):
     K, eps = 60, 1e-4
     Xg, itg = gpu_solve(G, h, x0, max_inner=K, eps=eps, fast_break_cols=chunk)
     Xo, ito, _ = oracle.nqp_batch_faststop(G, h, x0, chunk, max_inner=K, eps=eps)
-    _, ito_plain = oracle.nqp_batch(G, h, x0, max_inner=K, eps=eps)
+    # a fast-broken column's path is the plain solve's, cut short: its
+    # near-ties are those of the plain path's first ito iterations
+    _, ito_plain, cd = oracle.nqp_batch_cdtrace(G, h, x0, max_inner=K, eps=eps, trace_iters=int(ito.max()))
+    cd[np.arange(cd.shape[1])[None, :] >= ito[:, None]] = -2.0
+    tie = near_tied(cd)
     agree = (itg == ito).mean()
     e = rel_err_rows(Xg, Xo)
     print(f"r={r} chunk={chunk}: iterations agree on {agree:.4f}; mean k gpu {itg.mean():.3f} "
-          f"oracle {ito.mean():.3f} (no fast-break {ito_plain.mean():.3f}); x rel median {np.median(e):.2e}")
+          f"oracle {ito.mean():.3f} (no fast-break {ito_plain.mean():.3f}); x rel median {np.median(e):.2e} "
+          f"p99 {np.quantile(e, .99):.2e} max {e.max():.2e}; near-tied {tie.mean():.3f}, without x max "
+          f"{e[~tie].max() if (~tie).any() else 0:.2e}")
     assert ito.mean() <= ito_plain.mean()
     if r < 100:
         assert ito.mean() < ito_plain.mean()  # the fast-break does cut iterations here
     assert agree > 0.95
     assert abs(itg.mean() - ito.mean()) < 0.03 * ito.mean()
     assert np.median(e) < 1e-4
+    assert not ((e > 1e-4) & ~tie & (itg == ito)).any()
 
 
 def test_fast_break_off_and_one_column_runs_are_identical():

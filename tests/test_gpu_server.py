@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 import oracle
+from near_ties import near_tied
 from paper_1506_08938_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -77,10 +78,14 @@ def test_alone_equals_mix_equals_direct(basis):
     # and the fold-in matches the FP64 oracle (cold start, same stopping rule)
     G = oracle.gram(W, 0.0)
     P = oracle.product_csr(req, W, 1)
-    xo, _ = oracle.nqp_batch(G.astype(np.float32), (-P + np.float32(0.05)).astype(np.float32),
-                             np.zeros((300, r)), max_inner=100, eps=1e-3)
+    xo, ito, cd = oracle.nqp_batch_cdtrace(G.astype(np.float32), (-P + np.float32(0.05)).astype(np.float32),
+                                           np.zeros((300, r)), max_inner=100, eps=1e-3, trace_iters=10)
     e = np.linalg.norm(direct - xo, axis=1) / np.maximum(np.linalg.norm(xo, axis=1), 1e-30)
-    assert np.median(e) < 1e-3
+    tie = near_tied(cd) | (ito > 10)
+    print(f"served fold-in vs oracle: median {np.median(e):.2e} p99 {np.quantile(e, .99):.2e} "
+          f"max {e.max():.2e}; near-tied {tie.mean():.3f}")
+    assert np.median(e) < 1e-5 and np.quantile(e, 0.99) < 2e-5
+    assert not ((e > 1e-4) & ~tie).any()
 
 
 def test_bf16_basis_alone_equals_mix_equals_direct():
@@ -114,8 +119,9 @@ def test_bf16_basis_alone_equals_mix_equals_direct():
                              (-oracle.product_csr(req, Wb, 1) + np.float32(0.05)).astype(np.float32),
                              np.zeros((200, r)), max_inner=100, eps=1e-3)
     e = np.linalg.norm(direct - xo, axis=1) / np.maximum(np.linalg.norm(xo, axis=1), 1e-30)
-    print(f"bf16 basis fold-in vs rounded-W oracle: median {np.median(e):.2e}")
-    assert np.median(e) < 1e-3
+    print(f"bf16 basis fold-in vs rounded-W oracle: median {np.median(e):.2e} p99 {np.quantile(e, .99):.2e} "
+          f"max {e.max():.2e}")
+    assert np.median(e) < 1e-5 and np.quantile(e, 0.99) < 1e-4
     B.close()
 
 
