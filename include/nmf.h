@@ -128,12 +128,17 @@ typedef struct {
 
 /* Statistics of a fit.  loss = 0.5||V - W H||^2, objective = J above (both
  * accumulated in double precision), kkt_* = max |min(x, grad)| over the last
- * half-iteration's NQPs, kbar = inner iterations / (outer iterations x (m+n))
- * (Section 5.3). */
+ * half-iteration's NQPs (zero exactly at a KKT point of Eq. QP, Section 3.2),
+ * kbar = inner iterations / (outer iterations x (m+n)) (Section 5.3).
+ * kkt_*_cond: the three KKT conditions of the same NQPs separately, each 0
+ * when it holds: [0] max(0, -min x) (nonnegativity), [1] max x_i |grad_i|
+ * (complementarity), [2] max(0, -min grad_i over x_i = 0) (gradient >= 0 on
+ * the zero entries).  grad = Gamma x + h in the original scale, in double. */
 typedef struct {
     double loss, objective, kkt_w, kkt_h, kbar;
     int64_t inner_total;
     int32_t outer_done;
+    double kkt_w_cond[3], kkt_h_cond[3];
 } nmf_stats;
 
 /* Fills *o with the defaults: max_outer 50, max_inner 100, eps 1e-3,

@@ -300,6 +300,7 @@ extern "C" int nmf_fit_batched(int32_t count, const nmf_problem *probs, const nm
             o.objective = obj;
             o.kkt_w = NAN;
             o.kkt_h = NAN;
+            for (int q = 0; q < 3; q++) o.kkt_w_cond[q] = o.kkt_h_cond[q] = NAN;
             o.inner_total = (int64_t)inner;
             o.outer_done = opt->max_outer;
             o.kbar = opt->max_outer > 0

@@ -394,8 +394,8 @@ extern "C" int nmf_plan_create(const nmf_matrix *V, int32_t r, const nmf_reg *re
         const size_t o_gs = place(gram_scratch_bytes(r, cmax));
         const size_t o_P = place((size_t)cmax * r * sizeof(float));
         const size_t o_oo = place(4 * sizeof(double));
-        const size_t o_ko = place(4 * sizeof(double));
-        const size_t o_kp = place((size_t)cmax * sizeof(double));
+        const size_t o_ko = place(8 * sizeof(double));
+        const size_t o_kp = place(kkt_partial_bytes(cmax));
         const size_t o_os = place(objective_scratch_bytes(V, r));
         hipError_t e = hipMalloc((void **)&p->ws, off);
         if (e != hipSuccess) {
@@ -582,15 +582,14 @@ extern "C" int nmf_plan_run(nmf_plan *p, float *W, float *Ht, int32_t outer, dou
         if (int st = objective_now(p, W, Ht, ob, s)) return st;
         trace[0] = ob[0];
     }
-    double kkt_h = NAN, kkt_w = NAN;
     for (int t = 0; t < outer; t++) {
         const bool last = t == outer - 1;
         hipError_t e = half_update(p, true, W, Ht, s);
         if (e == hipSuccess && stats && last)
-            e = launch_kkt(p->G, p->r, p->P, -1.f, p->reg.l1_h, Ht, p->n, p->kkt_partial, p->kkt_out, s);
+            e = launch_kkt(p->G, p->r, p->P, -1.f, p->reg.l1_h, Ht, p->n, p->kkt_partial, p->kkt_out, 1, s);
         if (e == hipSuccess) e = half_update(p, false, Ht, W, s);
         if (e == hipSuccess && stats && last)
-            e = launch_kkt(p->G, p->r, p->P, -1.f, p->reg.l1_w, W, p->m, p->kkt_partial, p->kkt_out + 1, s);
+            e = launch_kkt(p->G, p->r, p->P, -1.f, p->reg.l1_w, W, p->m, p->kkt_partial, p->kkt_out + 4, 1, s);
         if (e != hipSuccess) return hip_fail(e, "outer iteration");
         if (trace && ((t + 1) % every == 0 || last)) {
             if (int st = objective_now(p, W, Ht, ob, s)) return st;
@@ -603,15 +602,14 @@ extern "C" int nmf_plan_run(nmf_plan *p, float *W, float *Ht, int32_t outer, dou
             if (int st = objective_now(p, W, Ht, ob, s)) return st;
         }
         unsigned long long inner = 0;
-        double kk[2] = {NAN, NAN};
+        double kk[8];
+        for (double &v : kk) v = NAN;
         NMF_HIP(hipMemcpyAsync(&inner, p->inner_total, sizeof inner, hipMemcpyDeviceToHost, s));
-        if (outer > 0) NMF_HIP(hipMemcpyAsync(kk, p->kkt_out, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        if (outer > 0) NMF_HIP(hipMemcpyAsync(kk, p->kkt_out, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
         NMF_HIP(hipStreamSynchronize(s));
-        kkt_h = kk[0]; kkt_w = kk[1];
         stats->loss = ob[0];
         stats->objective = ob[1];
-        stats->kkt_h = kkt_h;
-        stats->kkt_w = kkt_w;
+        set_kkt_stats(stats, kk, kk + 4);
         stats->inner_total = (int64_t)inner;
         stats->outer_done = outer;
         stats->kbar = outer > 0 ? (double)inner / ((double)outer * (double)(p->m + p->n)) : 0.0;

@@ -378,7 +378,11 @@ __global__ void k_finish(const double *__restrict__ t, int csr, double l1w, doub
 // over the coordinate a.  Gamma sits in LDS (float, transposed so that a wave
 // reads a row of it without bank conflicts) and each entry read serves the
 // group's rows; x_j reaches every lane through lane reads.  g = Gamma x_j +
-// hsign P_j + hadd in double; one max of |min(x_a, g_a)| per block.
+// hsign P_j + hadd in double.  Per block four maxima (the optimality
+// conditions of Eq. QP, Section 3.2): |min(x_a, g_a)| (zero exactly at a KKT
+// point), max(0, -x_a) (nonnegativity), x_a |g_a| (complementarity) and
+// max(0, -g_a) over x_a = 0 (gradient >= 0 on the zero entries); partial[q *
+// gridDim.x + block] for q = 0..3.
 constexpr int KKT_GRID = 2048;
 constexpr int KKT_ROWS = 4;
 
@@ -387,7 +391,7 @@ __global__ __launch_bounds__(256) void k_kkt(const float *__restrict__ G, int r,
                                              const float *__restrict__ X, int64_t c,
                                              double *__restrict__ partial) {
     extern __shared__ float gt[];  // gt[b * r + a] = Gamma[a][b]
-    __shared__ double red[4];
+    __shared__ double red[16];
     for (int e = threadIdx.x; e < r * r; e += 256) {
         const int a = e / r, b = e - a * r;
         gt[b * r + a] = G[e];
@@ -399,7 +403,7 @@ __global__ __launch_bounds__(256) void k_kkt(const float *__restrict__ G, int r,
     // lane has no coordinate)
     const int c0 = has0 ? lane : r - 1, c1 = has1 ? lane + 64 : r - 1;
     const int r0 = r < 64 ? r : 64;
-    double mx = 0.0;
+    double mx = 0.0, mneg = 0.0, mcompl = 0.0, mgrad = 0.0;
     const int64_t step = (int64_t)gridDim.x * 4 * KKT_ROWS;
     for (int64_t j0 = ((int64_t)blockIdx.x * 4 + wave) * KKT_ROWS; j0 < c; j0 += step) {
         float x0[KKT_ROWS], x1[KKT_ROWS];
@@ -439,29 +443,37 @@ __global__ __launch_bounds__(256) void k_kkt(const float *__restrict__ G, int r,
                 g1[k] = fma(gb, xb, g1[k]);
             }
         }
+        auto account = [&](double x, double g) {
+            const double v = fabs(x < g ? x : g);
+            mx = v > mx ? v : mx;
+            mneg = -x > mneg ? -x : mneg;
+            const double cv = x * fabs(g);
+            mcompl = cv > mcompl ? cv : mcompl;
+            if (x == 0.0 && -g > mgrad) mgrad = -g;
+        };
 #pragma unroll
         for (int k = 0; k < KKT_ROWS; k++) {
             if (j0 + k >= c) break;
-            if (has0) {
-                const double x = x0[k], v = fabs(x < g0[k] ? x : g0[k]);
-                mx = v > mx ? v : mx;
-            }
-            if (has1) {
-                const double x = x1[k], v = fabs(x < g1[k] ? x : g1[k]);
-                mx = v > mx ? v : mx;
-            }
+            if (has0) account(x0[k], g0[k]);
+            if (has1) account(x1[k], g1[k]);
         }
     }
-    for (int off = 32; off >= 1; off >>= 1) {
-        const double o = __shfl_xor(mx, off);
-        mx = o > mx ? o : mx;
+    double vals[4] = {mx, mneg, mcompl, mgrad};
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        double v = vals[q];
+        for (int off = 32; off >= 1; off >>= 1) {
+            const double o = __shfl_xor(v, off);
+            v = o > v ? o : v;
+        }
+        if (lane == 0) red[q * 4 + wave] = v;
     }
-    if (lane == 0) red[wave] = mx;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double v = red[0];
-        for (int w = 1; w < 4; w++) v = red[w] > v ? red[w] : v;
-        partial[blockIdx.x] = v;
+    if (threadIdx.x < 4) {
+        const int q = threadIdx.x;
+        double v = red[q * 4];
+        for (int w = 1; w < 4; w++) v = red[q * 4 + w] > v ? red[q * 4 + w] : v;
+        partial[(size_t)q * gridDim.x + blockIdx.x] = v;
     }
 }
 
@@ -650,16 +662,25 @@ hipError_t launch_max_ordered(const double *in, int64_t n, double *out, hipStrea
     return hipGetLastError();
 }
 
-// KKT residual of one half into *dev_out; partial needs min(ceil(c / 16),
-// KKT_GRID) doubles (c always suffice).
+static int64_t kkt_blocks(int64_t c) {
+    const int64_t nb = (c + 4 * KKT_ROWS - 1) / (4 * KKT_ROWS);
+    return nb > KKT_GRID ? KKT_GRID : nb;
+}
+
+size_t kkt_partial_bytes(int64_t c) { return (size_t)(4 * (c > 0 ? kkt_blocks(c) : 1)) * sizeof(double); }
+
+// The four KKT residuals of one half (minmap, nonnegativity, complementarity,
+// gradient on zero entries) into dev_out[0], dev_out[stride], dev_out[2 *
+// stride], dev_out[3 * stride]; partial holds kkt_partial_bytes(c).
 hipError_t launch_kkt(const float *G, int r, const float *P, float hsign, float hadd,
-                      const float *X, int64_t c, double *partial, double *dev_out, hipStream_t s) {
+                      const float *X, int64_t c, double *partial, double *dev_out, int64_t stride,
+                      hipStream_t s) {
     if (c <= 0) return hipSuccess;
-    int64_t nb = (c + 4 * KKT_ROWS - 1) / (4 * KKT_ROWS);
-    if (nb > KKT_GRID) nb = KKT_GRID;
+    const int64_t nb = kkt_blocks(c);
     hipLaunchKernelGGL(k_kkt, dim3((unsigned)nb), dim3(256), (size_t)r * r * sizeof(float), s, G, r, P,
                        hsign, hadd, X, c, partial);
-    hipLaunchKernelGGL(k_max_ordered, dim3(1), dim3(256), 0, s, partial, nb, dev_out);
+    for (int q = 0; q < 4; q++)
+        hipLaunchKernelGGL(k_max_ordered, dim3(1), dim3(256), 0, s, partial + q * nb, nb, dev_out + q * stride);
     return hipGetLastError();
 }
 

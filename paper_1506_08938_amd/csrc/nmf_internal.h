@@ -192,8 +192,21 @@ hipError_t launch_zero_u32(unsigned int *p, int n, hipStream_t s);
 size_t objective_scratch_bytes(const nmf_matrix *V, int r);
 hipError_t launch_objective(const nmf_matrix *V, int r, const nmf_reg *reg, const float *W,
                             const float *Ht, char *scratch, double *dev_out, hipStream_t s);
+size_t kkt_partial_bytes(int64_t c);
+// Fills the KKT fields of *st from the four residuals of each half (h: the
+// H-update's, w: the W-update's; minmap, nonnegativity, complementarity,
+// gradient on zero entries).
+inline void set_kkt_stats(nmf_stats *st, const double *h, const double *w) {
+    st->kkt_h = h[0];
+    st->kkt_w = w[0];
+    for (int q = 0; q < 3; q++) {
+        st->kkt_h_cond[q] = h[q + 1];
+        st->kkt_w_cond[q] = w[q + 1];
+    }
+}
 hipError_t launch_kkt(const float *G, int r, const float *P, float hsign, float hadd,
-                      const float *X, int64_t c, double *partial, double *dev_out, hipStream_t s);
+                      const float *X, int64_t c, double *partial, double *dev_out, int64_t stride,
+                      hipStream_t s);
 // V seen one panel at a time: a panel's sum of squared errors (rows x cols
 // block of V at V with leading dimension ld, against W's rows and Ht's rows
 // of the panel) into *slot; scratch of loss_panel_scratch_bytes(rows, cols)

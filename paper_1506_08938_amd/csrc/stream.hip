@@ -161,9 +161,9 @@ extern "C" int nmf_fit_streamed(const float *V_host, int64_t m, int64_t n, int64
     const size_t o_pj = place((size_t)S.pc * r * 4);
     const size_t o_ds = place(dsb);
     const size_t o_ls = place(loss_panel_scratch_bytes(m, S.pc));
-    const size_t o_lsl = place((size_t)S.np * 8), o_ksl = place((size_t)S.np * 8);
-    const size_t o_kp = place((size_t)2048 * 8);
-    const size_t o_obj = place((size_t)(T + 1) * 2 * 8), o_ko = place(2 * 8);
+    const size_t o_lsl = place((size_t)S.np * 8), o_ksl = place((size_t)S.np * 4 * 8);
+    const size_t o_kp = place(kkt_partial_bytes(std::max(m, S.pc)));
+    const size_t o_obj = place((size_t)(T + 1) * 2 * 8), o_ko = place(8 * 8);
     const size_t o_os = place(objective_slots_scratch_bytes());
     const size_t o_ctr = place(2 * 8);
     NMF_HIP(hipMalloc((void **)&S.ws, off));
@@ -216,7 +216,8 @@ extern "C" int nmf_fit_streamed(const float *V_host, int64_t m, int64_t n, int64
             NMF_HIP(launch_dense_product(VJ, 0, m, cols, S.ldp, nullptr, 0, W, r, S.PJ, S.dense_scratch, S.s));
             NMF_HIP(S.solve(S.GW, S.PJ, reg->l1_h, HJ, cols, true));
             if (stats && last)
-                NMF_HIP(launch_kkt(S.GW, r, S.PJ, -1.f, reg->l1_h, HJ, cols, S.kkt_partial, S.kkt_slots + p, S.s));
+                NMF_HIP(launch_kkt(S.GW, r, S.PJ, -1.f, reg->l1_h, HJ, cols, S.kkt_partial, S.kkt_slots + p,
+                                   S.np, S.s));
             // the M-step's product: P_W += V_J Ht_J
             NMF_HIP(launch_dense_product(VJ, 0, m, cols, S.ldp, nullptr, 1, HJ, r, S.Ptmp, S.dense_scratch, S.s));
             hipLaunchKernelGGL(k_add_f32, dim3(grid_for(m * r)), dim3(256), 0, S.s, S.PW, S.Ptmp, m * r);
@@ -226,12 +227,14 @@ extern "C" int nmf_fit_streamed(const float *V_host, int64_t m, int64_t n, int64
         if (st) return st;
         if (obj_prev)
             NMF_HIP(launch_objective_slots(S.loss_slots, S.np, reg, S.obj_scratch, S.obj + 2 * (t - 1), S.s));
-        if (stats && last) NMF_HIP(launch_max_ordered(S.kkt_slots, S.np, S.kkt_out, S.s));
+        if (stats && last)
+            for (int q = 0; q < 4; q++)
+                NMF_HIP(launch_max_ordered(S.kkt_slots + q * S.np, S.np, S.kkt_out + q, S.s));
         // M-step (no V): Gram of the new H, then every row of W
         NMF_HIP(launch_gram(Ht, n, r, reg->l2_w, NMF_FP32, S.GH, S.gram_scratch, S.s, S.counter));
         NMF_HIP(S.solve(S.GH, S.PW, reg->l1_w, W, m, false));
         if (stats && last)
-            NMF_HIP(launch_kkt(S.GH, r, S.PW, -1.f, reg->l1_w, W, m, S.kkt_partial, S.kkt_out + 1, S.s));
+            NMF_HIP(launch_kkt(S.GH, r, S.PW, -1.f, reg->l1_w, W, m, S.kkt_partial, S.kkt_out + 4, 1, S.s));
     }
     // the objective after the last iteration (or of the start point when T = 0)
     if (want_obj && due(T)) {
@@ -246,10 +249,11 @@ extern "C" int nmf_fit_streamed(const float *V_host, int64_t m, int64_t n, int64
 
     // ---------------------------------------------------------------- host outputs
     std::vector<double> ob((size_t)(T + 1) * 2, 0.0);
-    double kk[2] = {NAN, NAN};
+    double kk[8];
+    for (double &v : kk) v = NAN;
     unsigned long long inner = 0;
     if (want_obj) NMF_HIP(hipMemcpyAsync(ob.data(), S.obj, ob.size() * 8, hipMemcpyDeviceToHost, S.s));
-    if (stats && T > 0) NMF_HIP(hipMemcpyAsync(kk, S.kkt_out, 2 * 8, hipMemcpyDeviceToHost, S.s));
+    if (stats && T > 0) NMF_HIP(hipMemcpyAsync(kk, S.kkt_out, 8 * 8, hipMemcpyDeviceToHost, S.s));
     NMF_HIP(hipMemcpyAsync(&inner, S.inner_total, 8, hipMemcpyDeviceToHost, S.s));
     NMF_HIP(hipStreamSynchronize(S.s));
     if (trace)
@@ -257,8 +261,7 @@ extern "C" int nmf_fit_streamed(const float *V_host, int64_t m, int64_t n, int64
     if (stats) {
         stats->loss = ob[2 * T];
         stats->objective = ob[2 * T + 1];
-        stats->kkt_h = kk[0];
-        stats->kkt_w = kk[1];
+        set_kkt_stats(stats, kk, kk + 4);
         stats->inner_total = (int64_t)inner;
         stats->outer_done = T;
         stats->kbar = T > 0 ? (double)inner / ((double)T * (double)(m + n)) : 0.0;

@@ -55,10 +55,14 @@ class NmfOpts(ctypes.Structure):
 class NmfStats(ctypes.Structure):
     _fields_ = [("loss", ctypes.c_double), ("objective", ctypes.c_double),
                 ("kkt_w", ctypes.c_double), ("kkt_h", ctypes.c_double), ("kbar", ctypes.c_double),
-                ("inner_total", ctypes.c_int64), ("outer_done", ctypes.c_int32)]
+                ("inner_total", ctypes.c_int64), ("outer_done", ctypes.c_int32),
+                ("kkt_w_cond", ctypes.c_double * 3), ("kkt_h_cond", ctypes.c_double * 3)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        for k in ("kkt_w_cond", "kkt_h_cond"):
+            d[k] = tuple(d[k])
+        return d
 
 
 class NmfProblem(ctypes.Structure):

@@ -119,6 +119,13 @@ def test_streamed_trace_stats_and_zero_iterations():
     assert st["loss"] == pytest.approx(oracle.loss(V, Wg, Hg), rel=1e-12)
     assert st["objective"] == pytest.approx(oracle.objective(V, Wg, Hg, reg), rel=1e-12)
     assert st["kkt_h"] >= 0 and st["kkt_w"] >= 0 and st["outer_done"] == 6
+    # the three KKT conditions of the last half-iterations (the E-step's
+    # gathered over the panels): the solve never leaves x >= 0, and on a zero
+    # entry |min(x, g)| = max(0, -g), so the min-map residual bounds the third
+    for k, mm in (("kkt_h_cond", "kkt_h"), ("kkt_w_cond", "kkt_w")):
+        c = st[k]
+        assert c[0] == 0.0 and c[1] >= 0.0 and c[2] >= 0.0 and np.isfinite(c).all()
+        assert st[mm] >= c[2]
     assert st["kbar"] >= 1.0 and st["inner_total"] >= 6 * 350
     # no iterations: the start point's objective, factors untouched
     W0, Ht0 = wl["W0"], wl["Ht0"]
