@@ -27,6 +27,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+
 #include "nmf_internal.h"
 
 namespace nmfi {
@@ -683,16 +685,20 @@ __attribute__((amdgpu_waves_per_eu(nqp_waves_per_eu<E, L>(), 8))) void k_bnqp(
     }
 }
 
-// Blocks of one kernel per CU at the given block size (cached per size).
+// Blocks of one kernel per CU at the given block size (cached per size; the
+// cache is shared by every host thread that launches the kernel, and each one
+// that finds it empty stores the same value).
 template <class K>
-int nqp_blocks_per_cu(K kernel, int block, int (&cache)[2]) {
-    int &c = cache[block == NQP_BLOCK_SMALL ? 0 : 1];
-    if (c < 0) {
+int nqp_blocks_per_cu(K kernel, int block, std::atomic<int> (&cache)[2]) {
+    std::atomic<int> &c = cache[block == NQP_BLOCK_SMALL ? 0 : 1];
+    int v = c.load(std::memory_order_relaxed);
+    if (v < 0) {
         int nb = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, block, 0) != hipSuccess || nb < 1) nb = 1;
-        c = nb;
+        c.store(nb, std::memory_order_relaxed);
+        v = nb;
     }
-    return c;
+    return v;
 }
 
 template <int E, int L>
@@ -700,7 +706,7 @@ hipError_t launch_bnqp_t(const BSolveChunk *chunks, int nchunks, unsigned int *q
                          const BSolveProb *probs, int max_inner, double eps, int ls_guard, int unit,
                          hipStream_t s) {
     if (nchunks <= 0) return hipSuccess;
-    static int cache[2] = {-1, -1};
+    static std::atomic<int> cache[2] = {{-1}, {-1}};
     // small launches spread four-wave blocks over more CUs
     const int block = nchunks >= 2 * device_cu_count() ? nqp_block<E, L>() : NQP_BLOCK_SMALL;
     const int64_t cap = (int64_t)nqp_blocks_per_cu(k_bnqp<E, L>, block, cache) * device_cu_count();
@@ -713,7 +719,7 @@ hipError_t launch_bnqp_t(const BSolveChunk *chunks, int nchunks, unsigned int *q
 template <int E, int L>
 hipError_t launch_nqp_t(const NqpParams &p, hipStream_t s) {
     if (p.ncols <= 0) return hipSuccess;
-    static int cache[2] = {-1, -1};
+    static std::atomic<int> cache[2] = {{-1}, {-1}};
     // a launch that cannot give every CU two large blocks uses four-wave blocks
     const int big = nqp_block<E, L>();
     const int64_t big_cols = (int64_t)2 * device_cu_count() * (big / 64) * (64 / L);
