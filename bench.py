@@ -9,24 +9,31 @@ library's HIP kernels, with inputs resident in HBM.
 
 value = column NNLS solves per second = (m + n) x steps / elapsed.  The
 roofline entry is for the dominant kernel (the NQP solve), timed with HIP
-events recorded on its stream during the timed steps; its algorithmic work
-is counted per solved column as  init(r) = r^2 + 5r  plus, per inner
-iteration,  iter(r) = 7r^2 + 13r  lane operations, against
-the VALU issue rate of 256 CUs x 64 lanes x 2.4 GHz.  The CPU baseline is
-the FP64 oracle timed on the host cores for one outer iteration of the same
-workload from the same start point (its first --cpu-iters outer
-iterations).
+events attached to its own dispatches during the timed steps; its
+algorithmic work is counted per solved column as  r^2  (the warm start)
+plus, per inner iteration,  11 r^2 + 11 r  lane operations (the line search
+about 2 r^2, the r greedy CD steps about 9 r^2), against the VALU issue rate
+of 256 CUs x 64 lanes x 2.4 GHz; the exact count of the operations the
+method performs (r^2 + 5r, then 7 r^2 + 13 r per iteration) is reported
+beside it.  The product_roofline entry is for the product phase (row
+gathers of the CSR products), algorithmic bytes per step over its time from
+a separate run with events around every phase, against 8 TB/s.  The CPU
+baseline is the FP64 oracle timed on the host cores for the first
+--cpu-iters outer iterations of the same workload from the same start point.
 
 The "serving" entry covers the fold-in side of the metric: a basis W
 (100000 x 128) fitted on the device to Gamma-factor data stays resident;
 fold-in requests of c ~ logU[1, 8192] sparse columns (0.5% density) and 5%
 small full fits go through nmf_server_*.  First every request is submitted at
 once (saturated: fold-in columns solved per second), then the same mix
-arrives as a Poisson stream at --serve-load times the saturated request rate
-and the per-request latencies (submission to completion) give p50/p99.
+arrives as a Poisson stream at each of --serve-loads times the saturated
+request rate, --serve-requests measured after --serve-warmup warm-up
+requests, and the per-request latencies (submission to completion) give
+p50/p99.  "foldin_solve" is the fold-in's solve kernel alone on 8192 request
+columns: its kbar and lane operations per second against the VALU peak.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--cpu-iters T]
-                       [--no-serve] [--serve-requests N] [--serve-load F]
+                       [--no-serve] [--serve-requests N] [--serve-warmup N] [--serve-loads a,b,c]
        python bench.py --calibrate-copy   (1 GiB device copy, for counter scaling)
 """
 import argparse
@@ -43,11 +50,30 @@ METRIC = "column NNLS solves/s at r=100 vs roofline; p50/p99 fold-in latency at 
 
 
 def init_ops(r):
+    """Lane operations of Algorithm 3's start per column, counted exactly:
+    q = h / sqrt(d), y = x0 sqrt(d), g = Q y + q and ||pg_0||^2."""
     return r * r + 5 * r
 
 
 def iter_ops(r):
+    """Lane operations of one iteration of Algorithm 3 per column, counted
+    exactly: the projected gradient and its norm 2r, Q pg r^2, pg'Q pg r,
+    the projected step 3r, Q delta r^2, the guard 2r, the y and g updates
+    2r, r CD steps of 5r + 1 each, the stop test 2r."""
     return 7 * r * r + 13 * r
+
+
+def init_ops_agreed(r):
+    """The same start in the scope's count of algorithmic work: r^2 (the warm
+    start's Q y)."""
+    return r * r
+
+
+def iter_ops_agreed(r):
+    """One iteration in the scope's count: 11 r^2 + 11 r (the line search about
+    2 r^2, the r CD steps about 9 r^2: every coordinate's step, decrease and
+    comparison plus the gradient update, each weighted as in that count)."""
+    return 11 * r * r + 11 * r
 
 
 def log(msg):
@@ -83,7 +109,40 @@ def measured_traffic(kernel, L):
     return float(fields["traffic_bytes_per_launch"])
 
 
-def serving_leg(native, synth, torch, n_req, loads=(0.5,), seed=5005, n_warm=None, batch_cols=16384):
+def foldin_solve_roofline(native, synth, torch, W, m, r, seed, ncols=8192):
+    """The fold-in's solve kernel alone (Algorithm 3 from x0 = 0 against the resident basis'
+    Gram), on the configured request columns: kbar, and lane operations per second against the
+    VALU peak, timed with HIP events on the stream the kernel runs on."""
+    import numpy as np
+    l1 = 0.05
+    G = native.gram(W, 0.0)
+    req = synth.foldin_columns_many(m, ncols, 500, seed)
+    P = native.product(native.sparse_request(req, m), W, 0)   # (c x r) = (W' Vnew)'
+    h = (l1 - P).contiguous()
+    it = torch.zeros(ncols, dtype=torch.int32, device="cuda")
+    opt = native.opts(max_inner=100, eps=1e-3)
+    X = torch.zeros((ncols, r), device="cuda")
+    native.nnls_solve_batch(G, h, X, opt, it)  # warm
+    times = []
+    for _ in range(5):
+        X.zero_()
+        a = torch.cuda.Event(enable_timing=True); b = torch.cuda.Event(enable_timing=True)
+        a.record(); native.nnls_solve_batch(G, h, X, opt, it); b.record(); b.synchronize()
+        times.append(a.elapsed_time(b))
+    ms = float(np.median(times))
+    inner = int(it.sum().item())
+    # cold start: g = q, no Q y (the agreed count's r^2 start term is the warm start's)
+    ops = inner * iter_ops_agreed(r)
+    E, L = native.layout(r, ncols)
+    return {"kernel": f"k_nqp<{E}, {L}> (Algorithm 3 from x0 = 0)", "columns": ncols, "r": r,
+            "kbar": inner / ncols, "ms": ms, "solves_per_s": ncols / (ms / 1e3),
+            "achieved": ops / (ms / 1e3), "peak": PEAK_LANE_OPS, "unit": "lane-ops/s",
+            "frac": ops / (ms / 1e3) / PEAK_LANE_OPS,
+            "ops_count": "per column k (11 r^2 + 11 r), k its inner iterations"}
+
+
+def serving_leg(native, synth, torch, n_req, loads=(0.5,), seed=5005, n_warm=None, batch_cols=16384,
+                foldin_solve=False):
     """Saturated throughput and Poisson-arrival latency of nmf_server_* at each offered load
     (a fraction of the saturated request rate)."""
     import numpy as np
@@ -95,9 +154,10 @@ def serving_leg(native, synth, torch, n_req, loads=(0.5,), seed=5005, n_warm=Non
     Vb = native.DeviceMatrix(torch.from_numpy(wb["V"]).cuda())
     W = torch.from_numpy(wb["W0"]).cuda()
     Ht = torch.from_numpy(wb["Ht0"]).cuda()
-    native.fit(Vb, r, native.reg(), native.opts(max_outer=10), W, Ht, want_trace=False)
+    native.fit(Vb, r, native.reg(), native.opts(max_outer=20), W, Ht, want_trace=False)
     del Vb, Ht
     basis = native.Basis(W, l1=0.05, l2=0.0, opt=native.opts(max_inner=100, eps=1e-3))
+    fsolve = foldin_solve_roofline(native, synth, torch, W, m, r, seed + 4242) if foldin_solve else None
     # a pool of distinct requests, reused by the arrivals (each arrival has its own output)
     n_pool = 96
     sizes = synth.request_sizes(n_pool, seed, cmax=8192)
@@ -186,8 +246,8 @@ def serving_leg(native, synth, torch, n_req, loads=(0.5,), seed=5005, n_warm=Non
             f"p99 {per_load[-1]['fold_in_p99_ms']:.3f} ms")
     basis.close()
     res = {
-        "workload": "resident basis W 100000x128 (10 outer iterations fitted on the device to "
-                    "Gamma(2,0.5)-factor data), L1=0.05, eps=1e-3; fold-in requests of "
+        "workload": "resident basis W 100000x128 (20 outer iterations fitted on the device to "
+                    "2048 columns of Gamma(2,0.5)-factor data), L1=0.05, eps=1e-3; fold-in requests of "
                     "c~logU[1,8192] columns at 0.5% density, values log(1+Poisson(3)); 5% small "
                     "full fits (m,n~logU[64,2048], r~U{4..32}, 30 outer iterations); 4 slots, "
                     f"batches of up to {batch_cols} columns",
@@ -199,6 +259,8 @@ def serving_leg(native, synth, torch, n_req, loads=(0.5,), seed=5005, n_warm=Non
         "saturated_batches": st_sat["batches"],
         "loads": per_load,
     }
+    if fsolve is not None:
+        res["foldin_solve"] = fsolve
     if len(per_load) == 1:  # the headline line's short form
         res.update({k: per_load[0][k] for k in ("fold_in_p50_ms", "fold_in_p99_ms", "fit_p50_ms")})
         res["load"] = per_load[0]["load"]
@@ -462,7 +524,8 @@ def bench_streamed(args, native, synth, torch, np):
 def bench_serving(args, native, synth, torch, np):
     """The serving configuration at several offered loads."""
     loads = (0.3, 0.6, 0.9)
-    res = serving_leg(native, synth, torch, args.serve_requests, loads, n_warm=1000, batch_cols=args.serve_batch_cols)
+    res = serving_leg(native, synth, torch, args.serve_requests, loads, n_warm=args.serve_warmup,
+                      batch_cols=args.serve_batch_cols, foldin_solve=True)
     out = base_line(
         "fold-in serving: column NNLS solves/s and p50/p99 latency at offered loads",
         res["saturated_solves_per_s"], "column NNLS solves/s", args.serve_requests, 0,
@@ -479,11 +542,13 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=8,
                     help="outer iterations of the CPU-oracle sample")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
-    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-requests", type=int, default=20000,
+                    help="measured requests per offered load")
+    ap.add_argument("--serve-warmup", type=int, default=1000, help="warm-up requests before each measurement")
+    ap.add_argument("--serve-loads", default="0.3,0.6,0.9",
+                    help="offered loads, as fractions of the saturated request rate")
     ap.add_argument("--serve-batch-cols", type=int, default=16384,
                     help="largest fold-in batch (columns) the server forms")
-    ap.add_argument("--serve-load", type=float, default=0.5,
-                    help="Poisson arrival rate as a fraction of the saturated request rate")
     ap.add_argument("--workload", default="sparse", choices=["sparse", "dense", "batched", "serving", "streamed"],
                     help="sparse: the headline line (default); the others print supplementary lines")
     ap.add_argument("--lanes", type=int, default=0,
@@ -583,10 +648,18 @@ def main():
     value = solves / elapsed
     solve_ms, solve_calls = timers["solve"]
     inner_total = st["inner_total"]
-    ops = solves * init_ops(r) + inner_total * iter_ops(r)
+    ops = solves * init_ops_agreed(r) + inner_total * iter_ops_agreed(r)
+    ops_exact = solves * init_ops(r) + inner_total * iter_ops(r)
     avg_launch_s = solve_ms / 1e3 / solve_calls
     achieved = ops / solve_calls / avg_launch_s
     kbar = st["kbar"]
+    # the product phase (the row gathers k_spmm with its split-row fixup, and
+    # the H-update's hot columns on k_dense), from the separate run with
+    # events around every phase; algorithmic bytes of a CSR product:
+    # 8 nnz + 4 (rows + 1) + 4 k r (the fixed factor once) + 4 c r (the output)
+    nnz = int(V.nnz)
+    prod_bytes = (8 * nnz + 4 * (n + 1) + 4 * m * r + 4 * n * r) + (8 * nnz + 4 * (m + 1) + 4 * n * r + 4 * m * r)
+    prod_s = phases["product"] / 1e3  # both halves' product phases of one step
 
     out = {
         "metric": METRIC,
@@ -621,6 +694,21 @@ def main():
             "traffic": traffic,
             "avg_launch_ms": solve_ms / solve_calls,
             "ops_per_launch": ops / solve_calls,
+            "ops_count": "per column r^2 + k (11 r^2 + 11 r), k its inner iterations",
+            "ops_per_launch_exact_count": ops_exact / solve_calls,
+            "frac_exact_count": ops_exact / solve_calls / avg_launch_s / PEAK_LANE_OPS,
+        },
+        "product_roofline": {
+            "bound": "hbm",
+            "kernel": "product phase: k_spmm row gathers + split-row fixup (+ hot columns on k_dense in the "
+                      "H-update), both halves",
+            "achieved": prod_bytes / prod_s,
+            "peak": 8e12,
+            "unit": "B/s",
+            "frac": prod_bytes / prod_s / 8e12,
+            "traffic": None,
+            "algorithmic_bytes_per_step": prod_bytes,
+            "ms_per_step": prod_s * 1e3,
         },
         "kbar": kbar,
         "phases_ms_per_step": phases,
@@ -640,8 +728,10 @@ def main():
         }
         log(f"[bench] BF16 products: {el16 * 1e3 / K:.3f} ms/step")
     if not args.no_serve:
-        out["serving"] = serving_leg(native, synth, torch, args.serve_requests, (args.serve_load,),
-                                     batch_cols=args.serve_batch_cols)
+        loads = tuple(float(x) for x in args.serve_loads.split(","))
+        res = serving_leg(native, synth, torch, args.serve_requests, loads, n_warm=args.serve_warmup,
+                          batch_cols=args.serve_batch_cols, foldin_solve=True)
+        out["serving"] = res
 
     if not args.no_cpu:
         import oracle

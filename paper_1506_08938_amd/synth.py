@@ -215,7 +215,7 @@ def foldin_columns_many(m, c, per_col, seed):
     return sp.csr_matrix((vals, cols, indptr), shape=(c, m))
 
 
-def workload5_basis(m=100000, nb=1024, r=128):
+def workload5_basis(m=100000, nb=2048, r=128):
     """Data and start point of the prior fit that yields the resident basis:
     V (m x nb) = W0 H0 + |N(0, 0.05)|, Gamma(2, 0.5) factors of inner
     dimension r."""
