@@ -295,6 +295,22 @@ NMF_API int nmf_foldin(const nmf_basis *B, const nmf_matrix *Vnew, float *Ht_new
                void *stream);
 NMF_API void nmf_basis_destroy(nmf_basis *B);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): nmf_foldin for
+ * sparse Vnew (CSR(Vnew') in the t_* arrays) with no allocation.  Its scratch
+ * (the solve's work counter and the c x r data-product rows) is a fixed
+ * device array of NMF_FOLDIN_NOALLOC_BYTES, held on every GPU the library
+ * runs on until the process ends; so c may be at most
+ * (NMF_FOLDIN_NOALLOC_BYTES - 256) / (4 r) columns (32767 at r = 128), and
+ * larger requests return NMF_E_INVAL before any launch.  Dense Vnew returns
+ * NMF_E_UNSUPPORTED.  Results equal nmf_foldin's bitwise.  Every call on a
+ * GPU shares that GPU's scratch and leaves its contents behind: calls that
+ * overlap on one GPU (different streams or host threads) race; serialise
+ * them. */
+#define NMF_FOLDIN_NOALLOC_BYTES (16 << 20)
+NMF_API int nmf_foldin_noalloc(const nmf_basis *B, const nmf_matrix *Vnew, float *Ht_new, int32_t *iters,
+                               void *stream);
+
 /* ---------------------------------------------------------------- serving
  * A request loop over a resident basis: fold-in requests (the E-step of
  * nmf_foldin for new columns) and small full fits (nmf_fit), continuously

@@ -707,7 +707,7 @@ extern "C" void nmf_basis_destroy(nmf_basis *b) {
 
 namespace nmfi {
 // Fold-in of c columns whose product rows P (c x r) the caller's stream will
-// produce; returns the P buffer to fill and launches the solve.
+// produce: launches the solve.
 int basis_solve(const nmf_basis *B, const float *P, int64_t c, float *Ht_new, int32_t *iters,
                 unsigned long long *counter, hipStream_t s) {
     NMF_HIP(launch_zero_u64(counter, 1, s));

@@ -242,6 +242,11 @@ struct nmf_basis {
 };
 namespace nmfi {
 size_t plan_footprint(const nmf_matrix *V, int r, const nmf_opts *opt);
+// The fold-in's solve of c columns whose data-product rows P (c x r) are on
+// the stream: zeroes *counter (a kernel, no memset) and launches Algorithm 3
+// from x0 = 0 against the basis' Gram.
+int basis_solve(const nmf_basis *B, const float *P, int64_t c, float *Ht_new, int32_t *iters,
+                unsigned long long *counter, hipStream_t s);
 
 // ------------------------------------------------------------------ misc
 hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t s);

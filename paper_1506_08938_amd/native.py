@@ -26,7 +26,7 @@ EXPORTS = [
     "nmf_fit", "nmf_fit_streamed", "nmf_objective", "nmf_fit_batched",
     "nmf_server_create", "nmf_server_submit", "nmf_server_poll", "nmf_server_wait",
     "nmf_server_stats", "nmf_server_destroy",
-    "nmf_basis_create", "nmf_foldin", "nmf_basis_destroy",
+    "nmf_basis_create", "nmf_foldin", "nmf_basis_destroy", "nmf_foldin_noalloc",
 ]
 
 
@@ -150,6 +150,7 @@ def lib():
                                        ctypes.c_float, ctypes.POINTER(NmfOpts),
                                        ctypes.POINTER(_vp), _vp]
         L.nmf_foldin.argtypes = [_vp, ctypes.POINTER(NmfMatrix), _vp, _vp, _vp]
+        L.nmf_foldin_noalloc.argtypes = [_vp, ctypes.POINTER(NmfMatrix), _vp, _vp, _vp]
         L.nmf_basis_destroy.argtypes = [_vp]
         L.nmf_basis_destroy.restype = None
         _lib = L
@@ -413,6 +414,17 @@ class Basis:
         _dev(iters, torch.int32, "iters", (c,))
         check(lib().nmf_foldin(self.h, ctypes.byref(Vnew.m), _ptr(out), _ptr(iters),
                                stream_ptr()))
+        return out
+
+    def foldin_noalloc(self, Vnew: DeviceMatrix, out, iters=None):
+        """nmf_foldin_noalloc: sparse Vnew, no device allocation by the
+        library (out, and iters if given, are the caller's)."""
+        torch = _torch()
+        c = Vnew.m.cols
+        _dev(out, torch.float32, "Ht_new", (c, self.r))
+        _dev(iters, torch.int32, "iters", (c,))
+        check(lib().nmf_foldin_noalloc(self.h, ctypes.byref(Vnew.m), _ptr(out), _ptr(iters),
+                                       stream_ptr()))
         return out
 
     def close(self):
