@@ -142,7 +142,7 @@ def foldin_solve_roofline(native, synth, torch, W, m, r, seed, ncols=8192):
 
 
 def serving_leg(native, synth, torch, n_req, loads=(0.5,), seed=5005, n_warm=None, batch_cols=16384,
-                foldin_solve=False):
+                foldin_solve=False, slots=3):
     """Saturated throughput and Poisson-arrival latency of nmf_server_* at each offered load
     (a fraction of the saturated request rate)."""
     import numpy as np
@@ -194,7 +194,7 @@ def serving_leg(native, synth, torch, n_req, loads=(0.5,), seed=5005, n_warm=Non
         """All requests at once (arrivals None) or at the given times; returns the elapsed
         time of the measured requests and their latencies."""
         reset_fits()
-        S = native.Server(basis, hbm_budget=8 << 30, max_slots=4, max_batch_cols=batch_cols)
+        S = native.Server(basis, hbm_budget=8 << 30, max_slots=slots, max_batch_cols=batch_cols)
         tickets = []
         t0 = time.perf_counter()
         t_first = None
@@ -207,10 +207,10 @@ def serving_leg(native, synth, torch, n_req, loads=(0.5,), seed=5005, n_warm=Non
             tickets.append(submit(S, i))
         S.wait()
         t_end = time.perf_counter()
-        lat = np.array([S.poll(t)[1] for t in tickets])
+        tl = np.array([S.poll_times(t)[1] for t in tickets])  # queued, launch, device, latency (ms)
         st = S.stats()
         S.close()
-        return t_end - t_first, lat[n_warm:], st
+        return t_end - t_first, tl[n_warm:], st
 
     meas = slice(n_warm, total)
     cols = int(csize[meas].sum())
@@ -225,8 +225,13 @@ def serving_leg(native, synth, torch, n_req, loads=(0.5,), seed=5005, n_warm=Non
     for k, ld in enumerate(loads):
         rate = ld * rate_sat
         arrivals = synth.poisson_arrivals(total, rate, seed + 7 + k)
-        el, lat, st = run(arrivals)
+        el, tl, st = run(arrivals)
+        lat = tl[:, 3]
         lf = lat[fold]
+        # where the slowest 1% of fold-in requests spent their time
+        slow = tl[fold][lf >= np.percentile(lf, 99)]
+        tail = {"queued_ms": float(np.median(slow[:, 0])), "launch_ms": float(np.median(slow[:, 1])),
+                "device_ms": float(np.median(slow[:, 2]))}
         sz = csize[meas][fold]
         edges = np.quantile(sz, np.linspace(0, 1, 11))
         dec = []
@@ -241,7 +246,7 @@ def serving_leg(native, synth, torch, n_req, loads=(0.5,), seed=5005, n_warm=Non
             "requests_per_s": n_req / el,
             "fold_in_p50_ms": float(np.percentile(lf, 50)), "fold_in_p99_ms": float(np.percentile(lf, 99)),
             "fit_p50_ms": float(np.percentile(lat[~fold], 50)) if (~fold).any() else None,
-            "batches": st["batches"], "by_size_decile": dec})
+            "batches": st["batches"], "p99_tail_median_breakdown": tail, "by_size_decile": dec})
         log(f"[bench] load {ld}: {rate:.0f} req/s, fold-in p50 {per_load[-1]['fold_in_p50_ms']:.3f} ms "
             f"p99 {per_load[-1]['fold_in_p99_ms']:.3f} ms")
     basis.close()
@@ -249,7 +254,7 @@ def serving_leg(native, synth, torch, n_req, loads=(0.5,), seed=5005, n_warm=Non
         "workload": "resident basis W 100000x128 (20 outer iterations fitted on the device to "
                     "2048 columns of Gamma(2,0.5)-factor data), L1=0.05, eps=1e-3; fold-in requests of "
                     "c~logU[1,8192] columns at 0.5% density, values log(1+Poisson(3)); 5% small "
-                    "full fits (m,n~logU[64,2048], r~U{4..32}, 30 outer iterations); 4 slots, "
+                    f"full fits (m,n~logU[64,2048], r~U{{4..32}}, 30 outer iterations); {slots} slots, "
                     f"batches of up to {batch_cols} columns",
         "requests": n_req, "warmup_requests": n_warm,
         "fold_in_columns": cols,
@@ -525,7 +530,7 @@ def bench_serving(args, native, synth, torch, np):
     """The serving configuration at several offered loads."""
     loads = (0.3, 0.6, 0.9)
     res = serving_leg(native, synth, torch, args.serve_requests, loads, n_warm=args.serve_warmup,
-                      batch_cols=args.serve_batch_cols, foldin_solve=True)
+                      batch_cols=args.serve_batch_cols, foldin_solve=True, slots=args.serve_slots)
     out = base_line(
         "fold-in serving: column NNLS solves/s and p50/p99 latency at offered loads",
         res["saturated_solves_per_s"], "column NNLS solves/s", args.serve_requests, 0,
@@ -547,6 +552,8 @@ def main():
     ap.add_argument("--serve-warmup", type=int, default=1000, help="warm-up requests before each measurement")
     ap.add_argument("--serve-loads", default="0.3,0.6,0.9",
                     help="offered loads, as fractions of the saturated request rate")
+    ap.add_argument("--serve-slots", type=int, default=3,
+                    help="server slots (streams; the library caps them at the hardware queues minus one)")
     ap.add_argument("--serve-batch-cols", type=int, default=16384,
                     help="largest fold-in batch (columns) the server forms")
     ap.add_argument("--workload", default="sparse", choices=["sparse", "dense", "batched", "serving", "streamed"],
@@ -730,7 +737,7 @@ def main():
     if not args.no_serve:
         loads = tuple(float(x) for x in args.serve_loads.split(","))
         res = serving_leg(native, synth, torch, args.serve_requests, loads, n_warm=args.serve_warmup,
-                          batch_cols=args.serve_batch_cols, foldin_solve=True)
+                          batch_cols=args.serve_batch_cols, foldin_solve=True, slots=args.serve_slots)
         out["serving"] = res
 
     if not args.no_cpu:

@@ -314,15 +314,20 @@ NMF_API int nmf_foldin_noalloc(const nmf_basis *B, const nmf_matrix *Vnew, float
 /* ---------------------------------------------------------------- serving
  * A request loop over a resident basis: fold-in requests (the E-step of
  * nmf_foldin for new columns) and small full fits (nmf_fit), continuously
- * batched.  max_slots worker threads each own a stream; each admits work
- * from the head of the arrival-ordered queue while the HBM footprint of the
- * admitted work stays within hbm_budget bytes, packing consecutive fold-in
- * requests (up to max_batch_cols columns) into one batch with a single solve
- * launch; a fit request runs alone on its slot, and fits hold at most
- * max_slots - 1 slots (fold-in requests queued behind a waiting fit go
- * ahead of it).  Requests arriving while
- * others run are picked up by the next free slot, so batches overlap on the
- * device.  A request's result does not depend on what it is batched with.
+ * batched.  max_slots slots each own a stream, a launcher thread and a
+ * completion thread; a launcher admits work from the head of the
+ * arrival-ordered queue while the HBM footprint of the admitted work stays
+ * within hbm_budget bytes, packing consecutive fold-in requests (up to
+ * max_batch_cols columns) into one batch with one product launch over its
+ * sparse requests and a single solve launch; a fit request runs alone on its
+ * slot with stream-ordered memory, and fits hold at most max_slots - 1
+ * slots (fold-in requests queued behind a waiting fit go ahead of it).
+ * Launchers do not wait for the device (up to two batches per slot are in
+ * flight); the completion thread reports a batch done when its stream has
+ * passed it.  The slots are capped at the process's hardware queues minus one
+ * (GPU_MAX_HW_QUEUES, 4 unless set, so 3 slots by default): streams beyond
+ * that would share hardware queues, whose work runs in order.  Requests arriving while others run are picked up by the next
+ * free slot, so batches overlap on the device.  A request's result does not depend on what it is batched with.
  * Request memory is the caller's (device pointers): its inputs must be
  * written before submission (workers run on their own streams, unordered with
  * the caller's) and it must stay valid until the request is done.  Fold-in requests use the basis' options; fit requests
@@ -351,6 +356,12 @@ NMF_API int nmf_server_submit(nmf_server *s, const nmf_request *req, uint64_t *t
  * Returns the request's status once done.  A request reported done by poll
  * or by wait(ticket) is forgotten: its ticket is unknown afterwards. */
 NMF_API int nmf_server_poll(nmf_server *s, uint64_t ticket, int32_t *done, double *latency_ms);
+/* As nmf_server_poll, with the request's timeline (host clock, ms): once done,
+ * times_ms[0] = submission -> admission (waiting in the queue), [1] =
+ * admission -> its batch's last launch returned, [2] = that -> completion,
+ * [3] = the whole latency; NaN while not done.  A request reported done is
+ * forgotten, as with nmf_server_poll. */
+NMF_API int nmf_server_poll_times(nmf_server *s, uint64_t ticket, int32_t *done, double *times_ms);
 /* Blocks until the request (ticket 0: every request submitted so far; those
  * records stay until polled) is done. */
 NMF_API int nmf_server_wait(nmf_server *s, uint64_t ticket, double *latency_ms);

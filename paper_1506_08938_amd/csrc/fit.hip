@@ -200,6 +200,11 @@ extern "C" int nmf_product(const nmf_matrix *V, int32_t trans, int32_t r, const 
 
 // ============================================================ plan / fit
 struct nmf_plan {
+    // stream-ordered memory (hipMallocAsync / hipFreeAsync on mem_stream): no
+    // device-wide synchronisation when the plan comes and goes (the server's
+    // fit requests; dense V only)
+    bool async_mem = false;
+    hipStream_t mem_stream = nullptr;
     nmf_matrix V{};
     int64_t m = 0, n = 0;
     int r = 0;
@@ -255,11 +260,20 @@ static void plan_free(nmf_plan *p) {
     if (p->P_hot) (void)hipFree(p->P_hot);
     if (p->hot_scratch) (void)hipFree(p->hot_scratch);
     if (p->A16) (void)hipFree(p->A16);
-    if (p->V16) (void)hipFree(p->V16);
-    if (p->V16t) (void)hipFree(p->V16t);
-    if (p->dense_scratch) (void)hipFree(p->dense_scratch);
-    if (p->ws) (void)hipFree(p->ws);
+    auto rel = [p](void *x) {
+        if (!x) return;
+        if (p->async_mem) (void)hipFreeAsync(x, p->mem_stream);
+        else (void)hipFree(x);
+    };
+    rel(p->V16);
+    rel(p->V16t);
+    rel(p->dense_scratch);
+    rel(p->ws);
     delete p;
+}
+
+static hipError_t plan_malloc(const nmf_plan *p, void **ptr, size_t bytes) {
+    return p->async_mem ? hipMallocAsync(ptr, bytes, p->mem_stream) : hipMalloc(ptr, bytes);
 }
 
 // Hot columns of a CSR V: a column j with c_j stored entries costs the
@@ -308,8 +322,16 @@ static int choose_hot_columns(nmf_plan *p, const std::vector<int32_t> &t_rowptr,
     return NMF_OK;
 }
 
+static int plan_create(const nmf_matrix *V, int32_t r, const nmf_reg *reg, const nmf_opts *opt,
+                       nmf_plan **out, void *stream, bool async_mem);
+
 extern "C" int nmf_plan_create(const nmf_matrix *V, int32_t r, const nmf_reg *reg, const nmf_opts *opt,
                                nmf_plan **out, void *stream) {
+    return plan_create(V, r, reg, opt, out, stream, false);
+}
+
+static int plan_create(const nmf_matrix *V, int32_t r, const nmf_reg *reg, const nmf_opts *opt,
+                       nmf_plan **out, void *stream, bool async_mem) {
     if (!out) return fail(NMF_E_INVAL, "out is NULL");
     *out = nullptr;
     if (int st = validate_matrix(V, true)) return st;
@@ -333,6 +355,8 @@ extern "C" int nmf_plan_create(const nmf_matrix *V, int32_t r, const nmf_reg *re
         if (st) return st;
     }
     nmf_plan *p = new nmf_plan();
+    p->async_mem = async_mem && V->kind == NMF_DENSE;
+    p->mem_stream = s;
     p->V = *V; p->m = V->rows; p->n = V->cols; p->r = r; p->reg = *reg; p->opt = *opt;
     p->var_h = nqp_pick(r, p->n, opt->lanes);
     p->var_w = nqp_pick(r, p->m, opt->lanes);
@@ -374,14 +398,14 @@ extern "C" int nmf_plan_create(const nmf_matrix *V, int32_t r, const nmf_reg *re
         }
     } else {
         if (opt->precision == NMF_BF16) {
-            hipError_t e = hipMalloc((void **)&p->V16, (size_t)p->m * p->n * sizeof(__bf16));
-            if (e == hipSuccess) e = hipMalloc((void **)&p->V16t, (size_t)p->m * p->n * sizeof(__bf16));
+            hipError_t e = plan_malloc(p, (void **)&p->V16, (size_t)p->m * p->n * sizeof(__bf16));
+            if (e == hipSuccess) e = plan_malloc(p, (void **)&p->V16t, (size_t)p->m * p->n * sizeof(__bf16));
             if (e == hipSuccess) e = launch_to_bf16(V->dense, p->m, p->n, V->ld, p->V16, s);
             if (e == hipSuccess) e = launch_to_bf16_t(V->dense, p->m, p->n, V->ld, p->V16t, s);
             if (e != hipSuccess) st = hip_fail(e, "BF16 copy of V");
         }
         if (!st) {
-            hipError_t e = hipMalloc((void **)&p->dense_scratch, dense_scratch_bytes(p->m, p->n, r));
+            hipError_t e = plan_malloc(p, (void **)&p->dense_scratch, dense_scratch_bytes(p->m, p->n, r));
             if (e != hipSuccess) st = hip_fail(e, "hipMalloc");
         }
     }
@@ -397,7 +421,7 @@ extern "C" int nmf_plan_create(const nmf_matrix *V, int32_t r, const nmf_reg *re
         const size_t o_ko = place(8 * sizeof(double));
         const size_t o_kp = place(kkt_partial_bytes(cmax));
         const size_t o_os = place(objective_scratch_bytes(V, r));
-        hipError_t e = hipMalloc((void **)&p->ws, off);
+        hipError_t e = plan_malloc(p, (void **)&p->ws, off);
         if (e != hipSuccess) {
             st = hip_fail(e, "plan workspace");
         } else {
@@ -412,11 +436,12 @@ extern "C" int nmf_plan_create(const nmf_matrix *V, int32_t r, const nmf_reg *re
             p->obj_scratch = p->ws + o_os;
         }
     }
-    if (!st) {
+    if (!st && !p->async_mem) {
         hipError_t e = hipStreamSynchronize(s);
         if (e != hipSuccess) st = hip_fail(e, "plan set-up");
     }
     if (st) {
+        if (p->async_mem) (void)hipStreamSynchronize(s);
         plan_free(p);
         return st;
     }
@@ -616,6 +641,21 @@ extern "C" int nmf_plan_run(nmf_plan *p, float *W, float *Ht, int32_t outer, dou
     }
     return NMF_OK;
 }
+
+namespace nmfi {
+// nmf_fit without host synchronisation: the plan's memory comes and goes
+// stream-ordered on `stream` (dense V), so nothing waits for the device and
+// no other stream is held up; the results are complete once `stream` drains.
+int fit_stream_ordered(const nmf_matrix *V, int32_t r, const nmf_reg *reg, const nmf_opts *opt, float *W,
+                       float *Ht, hipStream_t stream) {
+    nmf_plan *p = nullptr;
+    if (int st = plan_create(V, r, reg, opt, &p, stream, true)) return st;
+    int st = nmf_plan_run(p, W, Ht, opt->max_outer, nullptr, nullptr, stream);
+    if (!p->async_mem) (void)hipStreamSynchronize(stream);
+    plan_free(p);
+    return st;
+}
+}  // namespace nmfi
 
 extern "C" int nmf_fit(const nmf_matrix *V, int32_t r, const nmf_reg *reg, const nmf_opts *opt, float *W,
                        float *Ht, double *trace, nmf_stats *stats, void *stream) {

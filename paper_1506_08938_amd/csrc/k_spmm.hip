@@ -352,6 +352,49 @@ __global__ __launch_bounds__(256) void k_spmm_rows(const int32_t *__restrict__ r
     spmm_finish<VEC, LPN, NV>(acc, r, P + w * r);
 }
 
+// The rows of several matrices in one launch (a fold-in batch of several
+// requests): launch row w belongs to the last request with row0 <= w and is
+// written to row p0 + (w - row0) of P; each row's arithmetic is that of
+// k_spmm_rows.
+template <typename TA, int VEC, int LPN, int NV>
+__global__ __launch_bounds__(256) void k_spmm_rows_multi(const SpRowsReq *__restrict__ reqs, int nreq,
+                                                         int64_t nrows, const TA *__restrict__ A, int r,
+                                                         int lda, float *__restrict__ P) {
+    const int64_t w = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (w >= nrows) return;
+    int lo = 0, hi = nreq - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (reqs[mid].row0 <= w) lo = mid;
+        else hi = mid - 1;
+    }
+    const SpRowsReq q = reqs[lo];
+    const int64_t i = w - q.row0;
+    float acc[NV][VEC];
+#pragma unroll
+    for (int t = 0; t < NV; t++)
+#pragma unroll
+        for (int v = 0; v < VEC; v++) acc[t][v] = 0.f;
+    spmm_range<TA, VEC, LPN, NV>(q.rowptr[i], q.rowptr[i + 1], q.colidx, q.vals, A, r, lda, acc);
+    spmm_finish<VEC, LPN, NV>(acc, r, P + (q.p0 + i) * r);
+}
+
+hipError_t launch_spmm_rows_multi(const SpRowsReq *reqs, int nreq, int64_t nrows, const float *A,
+                                  const __bf16 *A16, int lda16, int r, float *P, hipStream_t s) {
+    if (nrows <= 0 || nreq <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((nrows + 3) / 4)), blk(256);
+    if (A16)
+        hipLaunchKernelGGL((k_spmm_rows_multi<__bf16, NMF_SPMM_VEC16, 128 / NMF_SPMM_VEC16, 1>), grid, blk, 0, s,
+                           reqs, nreq, nrows, A16, r, lda16, P);
+    else if (r % 4 == 0 && r <= 128)
+        hipLaunchKernelGGL((k_spmm_rows_multi<float, 4, 32, 1>), grid, blk, 0, s, reqs, nreq, nrows, A, r, r, P);
+    else if (r <= 64)
+        hipLaunchKernelGGL((k_spmm_rows_multi<float, 1, 64, 1>), grid, blk, 0, s, reqs, nreq, nrows, A, r, r, P);
+    else
+        hipLaunchKernelGGL((k_spmm_rows_multi<float, 1, 64, 2>), grid, blk, 0, s, reqs, nreq, nrows, A, r, r, P);
+    return hipGetLastError();
+}
+
 hipError_t launch_spmm_rows(const int32_t *rowptr, int64_t nrows, const int32_t *colidx,
                             const float *vals, const float *A, int r, float *P, hipStream_t s) {
     if (nrows <= 0) return hipSuccess;

@@ -100,6 +100,21 @@ hipError_t launch_spmm16(const SpmmPlan &pl, const int32_t *colidx, const float 
 hipError_t launch_spmm_rows16(const int32_t *rowptr, int64_t nrows, const int32_t *colidx,
                               const float *vals, const __bf16 *A16, int lda16, int r, float *P,
                               hipStream_t s);
+// One request of a multi-request row product: its CSR (rows of the
+// request's transpose) and the global index of its first row.
+struct SpRowsReq {
+    const int32_t *rowptr;
+    const int32_t *colidx;
+    const float *vals;
+    int64_t row0;  // index of its first row among the launch's rows
+    int64_t p0;    // row of P its first row is written to
+};
+// The launch's nrows rows are those of nreq requests (reqs: device array
+// sorted by row0, row0[0] = 0, every request non-empty); request q's row i
+// times A (FP32), or A16 (BF16 copy with leading dimension lda16) when A16 is
+// non-null, goes to row q.p0 + i of P (ld r).
+hipError_t launch_spmm_rows_multi(const SpRowsReq *reqs, int nreq, int64_t nrows, const float *A,
+                                  const __bf16 *A16, int lda16, int r, float *P, hipStream_t s);
 
 size_t gram_scratch_bytes(int r, int64_t k);
 // Also zeroes *counter (when non-NULL) so that a solve can follow on the stream.
@@ -247,6 +262,10 @@ size_t plan_footprint(const nmf_matrix *V, int r, const nmf_opts *opt);
 // from x0 = 0 against the basis' Gram.
 int basis_solve(const nmf_basis *B, const float *P, int64_t c, float *Ht_new, int32_t *iters,
                 unsigned long long *counter, hipStream_t s);
+// nmf_fit with stream-ordered plan memory and no host synchronisation (dense
+// V): complete once `stream` drains.
+int fit_stream_ordered(const nmf_matrix *V, int32_t r, const nmf_reg *reg, const nmf_opts *opt, float *W,
+                       float *Ht, hipStream_t stream);
 
 // ------------------------------------------------------------------ misc
 hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t s);

@@ -1,26 +1,39 @@
 // Serving: fold-in requests (the E-step alone against a resident basis,
 // Section 3.1) and small full fits (Algorithm 2), continuously batched.
 //
-// Each of `max_slots` worker threads owns a HIP stream (default priority).
-// Requests queue in arrival order; a free worker admits from the head of the
-// queue (fit requests hold at most max_slots - 1 slots: one stays free for
-// fold-ins, which pass a fit that has to wait) while the HBM footprint of the
-// admitted work stays within the budget:
+// Each of `max_slots` slots owns a HIP stream (default priority), a launcher
+// thread and a completion thread.  Requests queue in arrival order; a
+// launcher admits from the head of the queue (fit requests hold at most
+// max_slots - 1 slots: one stays free for fold-ins, which pass a fit that has
+// to wait) while the HBM footprint of the admitted work stays within the
+// budget:
 // consecutive fold-in requests (up to max_batch_cols columns) become one
-// batch -- one product launch per request, then ONE solve launch over all of
-// the batch's columns -- and a full-fit request runs alone on its slot.
+// batch -- one product launch over all of its sparse requests' columns, then
+// ONE solve launch over all of the batch's columns -- and a full-fit request
+// runs alone on its slot, its plan's memory stream-ordered on the slot's
+// stream (no device-wide synchronisation).  The launcher never waits for the
+// device: it hands the batch, with an event recorded after its last launch,
+// to the slot's completion thread and may admit the next one.  A slot with
+// work in flight takes more (at most kMaxInFlight batches) only behind a
+// fold-in batch and only while no slot is idle: work queued on a stream waits
+// for the work ahead of it, and a fit keeps its stream busy for long.  The
+// completion thread waits for the events in order and releases the batch's
+// footprint.
 // Requests arriving while batches run are picked up by the next free slot,
 // so work from different batches overlaps on the device.  A column's
 // arithmetic does not depend on the batch it lands in: results are the same
 // alone and in the mix.
 #include <math.h>
+#include <stdlib.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
 #include <memory>
 #include <mutex>
+#include <string>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -37,16 +50,45 @@ double now_s() {
 
 size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+constexpr size_t kMaxInFlight = 2;  // batches launched and not yet complete, per slot
+
 struct Req {
     uint64_t ticket = 0;
     nmf_request q{};
     size_t footprint = 0;
-    double t_submit = 0.0, t_done = 0.0;
+    double t_submit = 0.0, t_admit = 0.0, t_launch = 0.0, t_done = 0.0;
     int state = 0;  // 0 queued, 1 running, 2 done
     int status = NMF_OK;
+    std::string msg;  // the failure's message (the status is reported on another thread)
 };
 
 int64_t req_cols(const nmf_request &q) { return q.V.cols; }
+
+// A batch whose launches are on its slot's stream; the host arrays it
+// copied from live here until the batch completes.
+struct InFlight {
+    std::vector<std::shared_ptr<Req>> batch;
+    size_t fp = 0;
+    bool is_fit = false;
+    int status = NMF_OK;
+    std::string msg;
+    hipEvent_t ev = nullptr;
+    std::vector<BSolveProb> probs;
+    std::vector<BSolveChunk> chunks;
+    std::vector<SpRowsReq> rows;
+};
+
+struct Slot {
+    hipStream_t s = nullptr;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<std::unique_ptr<InFlight>> inflight;
+    bool closing = false;  // the launcher has finished; drain and stop
+    std::thread launcher, completer;
+    // under the server's mutex: batches in flight, and whether one is a fit
+    int busy = 0;
+    bool has_fit = false;
+};
 
 }  // namespace
 
@@ -63,7 +105,8 @@ struct nmf_server {
     std::unordered_map<uint64_t, std::shared_ptr<Req>> reqs;
     uint64_t next_ticket = 1;
     bool stop = false;
-    std::vector<std::thread> workers;
+    std::vector<std::unique_ptr<Slot>> slots;
+    int idle = 0;  // slots with nothing in flight
     int64_t batches = 0, completed = 0, columns = 0, submitted = 0;
 };
 
@@ -75,81 +118,92 @@ size_t foldin_footprint(const nmf_basis *B, const nmf_request &q) {
     return b;
 }
 
-// one batch of fold-in requests on stream s
-int run_foldin_batch(nmf_server *S, std::vector<std::shared_ptr<Req>> &batch, hipStream_t s) {
+// Launches one batch of fold-in requests on stream s (no waiting).
+int launch_foldin_batch(nmf_server *S, InFlight &F, hipStream_t s) {
     const nmf_basis *B = S->B;
     const int r = B->r;
-    int64_t ctot = 0;
+    int64_t ctot = 0, sparse_rows = 0;
     size_t dense_scr = 0;
-    for (auto &q : batch) {
+    for (auto &q : F.batch) {
         ctot += req_cols(q->q);
         if (q->q.V.kind == NMF_DENSE) dense_scr = std::max(dense_scr, dense_scratch_bytes(B->m, q->q.V.cols, r));
     }
-    std::vector<BSolveProb> probs;
-    std::vector<BSolveChunk> chunks;
     const int chunk = bnqp_chunk_cols(B->var.L, B->opt.fast_break_cols);
     int64_t off = 0;
-    for (size_t j = 0; j < batch.size(); j++) {
-        const nmf_request &q = batch[j]->q;
-        probs.push_back(BSolveProb{B->G, nullptr, q.out, r, B->l1, nullptr, q.iters, 1});
+    for (size_t j = 0; j < F.batch.size(); j++) {
+        const nmf_request &q = F.batch[j]->q;
+        F.probs.push_back(BSolveProb{B->G, nullptr, q.out, r, B->l1, nullptr, q.iters, 1});
         for (int64_t c0 = 0; c0 < q.V.cols; c0 += chunk)
-            chunks.push_back({(int32_t)j, (int32_t)c0, (int32_t)std::min<int64_t>(q.V.cols, c0 + chunk)});
+            F.chunks.push_back({(int32_t)j, (int32_t)c0, (int32_t)std::min<int64_t>(q.V.cols, c0 + chunk)});
+        if (q.V.kind == NMF_CSR) {
+            F.rows.push_back(SpRowsReq{q.V.t_rowptr, q.V.t_colidx, q.V.t_vals, sparse_rows, off});
+            sparse_rows += q.V.cols;
+        }
         off += q.V.cols;
     }
     const size_t pbytes = al256((size_t)ctot * r * 4), dbytes = al256(dense_scr);
-    const size_t lbytes = al256(probs.size() * sizeof(BSolveProb)) + al256(chunks.size() * sizeof(BSolveChunk));
+    const size_t bp = al256(F.probs.size() * sizeof(BSolveProb)), bc = al256(F.chunks.size() * sizeof(BSolveChunk));
+    const size_t br = al256(F.rows.size() * sizeof(SpRowsReq));
     char *ws = nullptr;
-    NMF_HIP(hipMallocAsync((void **)&ws, 256 + pbytes + dbytes + lbytes, s));
+    NMF_HIP(hipMallocAsync((void **)&ws, 256 + pbytes + dbytes + bp + bc + br, s));
     unsigned int *queue = (unsigned int *)ws;
     float *P = (float *)(ws + 256);
     float *dscr = (float *)(ws + 256 + pbytes);
     BSolveProb *dprobs = (BSolveProb *)(ws + 256 + pbytes + dbytes);
-    BSolveChunk *dchunks = (BSolveChunk *)((char *)dprobs + al256(probs.size() * sizeof(BSolveProb)));
+    BSolveChunk *dchunks = (BSolveChunk *)((char *)dprobs + bp);
+    SpRowsReq *drows = (SpRowsReq *)((char *)dchunks + bc);
     hipError_t e = hipSuccess;
     off = 0;
-    for (size_t j = 0; j < batch.size() && e == hipSuccess; j++) {
-        const nmf_request &q = batch[j]->q;
-        float *Pj = P + off * r;
-        probs[j].P = Pj;
+    for (size_t j = 0; j < F.batch.size() && e == hipSuccess; j++) {
+        const nmf_request &q = F.batch[j]->q;
+        F.probs[j].P = P + off * r;
         if (q.V.kind == NMF_DENSE)
-            e = launch_dense_product(q.V.dense, 0, B->m, q.V.cols, q.V.ld, nullptr, 0, B->W, r, Pj, dscr, s);
-        else if (B->W16)
-            e = launch_spmm_rows16(q.V.t_rowptr, q.V.cols, q.V.t_colidx, q.V.t_vals, B->W16, B->lda16, r, Pj, s);
-        else
-            e = launch_spmm_rows(q.V.t_rowptr, q.V.cols, q.V.t_colidx, q.V.t_vals, B->W, r, Pj, s);
+            e = launch_dense_product(q.V.dense, 0, B->m, q.V.cols, q.V.ld, nullptr, 0, B->W, r, P + off * r, dscr, s);
         off += q.V.cols;
     }
+    if (e == hipSuccess && !F.rows.empty()) {
+        e = hipMemcpyAsync(drows, F.rows.data(), F.rows.size() * sizeof(SpRowsReq), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = launch_spmm_rows_multi(drows, (int)F.rows.size(), sparse_rows, B->W, B->W16, B->lda16, r, P, s);
+    }
     if (e == hipSuccess)
-        e = hipMemcpyAsync(dprobs, probs.data(), probs.size() * sizeof(BSolveProb), hipMemcpyHostToDevice, s);
+        e = hipMemcpyAsync(dprobs, F.probs.data(), F.probs.size() * sizeof(BSolveProb), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(dchunks, chunks.data(), chunks.size() * sizeof(BSolveChunk), hipMemcpyHostToDevice, s);
+        e = hipMemcpyAsync(dchunks, F.chunks.data(), F.chunks.size() * sizeof(BSolveChunk), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = launch_zero_u32(queue, 1, s);
     if (e == hipSuccess)
-        e = launch_bnqp(B->var, dchunks, (int)chunks.size(), queue, dprobs, B->opt.max_inner,
+        e = launch_bnqp(B->var, dchunks, (int)F.chunks.size(), queue, dprobs, B->opt.max_inner,
                         B->opt.eps, B->opt.ls_guard ? 1 : 0, B->opt.fast_break_cols, s);
     (void)hipFreeAsync(ws, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host vectors live until here
     if (e != hipSuccess) return hip_fail(e, "server fold-in batch");
     return NMF_OK;
 }
 
-int run_fit_request(nmf_server *S, Req &R, hipStream_t s) {
-    (void)S;
+int launch_fit_request(InFlight &F, hipStream_t s) {
+    Req &R = *F.batch[0];
     nmf_opts o = R.q.fit_opts;
-    return nmf_fit(&R.q.V, R.q.r, &R.q.reg, &o, R.q.W, R.q.Ht, nullptr, nullptr, s);
+    return fit_stream_ordered(&R.q.V, R.q.r, &R.q.reg, &o, R.q.W, R.q.Ht, s);
 }
 
-void worker(nmf_server *S) {
+// Whether a slot may take more work now: always when idle; a second batch
+// behind a fold-in batch (never behind a fit, whose stream stays busy for
+// long) only when no slot is idle, since work queued on a busy stream waits
+// for the work ahead of it.
+bool slot_can_take(const nmf_server *S, const Slot *sl) {
+    if (sl->busy == 0) return true;
+    return sl->busy < (int)kMaxInFlight && !sl->has_fit && S->idle == 0;
+}
+
+// Takes admissible work off the queue, launches it, hands it to the
+// completion thread; never waits for the device.
+void launcher(nmf_server *S, Slot *sl) {
     (void)hipSetDevice(S->device);
-    hipStream_t s = nullptr;
-    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return;
+    const hipStream_t s = sl->s;
     for (;;) {
-        std::vector<std::shared_ptr<Req>> batch;
-        size_t fp = 0;
-        bool is_fit = false;
+        auto F = std::make_unique<InFlight>();
         {
             std::unique_lock<std::mutex> lk(S->mu);
-            // The first request this worker may start: the head of the queue,
+            // The first request this slot may start: the head of the queue,
             // except that a fit request waits while max_fits fits run, and the
             // fold-in requests queued behind it go ahead meanwhile.
             auto first = [&]() -> std::deque<std::shared_ptr<Req>>::iterator {
@@ -161,16 +215,17 @@ void worker(nmf_server *S) {
             };
             S->cv_work.wait(lk, [&] {
                 if (S->stop && S->queue.empty()) return true;
+                if (!slot_can_take(S, sl)) return false;
                 auto it = first();
                 return it != S->queue.end() && S->in_use + (*it)->footprint <= S->budget;
             });
             if (S->queue.empty()) break;  // stopping
             auto it = first();
             if ((*it)->q.kind == NMF_REQ_FIT) {
-                batch.push_back(*it);
-                fp = (*it)->footprint;
+                F->batch.push_back(*it);
+                F->fp = (*it)->footprint;
                 S->queue.erase(it);
-                is_fit = true;
+                F->is_fit = true;
                 S->fits_running++;
             } else {
                 // consecutive fold-in requests from there, in arrival order
@@ -178,40 +233,109 @@ void worker(nmf_server *S) {
                 while (it != S->queue.end()) {
                     auto &q = *it;
                     if (q->q.kind != NMF_REQ_FOLDIN) break;
-                    if (!batch.empty() && cols + req_cols(q->q) > S->max_cols) break;
-                    if (S->in_use + fp + q->footprint > S->budget) break;
+                    if (!F->batch.empty() && cols + req_cols(q->q) > S->max_cols) break;
+                    if (S->in_use + F->fp + q->footprint > S->budget) break;
                     cols += req_cols(q->q);
-                    fp += q->footprint;
-                    batch.push_back(q);
+                    F->fp += q->footprint;
+                    F->batch.push_back(q);
                     it = S->queue.erase(it);
                 }
             }
-            S->in_use += fp;
-            for (auto &q : batch) q->state = 1;
+            S->in_use += F->fp;
+            if (sl->busy++ == 0) S->idle--;
+            if (F->is_fit) sl->has_fit = true;
+            const double t = now_s();
+            for (auto &q : F->batch) {
+                q->state = 1;
+                q->t_admit = t;
+            }
         }
-        int st;
-        if (batch.size() == 1 && batch[0]->q.kind == NMF_REQ_FIT) st = run_fit_request(S, *batch[0], s);
-        else st = run_foldin_batch(S, batch, s);
+        F->status = F->is_fit ? launch_fit_request(*F, s) : launch_foldin_batch(S, *F, s);
+        if (F->status) F->msg = nmf_last_error();
+        if (hipEventCreateWithFlags(&F->ev, hipEventDisableTiming) != hipSuccess ||
+            hipEventRecord(F->ev, s) != hipSuccess) {
+            if (F->ev) (void)hipEventDestroy(F->ev);
+            F->ev = nullptr;  // the completion thread drains the stream instead
+        }
+        const double t = now_s();
+        for (auto &q : F->batch) q->t_launch = t;
+        {
+            std::lock_guard<std::mutex> lk(sl->mu);
+            sl->inflight.push_back(std::move(F));
+        }
+        sl->cv.notify_all();
+    }
+    {
+        std::lock_guard<std::mutex> lk(sl->mu);
+        sl->closing = true;
+    }
+    sl->cv.notify_all();
+}
+
+// Waits for the slot's batches in launch order and reports them done.
+void completer(nmf_server *S, Slot *sl) {
+    (void)hipSetDevice(S->device);
+    for (;;) {
+        InFlight *F = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(sl->mu);
+            sl->cv.wait(lk, [&] { return !sl->inflight.empty() || sl->closing; });
+            if (sl->inflight.empty()) break;  // closing, drained
+            F = sl->inflight.front().get();
+        }
+        hipError_t e = F->ev ? hipEventSynchronize(F->ev) : hipStreamSynchronize(sl->s);
+        if (F->ev) (void)hipEventDestroy(F->ev);
+        int st = F->status;
+        std::string msg = F->msg;
+        if (!st && e != hipSuccess) {
+            st = hip_fail(e, "server batch");
+            msg = nmf_last_error();
+        }
         const double t = now_s();
         {
             std::lock_guard<std::mutex> lk(S->mu);
-            S->in_use -= fp;
-            if (is_fit) S->fits_running--;
+            S->in_use -= F->fp;
+            if (F->is_fit) {
+                S->fits_running--;
+                sl->has_fit = false;
+            }
+            if (--sl->busy == 0) S->idle++;
             S->batches++;
-            for (auto &q : batch) {
+            for (auto &q : F->batch) {
                 q->state = 2;
                 q->status = st;
+                q->msg = msg;
                 q->t_done = t;
                 S->completed++;
                 S->columns += req_cols(q->q);
             }
         }
+        {
+            std::lock_guard<std::mutex> lk(sl->mu);
+            sl->inflight.pop_front();  // releases the batch's host arrays
+        }
+        sl->cv.notify_all();
         S->cv_done.notify_all();
         S->cv_work.notify_all();
     }
-    (void)hipStreamDestroy(s);
 }
 
+}  // namespace
+
+namespace {
+// Streams the server may use without two of them sharing a hardware queue:
+// the HIP runtime gives a process GPU_MAX_HW_QUEUES hardware queues (4 unless
+// set) and assigns streams to them in turn, and the work of streams on one
+// queue runs in order -- a fold-in batch would wait behind a fit on another
+// slot.  One queue is left to the default stream.
+int hw_queue_slots() {
+    int q = 4;
+    if (const char *e = getenv("GPU_MAX_HW_QUEUES")) {
+        const int v = atoi(e);
+        if (v >= 1) q = v;
+    }
+    return q > 1 ? q - 1 : 1;
+}
 }  // namespace
 
 extern "C" int nmf_server_create(const nmf_basis *B, size_t hbm_budget, int32_t max_slots,
@@ -222,13 +346,27 @@ extern "C" int nmf_server_create(const nmf_basis *B, size_t hbm_budget, int32_t 
     if (max_slots < 1 || max_slots > 16) return fail(NMF_E_INVAL, "max_slots must be in [1, 16]");
     if (max_batch_cols < 1) return fail(NMF_E_INVAL, "max_batch_cols must be >= 1");
     if (hbm_budget < 4096) return fail(NMF_E_INVAL, "hbm_budget too small");
+    max_slots = std::min(max_slots, hw_queue_slots());
     nmf_server *S = new nmf_server();
     S->B = B;
     S->budget = hbm_budget;
     S->max_cols = max_batch_cols;
     S->max_fits = max_slots > 1 ? max_slots - 1 : 1;
     if (hipGetDevice(&S->device) != hipSuccess) S->device = 0;
-    for (int i = 0; i < max_slots; i++) S->workers.emplace_back(worker, S);
+    for (int i = 0; i < max_slots; i++) {
+        auto sl = std::make_unique<Slot>();
+        hipError_t e = hipStreamCreateWithFlags(&sl->s, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            nmf_server_destroy(S);
+            return hip_fail(e, "server stream");
+        }
+        S->slots.push_back(std::move(sl));
+    }
+    S->idle = max_slots;
+    for (auto &sl : S->slots) {
+        sl->completer = std::thread(completer, S, sl.get());
+        sl->launcher = std::thread(launcher, S, sl.get());
+    }
     *out = S;
     return NMF_OK;
 }
@@ -279,8 +417,30 @@ extern "C" int nmf_server_poll(nmf_server *S, uint64_t ticket, int32_t *done, do
     if (latency_ms) *latency_ms = R.state == 2 ? (R.t_done - R.t_submit) * 1e3 : NAN;
     if (R.state != 2) return NMF_OK;
     const int st = R.status;
+    const std::string msg = R.msg;
     S->reqs.erase(it);  // reported done: the record is released
-    return st;
+    return st ? fail(st, "%s", msg.c_str()) : NMF_OK;
+}
+
+extern "C" int nmf_server_poll_times(nmf_server *S, uint64_t ticket, int32_t *done, double *times_ms) {
+    if (!S || !done || !times_ms) return fail(NMF_E_INVAL, "server, done and times_ms must be non-NULL");
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end()) return fail(NMF_E_INVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    const Req &R = *it->second;
+    *done = R.state == 2;
+    if (R.state != 2) {
+        for (int i = 0; i < 4; i++) times_ms[i] = NAN;
+        return NMF_OK;
+    }
+    times_ms[0] = (R.t_admit - R.t_submit) * 1e3;
+    times_ms[1] = (R.t_launch - R.t_admit) * 1e3;
+    times_ms[2] = (R.t_done - R.t_launch) * 1e3;
+    times_ms[3] = (R.t_done - R.t_submit) * 1e3;
+    const int st = R.status;
+    const std::string msg = R.msg;
+    S->reqs.erase(it);  // reported done: the record is released
+    return st ? fail(st, "%s", msg.c_str()) : NMF_OK;
 }
 
 extern "C" int nmf_server_wait(nmf_server *S, uint64_t ticket, double *latency_ms) {
@@ -296,7 +456,7 @@ extern "C" int nmf_server_wait(nmf_server *S, uint64_t ticket, double *latency_m
     S->cv_done.wait(lk, [&] { return R->state == 2; });
     if (latency_ms) *latency_ms = (R->t_done - R->t_submit) * 1e3;
     S->reqs.erase(ticket);  // reported done: the record is released
-    return R->status;
+    return R->status ? fail(R->status, "%s", R->msg.c_str()) : NMF_OK;
 }
 
 extern "C" int nmf_server_stats(nmf_server *S, int64_t *completed, int64_t *columns, int64_t *batches) {
@@ -315,6 +475,10 @@ extern "C" void nmf_server_destroy(nmf_server *S) {
         S->stop = true;
     }
     S->cv_work.notify_all();
-    for (auto &t : S->workers) t.join();
+    for (auto &sl : S->slots) {
+        if (sl->launcher.joinable()) sl->launcher.join();
+        if (sl->completer.joinable()) sl->completer.join();
+        if (sl->s) (void)hipStreamDestroy(sl->s);
+    }
     delete S;
 }

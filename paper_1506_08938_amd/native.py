@@ -24,7 +24,7 @@ EXPORTS = [
     "nmf_product",
     "nmf_plan_create", "nmf_plan_run", "nmf_plan_destroy", "nmf_plan_profile", "nmf_plan_timers",
     "nmf_fit", "nmf_fit_streamed", "nmf_objective", "nmf_fit_batched",
-    "nmf_server_create", "nmf_server_submit", "nmf_server_poll", "nmf_server_wait",
+    "nmf_server_create", "nmf_server_submit", "nmf_server_poll", "nmf_server_poll_times", "nmf_server_wait",
     "nmf_server_stats", "nmf_server_destroy",
     "nmf_basis_create", "nmf_foldin", "nmf_basis_destroy", "nmf_foldin_noalloc",
 ]
@@ -141,6 +141,8 @@ def lib():
                                         ctypes.POINTER(ctypes.c_uint64)]
         L.nmf_server_poll.argtypes = [_vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32),
                                       ctypes.POINTER(ctypes.c_double)]
+        L.nmf_server_poll_times.argtypes = [_vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32),
+                                            ctypes.POINTER(ctypes.c_double)]
         L.nmf_server_wait.argtypes = [_vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)]
         L.nmf_server_stats.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64),
                                        ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
@@ -525,6 +527,15 @@ class Server:
         if done.value:
             self.refs.pop(ticket, None)
         return bool(done.value), lat.value
+
+    def poll_times(self, ticket):
+        """(done, (queued_ms, launch_ms, device_ms, latency_ms)) -- the
+        request's timeline once done."""
+        done = ctypes.c_int32(); t = (ctypes.c_double * 4)()
+        check(lib().nmf_server_poll_times(self.h, ticket, ctypes.byref(done), t))
+        if done.value:
+            self.refs.pop(ticket, None)
+        return bool(done.value), tuple(t)
 
     def wait(self, ticket=0):
         lat = ctypes.c_double()
