@@ -526,6 +526,60 @@ def bench_streamed(args, native, synth, torch, np):
     print(json.dumps(out), flush=True)
 
 
+def bench_sparse_accuracy(args, native, synth, torch, np):
+    """The sparse text-like workload: float32 against BF16 products at equal objective accuracy.
+    J* = the FP64 oracle's objective J after --accuracy-iters outer iterations from the same start
+    point (the oracle on the host cores); each GPU mode runs up to three times as many outer
+    iterations, J evaluated in FP64 after each, and reports the iterations and time it needs to
+    reach J <= J* (1 + d) for d = 1e-2, 1e-3, 1e-4 (None: never within the run)."""
+    import oracle
+    wl = synth.workload3()
+    V = wl["V"]
+    m, n = V.shape
+    r = wl["r"]
+    T_or = args.accuracy_iters
+    log(f"[bench] oracle: {T_or} outer iterations of the {m}x{n} sparse workload on {oracle.num_threads()} threads")
+    regs32 = tuple(float(np.float32(x)) for x in wl["reg"])  # the weights the library receives
+    t0 = time.perf_counter()
+    o = oracle.nmf_fit(V, r, regs32, wl["W0"], wl["Ht0"], T=T_or, max_inner=100, eps=1e-3, ls_guard=1,
+                       want_trace=False)
+    t_or = time.perf_counter() - t0
+    Jstar = float(oracle.objective(V, o["W"], o["Ht"], regs32))
+    log(f"[bench] oracle {t_or:.1f}s, J* = {Jstar:.8e}")
+    Vd = native.DeviceMatrix(V, with_transpose=False)
+    reg = native.reg(*wl["reg"])
+    acc = {}
+    for prec, name in ((0, "fp32"), (1, "bf16")):
+        opt = native.opts(max_inner=100, eps=1e-3, precision=prec)
+        ms, _, _, _ = timed_plan(native, torch, Vd, r, reg, opt, torch.from_numpy(wl["W0"]).cuda(),
+                                 torch.from_numpy(wl["Ht0"]).cuda(), 20, 2)
+        plan = native.Plan(Vd, r, reg, opt)
+        W = torch.from_numpy(wl["W0"]).cuda(); Ht = torch.from_numpy(wl["Ht0"]).cuda()
+        Js = []
+        for t in range(3 * T_or):
+            plan.run(W, Ht, 1)
+            Js.append(native.objective(Vd, r, reg, W, Ht)[1])
+        plan.close()
+        reach = {}
+        for d in (1e-2, 1e-3, 1e-4):
+            it = next((i + 1 for i, J in enumerate(Js) if J <= Jstar * (1 + d)), None)
+            reach[f"{d:g}"] = {"iterations": it, "ms": None if it is None else it * ms}
+        acc[name] = {"ms_per_iteration": ms, f"J_at_{T_or}_over_Jstar": Js[T_or - 1] / Jstar,
+                     "J_floor_over_Jstar": min(Js) / Jstar, "reach": reach}
+        log(f"[bench] {name}: J({T_or})/J* = {Js[T_or - 1] / Jstar:.6f}, {ms:.3f} ms/iteration")
+    fp, bf = acc["fp32"], acc["bf16"]
+    out = base_line(
+        "sparse NMF: time to equal objective accuracy, float32 against BF16 products",
+        (m + n) / (bf["ms_per_iteration"] / 1e3), "column NNLS solves/s", 20, 2, bf["ms_per_iteration"], "bf16",
+        {"workload": "sparse text-like CSR V 200000x100000 (0.1% density, Zipf(1.1) columns, log(1+Poisson(3)) "
+                     "values), r=100, L1=0.1 on H, L2=0.01 on W, eps=1e-3; J* = the FP64 oracle's J after "
+                     f"{T_or} outer iterations from the same start; value = the BF16-product mode",
+         "m": m, "n": n, "r": r},
+        equal_accuracy={"Jstar": Jstar, "oracle_iterations": T_or, "oracle_s": t_or,
+                        "oracle_threads": oracle.num_threads(), "modes": acc})
+    print(json.dumps(out), flush=True)
+
+
 def bench_serving(args, native, synth, torch, np):
     """The serving configuration at several offered loads."""
     loads = (0.3, 0.6, 0.9)
@@ -556,7 +610,10 @@ def main():
                     help="server slots (streams; the library caps them at the hardware queues minus one)")
     ap.add_argument("--serve-batch-cols", type=int, default=16384,
                     help="largest fold-in batch (columns) the server forms")
-    ap.add_argument("--workload", default="sparse", choices=["sparse", "dense", "batched", "serving", "streamed"],
+    ap.add_argument("--accuracy-iters", type=int, default=50,
+                    help="--workload sparse_accuracy: outer iterations of the oracle's reference run")
+    ap.add_argument("--workload", default="sparse",
+                    choices=["sparse", "dense", "batched", "serving", "streamed", "sparse_accuracy"],
                     help="sparse: the headline line (default); the others print supplementary lines")
     ap.add_argument("--lanes", type=int, default=0,
                     help="solve layout: lanes per column (0: the tuned table)")
@@ -601,6 +658,8 @@ def main():
         return bench_serving(args, native, synth, torch, np)
     if args.workload == "streamed":
         return bench_streamed(args, native, synth, torch, np)
+    if args.workload == "sparse_accuracy":
+        return bench_sparse_accuracy(args, native, synth, torch, np)
     log("[bench] generating the sparse workload")
     t_gen = time.perf_counter()
     wl = synth.workload3()

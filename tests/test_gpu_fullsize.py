@@ -9,6 +9,7 @@ entries, and Algorithm 3 from the same start point."""
 import numpy as np
 import pytest
 
+import fp32_sensitivity
 import oracle
 from near_ties import near_tied
 from paper_1506_08938_amd import synth
@@ -83,36 +84,63 @@ def one_iteration(full, opts):
     return H(W), H(Ht), (l1w, l2w, l1h, l2h)
 
 
-def check_half(G, P, l1, x0, xg, max_inner, eps, label, tight):
-    """x is compared relative to the distance it moved (from the random start
-    the solutions are small against x0, so |x| itself is no scale), f
-    relative to the decrease achieved.  Fixed-K mode (tight): a column off by
-    more than 1e-4 must have a near-tied greedy choice in the oracle's path
-    (near_ties.py), the others are bounded at max and p99.  Adaptive mode: a
-    column whose stopping test falls on the other side of eps n_0 in float32
-    stops one iteration earlier or later and moves by O(sqrt(eps))."""
+def check_half(G, P, l1, x0, xg, max_inner, eps, label, tight, k_terms):
+    """x is compared relative to max(|x|, the distance it moved) (from the
+    random start the solutions are small against x0), f relative to the
+    decrease achieved.  Each column's tolerance is the larger of the float32
+    solve's floor (1e-4 on x, 1e-9 on the objective gap in fixed-K mode) and
+    twice the oracle's own spread for that column when the half's Gram and
+    product carry float32-sized errors (rounded to float32, and the random-walk
+    model of a k_terms-term float32 sum, two draws): an ill-conditioned half
+    (the dense workload's W-update from the random start has a rescaled Gram
+    of condition number ~1e8) amplifies them far beyond the floor.  Fixed-K
+    mode: a column off by more than its tolerance must have a near-tied greedy
+    choice in the oracle's path (near_ties.py).  Adaptive mode: a column that
+    meets a near-tie, or whose stopping test falls on the other side of
+    eps n_0 in float32, moves by O(sqrt(eps)) with its objective nearly
+    unchanged, so columns are held through their objective gap."""
     h = -P + l1
     xo, ito, cd = oracle.nqp_batch_cdtrace(G, h, x0, max_inner=max_inner, eps=eps,
                                            trace_iters=min(max_inner, 20))
-    e = np.linalg.norm(xg - xo, axis=1) / np.maximum(np.linalg.norm(x0 - xo, axis=1), 1e-30)
-    f0, fg, fo = f_col(G, h, x0), f_col(G, h, xg), f_col(G, h, xo)
-    gap = np.abs(fg - fo) / np.maximum(np.abs(f0 - fo), 1e-30)
+
+    def col_err(x):
+        return np.linalg.norm(x - xo, axis=1) / np.maximum(
+            np.maximum(np.linalg.norm(xo, axis=1), np.linalg.norm(x0 - xo, axis=1)), 1e-30)
+
+    f0, fo = f_col(G, h, x0), f_col(G, h, xo)
+
+    def col_gap(x):
+        return np.abs(f_col(G, h, x) - fo) / np.maximum(np.abs(f0 - fo), 1e-30)
+
+    e, gap = col_err(xg), col_gap(xg)
+    # the oracle's own spread under float32-sized errors of G and P
+    sx, sg = np.zeros_like(e), np.zeros_like(gap)
+    g = np.random.default_rng(77)
+    for mode in ("round", "jitter", "jitter"):
+        if mode == "round":
+            G2, P2 = fp32_sensitivity._round32(G), fp32_sensitivity._round32(P)
+        else:
+            G2, P2 = fp32_sensitivity._jitter(G, k_terms, g), fp32_sensitivity._jitter(P, k_terms, g)
+        x2, _ = oracle.nqp_batch(G2, -P2 + l1, x0, max_inner=max_inner, eps=eps)
+        sx, sg = np.maximum(sx, col_err(x2)), np.maximum(sg, col_gap(x2))
     tie = near_tied(cd)
-    clean = ~tie
-    print(f"{label}: x error / distance moved median {np.median(e):.2e} p99 {np.quantile(e, .99):.2e} "
-          f"max {e.max():.2e}; f gap / decrease median {np.median(gap):.2e} p99 {np.quantile(gap, .99):.2e} "
-          f"max {gap.max():.2e}; oracle iterations mean {ito.mean():.2f}; near-tied {tie.mean():.3f}, "
-          f"without a near-tie x max {e[clean].max() if clean.any() else 0:.2e}")
-    # measured on MI355X (float32 and BF16 products): fixed K = 20, x p99
-    # 2.8e-5 .. 4.9e-5, max 6.5e-5, gap p99 <= 1.8e-11; adaptive, x p99
-    # 3.8e-5 .. 8.1e-5, max 1.2e-3 (an iteration-count flip), gap p99 3.5e-8
+    tol_x = np.maximum(1e-4, 2 * sx)
+    print(f"{label}: x error median {np.median(e):.2e} p99 {np.quantile(e, .99):.2e} max {e.max():.2e} "
+          f"(oracle spread median {np.median(sx):.2e} max {sx.max():.2e}); f gap / decrease median "
+          f"{np.median(gap):.2e} p99 {np.quantile(gap, .99):.2e} max {gap.max():.2e} (spread max {sg.max():.2e}); "
+          f"oracle iterations mean {ito.mean():.2f}; near-tied {tie.mean():.3f}; over tolerance "
+          f"{np.sum(e > tol_x)}")
     if tight:
-        assert not ((e > 1e-4) & clean).any()
-        assert np.median(e) < 3e-5 and np.quantile(e, 0.99) < 1e-4 and e.max() < 2e-4
-        assert np.quantile(gap, 0.99) < 1e-10 and gap.max() < 1e-9
+        assert not ((e > tol_x) & ~tie).any()
+        assert np.median(e) < np.median(tol_x)
+        # the objective gap's distribution against the spread's (a column's own
+        # spread, from three draws, is too noisy to compare column by column)
+        for q in (0.5, 0.99, 1.0):
+            assert np.quantile(gap, q) <= max(1e-9, 2 * np.quantile(sg, q)), q
     else:
-        assert np.median(e) < 3e-5 and np.quantile(e, 0.99) < 2e-4
-        assert np.quantile(gap, 0.99) < 1e-6 and gap.max() < 1e-5
+        assert np.median(e) < np.median(tol_x)
+        assert np.quantile(gap, 0.99) < max(1e-6, 2 * np.quantile(sg, 0.99))
+        assert gap.max() < max(1e-5, 2 * sg.max())
     return ito
 
 
@@ -131,12 +159,12 @@ def test_fullsize_outer_iteration_on_sampled_columns_and_rows(full, mode):
     Gw = oracle.gram(W0, l2h)
     Pc = rows_product(Vt, cols, W0)
     check_half(Gw, Pc, l1h, Ht0[cols], Hg[cols], opts["max_inner"], opts["eps"],
-               f"full size {mode} H-update, {NSAMPLE} columns", mode == "fixed")
+               f"full size {mode} H-update, {NSAMPLE} columns", mode == "fixed", m)
     # W-update: Gram of the new Ht (the GPU's), the sampled rows' products V(i, :) Ht
     Gh = oracle.gram(Hg, l2w)
     Pr = rows_product(V, rows, Hg)
     check_half(Gh, Pr, l1w, W0[rows], Wg[rows], opts["max_inner"], opts["eps"],
-               f"full size {mode} W-update, {NSAMPLE} rows", mode == "fixed")
+               f"full size {mode} W-update, {NSAMPLE} rows", mode == "fixed", n)
     assert (Wg >= 0).all() and (Hg >= 0).all() and np.isfinite(Wg).all() and np.isfinite(Hg).all()
 
 
@@ -174,9 +202,94 @@ def test_fullsize_bf16_outer_iteration_on_sampled_columns_and_rows(full):
     Ht0 = wl["Ht0"].astype(np.float64)
     Gw = oracle.gram(bf16_round(wl["W0"]), l2h)
     Pc = rows_product_bf16(Vt, cols, wl["W0"], hot)
-    check_half(Gw, Pc, l1h, Ht0[cols], Hg[cols], 20, 0.0, f"full size bf16 H-update, {NSAMPLE} columns", True)
+    check_half(Gw, Pc, l1h, Ht0[cols], Hg[cols], 20, 0.0, f"full size bf16 H-update, {NSAMPLE} columns", True, m)
     Hg32 = Hg.astype(np.float32)
     Gh = oracle.gram(bf16_round(Hg32), l2w)
     Pr = rows_product_bf16(V, rows, Hg32, set())
-    check_half(Gh, Pr, l1w, W0[rows], Wg[rows], 20, 0.0, f"full size bf16 W-update, {NSAMPLE} rows", True)
+    check_half(Gh, Pr, l1w, W0[rows], Wg[rows], 20, 0.0, f"full size bf16 W-update, {NSAMPLE} rows", True, n)
     assert (Wg >= 0).all() and (Hg >= 0).all() and np.isfinite(Wg).all() and np.isfinite(Hg).all()
+
+
+# --------------------------------------------------------------------------- dense, full size
+# The large dense workload (V 20000 x 10000 = Gamma-factor rank-64 data +
+# |N(0, 0.05)|, r = 64, L2 = 0.01 on both factors) in the launch configuration
+# the dense benchmark times: one outer iteration of a plan over the whole
+# matrix (its split-K count and tile grid are those of this size), sampled
+# columns of Ht and rows of W recomputed by the oracle one by one.  BF16
+# products: the oracle is fed the values the GPU rounds (V, and the fixed
+# factor in the Gram and the product).
+@pytest.fixture(scope="module")
+def dense_full():
+    from paper_1506_08938_amd import native as nat
+    wl = synth.workload2()
+    return dict(wl=wl, dev=nat.DeviceMatrix(T(wl["V"])))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("mode", ["fixed", "bench"])
+def test_fullsize_dense_outer_iteration_on_sampled_columns_and_rows(dense_full, precision, mode):
+    from paper_1506_08938_amd import native as nat
+    wl = dense_full["wl"]
+    V = wl["V"]
+    m, n = V.shape
+    r = wl["r"]
+    opts = dict(max_inner=20, eps=0.0) if mode == "fixed" else dict(max_inner=100, eps=1e-3)
+    l1w, l2w, l1h, l2h = (float(np.float32(x)) for x in wl["reg"])
+    plan = nat.Plan(dense_full["dev"], r, nat.reg(*wl["reg"]), nat.opts(precision=precision, **opts))
+    Wd, Hd = T(wl["W0"]), T(wl["Ht0"])
+    plan.run(Wd, Hd, 1)
+    plan.close()
+    Wg, Hg = H(Wd), H(Hd)
+    g = np.random.default_rng(2026 + precision)
+    cols = np.sort(g.choice(n, NSAMPLE, replace=False))
+    rows = np.sort(g.choice(m, NSAMPLE, replace=False))
+    rnd = bf16_round if precision else (lambda a: np.asarray(a, dtype=np.float32))
+    W0 = wl["W0"]
+    # H-update: Gram of the start W, the sampled columns' products V(:, j)' W
+    Wr = rnd(W0).astype(np.float64)
+    Gw = oracle.gram(Wr, l2h)
+    Pc = rnd(V[:, cols]).astype(np.float64).T @ Wr
+    check_half(Gw, Pc, l1h, wl["Ht0"][cols].astype(np.float64), Hg[cols], opts["max_inner"], opts["eps"],
+               f"dense full size {'bf16' if precision else 'fp32'} {mode} H-update, {NSAMPLE} columns",
+               mode == "fixed", m)
+    # W-update: Gram of the GPU's new Ht, the sampled rows' products V(i, :) Ht
+    Hr = rnd(Hg.astype(np.float32)).astype(np.float64)
+    Gh = oracle.gram(Hr, l2w)
+    Pr = rnd(V[rows]).astype(np.float64) @ Hr
+    check_half(Gh, Pr, l1w, W0[rows].astype(np.float64), Wg[rows], opts["max_inner"], opts["eps"],
+               f"dense full size {'bf16' if precision else 'fp32'} {mode} W-update, {NSAMPLE} rows",
+               mode == "fixed", n)
+    assert (Wg >= 0).all() and (Hg >= 0).all() and np.isfinite(Wg).all() and np.isfinite(Hg).all()
+
+
+# --------------------------------------------------------------------------- fold-in, full size
+# The serving workload's basis shape: W 100000 x 128 (Gamma(2, 0.5)), a
+# request of 3000 sparse columns with 500 stored entries each (0.5%), values
+# log(1 + Poisson(3)), L1 = 0.05, cold start, eps = 1e-3 -- the fold-in layout
+# and launch the server uses.  Every column is recomputed by the oracle.
+@pytest.mark.parametrize("precision", [0, 1])
+def test_fullsize_foldin_against_resident_basis(precision):
+    import torch
+    from paper_1506_08938_amd import native as nat
+    m, r, c, l1 = 100000, 128, 3000, 0.05
+    W = np.random.default_rng(5005).gamma(2.0, 0.5, (m, r)).astype(np.float32)
+    B = nat.Basis(T(W), l1=l1, l2=0.0, opt=nat.opts(max_inner=100, eps=1e-3, precision=precision))
+    req = synth.foldin_columns_many(m, c, 500, seed=5006)
+    it = torch.zeros(c, dtype=torch.int32, device="cuda")
+    out = H(B.foldin(nat.sparse_request(req, m), iters=it))
+    B.close()
+    Wr = bf16_round(W) if precision else W
+    G = oracle.gram(Wr, 0.0).astype(np.float32)
+    P = oracle.product_csr(req, Wr, 1)
+    xo, ito, cd = oracle.nqp_batch_cdtrace(G, (-P + np.float32(l1)).astype(np.float32), np.zeros((c, r)),
+                                           max_inner=100, eps=1e-3, trace_iters=5)
+    e = np.linalg.norm(out - xo, axis=1) / np.maximum(np.linalg.norm(xo, axis=1), 1e-30)
+    tie = near_tied(cd) | (ito > 5)
+    itg = H(it)
+    print(f"fold-in 100000x128 {'bf16' if precision else 'fp32'}: x rel median {np.median(e):.2e} "
+          f"p99 {np.quantile(e, .99):.2e} max {e.max():.2e}; iterations agree {np.mean(itg == ito):.4f} "
+          f"(mean gpu {itg.mean():.3f} oracle {ito.mean():.3f}); near-tied {tie.mean():.3f}, without x max "
+          f"{e[~tie].max() if (~tie).any() else 0:.2e}")
+    assert np.median(e) < 1e-5 and np.quantile(e, 0.99) < 1e-4
+    assert not ((e > 1e-4) & ~tie & (itg == ito)).any()
+    assert np.mean(itg == ito) > 0.98
