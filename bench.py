@@ -580,6 +580,46 @@ def bench_sparse_accuracy(args, native, synth, torch, np):
     print(json.dumps(out), flush=True)
 
 
+def bench_single_pass(args, native, synth, torch, np):
+    """Algorithm 2's single pass over a V resident in HBM (nmf_fit_single_pass: the M-step's data
+    term summed over instance panels while the E-step solves them, V read from memory once per
+    outer iteration) against the two-pass resident fit (nmf_plan_run: V read once per half), on
+    the dense workload in FP32."""
+    K, Wm = args.steps, args.warmup
+    panel = args.panel_cols
+    log("[bench] generating the dense workload")
+    wl = synth.workload2()
+    m, n = wl["V"].shape
+    r = wl["r"]
+    Vd = native.DeviceMatrix(torch.from_numpy(wl["V"]).cuda())
+    reg = native.reg(*wl["reg"])
+    W0 = torch.from_numpy(wl["W0"]).cuda(); H0 = torch.from_numpy(wl["Ht0"]).cuda()
+    opt = native.opts(max_inner=100, eps=1e-3)
+    two_ms, ph, _, st2 = timed_plan(native, torch, Vd, r, reg, opt, W0, H0, K, Wm)
+    W = W0.clone(); Ht = H0.clone()
+    if Wm:
+        native.fit_single_pass(Vd, r, reg, native.opts(max_outer=Wm, max_inner=100, eps=1e-3), W, Ht, panel,
+                               want_trace=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st = native.fit_single_pass(Vd, r, reg, native.opts(max_outer=K, max_inner=100, eps=1e-3), W, Ht, panel,
+                                   want_trace=False)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / K
+    log(f"[bench] single pass {ms:.3f} ms/step (panels of {panel}), two-pass {two_ms:.3f} ms/step")
+    out = base_line(
+        "dense NMF, single pass over resident V: column NNLS solves/s",
+        (m + n) / (ms / 1e3), "column NNLS solves/s", K, Wm, ms, "f32",
+        {"workload": "dense V 20000x10000 = W0 H0 + |N(0,0.05)|, Gamma(2,0.5) factors of inner dimension 64, "
+                     "FP32 resident in HBM; r=64, L2=0.01 on W and H; eps=1e-3, max_inner=100; "
+                     f"panels of {panel} instances; one step = one outer iteration (V read once); the run's "
+                     "statistics add one more read", "m": m, "n": n, "r": r, "panel_cols": panel},
+        two_pass_ms_per_step=two_ms, two_pass_phases_ms=ph, V_bytes=4 * m * n,
+        hbm_floor_ms_single=4 * m * n / 8e12 * 1e3, hbm_floor_ms_two_pass=2 * 4 * m * n / 8e12 * 1e3,
+        kbar=st["kbar"], kbar_two_pass=st2["kbar"], loss_after=st["loss"], loss_after_two_pass=st2["loss"])
+    print(json.dumps(out), flush=True)
+
+
 def bench_serving(args, native, synth, torch, np):
     """The serving configuration at several offered loads."""
     loads = (0.3, 0.6, 0.9)
@@ -613,7 +653,8 @@ def main():
     ap.add_argument("--accuracy-iters", type=int, default=50,
                     help="--workload sparse_accuracy: outer iterations of the oracle's reference run")
     ap.add_argument("--workload", default="sparse",
-                    choices=["sparse", "dense", "batched", "serving", "streamed", "sparse_accuracy"],
+                    choices=["sparse", "dense", "batched", "serving", "streamed", "sparse_accuracy",
+                             "single_pass"],
                     help="sparse: the headline line (default); the others print supplementary lines")
     ap.add_argument("--lanes", type=int, default=0,
                     help="solve layout: lanes per column (0: the tuned table)")
@@ -660,6 +701,8 @@ def main():
         return bench_streamed(args, native, synth, torch, np)
     if args.workload == "sparse_accuracy":
         return bench_sparse_accuracy(args, native, synth, torch, np)
+    if args.workload == "single_pass":
+        return bench_single_pass(args, native, synth, torch, np)
     log("[bench] generating the sparse workload")
     t_gen = time.perf_counter()
     wl = synth.workload3()

@@ -249,6 +249,22 @@ NMF_API int nmf_fit_streamed(const float *V_host, int64_t m, int64_t n, int64_t 
                              const nmf_reg *reg, const nmf_opts *opt, int64_t panel_cols, float *W,
                              float *Ht, double *trace, nmf_stats *stats, void *stream);
 
+/* Algorithm 2's single pass over a V resident in device memory (dense,
+ * float32, any leading dimension): the loop of Section 3.3 that forms the
+ * M-step's data term as the sum over instance panels J of V_J Ht_J while the
+ * E-step solves those panels, so that each outer iteration reads V from
+ * memory once (the panel's second read, for its share of V Ht right after
+ * its E-step product, comes from cache) instead of once per half.  Same
+ * iteration as nmf_fit and nmf_fit_streamed (H-update, then the W-update
+ * from the new H; results agree with nmf_fit to float32 rounding, the
+ * products' sums being grouped by panel); the panels' E-step solves are
+ * launches of panel_cols columns.  Arguments and outputs as nmf_fit_streamed,
+ * V given as an nmf_matrix (kind NMF_DENSE, device pointer).  opt->precision
+ * must be NMF_FP32.  Synchronises `stream` before returning. */
+NMF_API int nmf_fit_single_pass(const nmf_matrix *V, int32_t r, const nmf_reg *reg, const nmf_opts *opt,
+                                int64_t panel_cols, float *W, float *Ht, double *trace, nmf_stats *stats,
+                                void *stream);
+
 /* Loss and objective of (V, W, Ht) in double precision (host outputs). */
 NMF_API int nmf_objective(const nmf_matrix *V, int32_t r, const nmf_reg *reg, const float *W,
                   const float *Ht, double *loss_host, double *objective_host, void *stream);

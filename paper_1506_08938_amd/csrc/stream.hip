@@ -1,6 +1,9 @@
 // Limited-internal-memory fit (Section 3.3, Algorithm 2; the memory row of
 // Table 1).  V stays in host memory and every outer iteration reads it once,
-// one panel of instances (columns of V) at a time.  For a panel J the E-step
+// one panel of instances (columns of V) at a time.  The same single pass
+// over a V already in device memory (nmf_fit_single_pass) takes each panel as
+// a view of V: a panel's E-step product and its share of the M-step's product
+// read the same m x panel block back to back, the second time from cache.  For a panel J the E-step
 // solves the panel's columns of H against Q = W'W + 2 l2_h I, then adds the
 // panel's share of the M-step's product, V_J Ht_J (the paper's sum of
 // F_i V_i'), to P_W in panel order.  The M-step needs no V: its Gram
@@ -50,8 +53,10 @@ struct Streamer {
     float *buf[2] = {nullptr, nullptr};
     char *ws = nullptr;
 
-    const float *Vh = nullptr;
+    const float *Vh = nullptr;   // host V, or device V when resident
+    bool resident = false;       // V in device memory: panels are views into it, no copies
     int64_t m = 0, n = 0, ld = 0, pc = 0, ldp = 0, np = 0;
+    int64_t vld = 0;             // leading dimension of a panel as the kernels read it
     int r = 0;
     nmf_reg reg{};
     nmf_opts opt{};
@@ -82,6 +87,11 @@ struct Streamer {
     // copy of panel p waits until the work on panel p - 2 (same buffer) is done.
     template <class F>
     int for_each_panel(F body) {
+        if (resident) {
+            for (int64_t p = 0; p < np; p++)
+                if (int st = body(p, p * pc, cols_of(p), Vh + p * pc)) return st;
+            return NMF_OK;
+        }
         for (int64_t p = 0; p < np; p++) {
             const int b = (int)(p & 1);
             const int64_t j0 = p * pc, cols = cols_of(p);
@@ -117,6 +127,12 @@ struct Streamer {
 
 }  // namespace nmfi
 
+namespace nmfi {
+namespace {
+int run_panels(Streamer &S, float *W, float *Ht, double *trace, nmf_stats *stats);
+}  // namespace
+}  // namespace nmfi
+
 using namespace nmfi;
 
 extern "C" int nmf_fit_streamed(const float *V_host, int64_t m, int64_t n, int64_t ld, int32_t r,
@@ -143,7 +159,20 @@ extern "C" int nmf_fit_streamed(const float *V_host, int64_t m, int64_t n, int64
     S.Vh = V_host; S.m = m; S.n = n; S.ld = ld; S.r = r; S.reg = *reg; S.opt = *opt;
     S.pc = std::min(panel_cols, n);
     S.ldp = (S.pc + 3) / 4 * 4;  // 16-byte rows for the product's vector loads
+    S.vld = S.ldp;
     S.np = (n + S.pc - 1) / S.pc;
+    return run_panels(S, W, Ht, trace, stats);
+}
+
+namespace nmfi {
+namespace {
+// The outer iterations over the panels of S (set up by the caller), shared
+// by the host-memory and the resident single-pass fits.
+int run_panels(Streamer &S, float *W, float *Ht, double *trace, nmf_stats *stats) {
+    const int64_t m = S.m, n = S.n;
+    const int r = S.r;
+    const nmf_opts *opt = &S.opt;
+    const nmf_reg *reg = &S.reg;
     const int T = opt->max_outer;
     if (opt->check_finite) {
         if (int st = check_values(W, m * r, 1, S.s)) return st;
@@ -174,16 +203,18 @@ extern "C" int nmf_fit_streamed(const float *V_host, int64_t m, int64_t n, int64
     S.loss_slots = (double *)(w + o_lsl); S.kkt_slots = (double *)(w + o_ksl); S.kkt_partial = (double *)(w + o_kp);
     S.obj = (double *)(w + o_obj); S.kkt_out = (double *)(w + o_ko); S.obj_scratch = w + o_os;
     S.counter = (unsigned long long *)(w + o_ctr); S.inner_total = S.counter + 1;
-    // panel buffers: the padding columns stay zero (copies write cols of ldp)
-    for (int b = 0; b < 2; b++) {
-        NMF_HIP(hipMalloc((void **)&S.buf[b], (size_t)m * S.ldp * sizeof(float)));
-        NMF_HIP(hipMemsetAsync(S.buf[b], 0, (size_t)m * S.ldp * sizeof(float), S.s));
-    }
-    NMF_HIP(hipStreamCreateWithFlags(&S.cs, hipStreamNonBlocking));
-    for (int b = 0; b < 2; b++) {
-        NMF_HIP(hipEventCreateWithFlags(&S.copied[b], hipEventDisableTiming));
-        NMF_HIP(hipEventCreateWithFlags(&S.freed[b], hipEventDisableTiming));
-        NMF_HIP(hipEventRecord(S.freed[b], S.s));
+    if (!S.resident) {
+        // panel buffers: the padding columns stay zero (copies write cols of ldp)
+        for (int b = 0; b < 2; b++) {
+            NMF_HIP(hipMalloc((void **)&S.buf[b], (size_t)m * S.ldp * sizeof(float)));
+            NMF_HIP(hipMemsetAsync(S.buf[b], 0, (size_t)m * S.ldp * sizeof(float), S.s));
+        }
+        NMF_HIP(hipStreamCreateWithFlags(&S.cs, hipStreamNonBlocking));
+        for (int b = 0; b < 2; b++) {
+            NMF_HIP(hipEventCreateWithFlags(&S.copied[b], hipEventDisableTiming));
+            NMF_HIP(hipEventCreateWithFlags(&S.freed[b], hipEventDisableTiming));
+            NMF_HIP(hipEventRecord(S.freed[b], S.s));
+        }
     }
     NMF_HIP(launch_zero_u64(S.inner_total, 1, S.s));
 
@@ -195,7 +226,7 @@ extern "C" int nmf_fit_streamed(const float *V_host, int64_t m, int64_t n, int64
         return stats != nullptr && t == T;
     };
     auto panel_loss = [&](int64_t p, int64_t j0, int64_t cols, const float *VJ) {
-        return launch_loss_panel(VJ, S.ldp, m, cols, W, Ht + j0 * r, r, S.loss_scratch, S.loss_slots + p, S.s);
+        return launch_loss_panel(VJ, S.vld, m, cols, W, Ht + j0 * r, r, S.loss_scratch, S.loss_slots + p, S.s);
     };
 
     // ---------------------------------------------------------------- outer iterations
@@ -208,18 +239,18 @@ extern "C" int nmf_fit_streamed(const float *V_host, int64_t m, int64_t n, int64
         NMF_HIP(hipGetLastError());
         int st = S.for_each_panel([&](int64_t p, int64_t j0, int64_t cols, const float *VJ) -> int {
             float *HJ = Ht + j0 * r;
-            if (t == 1 && opt->check_finite) {
+            if (t == 1 && opt->check_finite && !S.resident) {
                 if (int st = check_values(VJ, m * S.ldp, 1, S.s)) return st;
             }
             if (obj_prev) NMF_HIP(panel_loss(p, j0, cols, VJ));
             // E-step: P_J = (W' V_J)', then the panel's NQPs
-            NMF_HIP(launch_dense_product(VJ, 0, m, cols, S.ldp, nullptr, 0, W, r, S.PJ, S.dense_scratch, S.s));
+            NMF_HIP(launch_dense_product(VJ, 0, m, cols, S.vld, nullptr, 0, W, r, S.PJ, S.dense_scratch, S.s));
             NMF_HIP(S.solve(S.GW, S.PJ, reg->l1_h, HJ, cols, true));
             if (stats && last)
                 NMF_HIP(launch_kkt(S.GW, r, S.PJ, -1.f, reg->l1_h, HJ, cols, S.kkt_partial, S.kkt_slots + p,
                                    S.np, S.s));
             // the M-step's product: P_W += V_J Ht_J
-            NMF_HIP(launch_dense_product(VJ, 0, m, cols, S.ldp, nullptr, 1, HJ, r, S.Ptmp, S.dense_scratch, S.s));
+            NMF_HIP(launch_dense_product(VJ, 0, m, cols, S.vld, nullptr, 1, HJ, r, S.Ptmp, S.dense_scratch, S.s));
             hipLaunchKernelGGL(k_add_f32, dim3(grid_for(m * r)), dim3(256), 0, S.s, S.PW, S.Ptmp, m * r);
             NMF_HIP(hipGetLastError());
             return NMF_OK;
@@ -267,4 +298,49 @@ extern "C" int nmf_fit_streamed(const float *V_host, int64_t m, int64_t n, int64
         stats->kbar = T > 0 ? (double)inner / ((double)T * (double)(m + n)) : 0.0;
     }
     return NMF_OK;
+}
+}  // namespace
+}  // namespace nmfi
+
+
+extern "C" int nmf_fit_single_pass(const nmf_matrix *V, int32_t r, const nmf_reg *reg, const nmf_opts *opt,
+                                   int64_t panel_cols, float *W, float *Ht, double *trace, nmf_stats *stats,
+                                   void *stream) {
+    if (!V) return fail(NMF_E_INVAL, "V is NULL");
+    if (V->kind != NMF_DENSE) return fail(NMF_E_UNSUPPORTED, "the single-pass fit takes dense V");
+    if (!V->dense) return fail(NMF_E_INVAL, "V->dense is NULL");
+    const int64_t m = V->rows, n = V->cols, ld = V->ld;
+    if (m < 1 || n < 1) return fail(NMF_E_INVAL, "V must be non-empty (m = %lld, n = %lld)", (long long)m, (long long)n);
+    if (ld < n) return fail(NMF_E_INVAL, "ld (%lld) must be >= n (%lld)", (long long)ld, (long long)n);
+    if (r < 1 || r > NMF_MAX_RANK) return fail(NMF_E_INVAL, "r must be in [1, %d] (got %d)", NMF_MAX_RANK, r);
+    if (!reg) return fail(NMF_E_INVAL, "reg is NULL");
+    if (int st = validate_opts(opt)) return st;
+    if (opt->precision != NMF_FP32)
+        return fail(NMF_E_UNSUPPORTED, "the single-pass fit computes its products in FP32 only");
+    const float regs[4] = {reg->l1_w, reg->l2_w, reg->l1_h, reg->l2_h};
+    for (float v : regs)
+        if (!(v >= 0.f) || !std::isfinite(v)) return fail(NMF_E_INVAL, "regularisation weights must be finite and >= 0");
+    if (opt->max_outer < 0) return fail(NMF_E_INVAL, "max_outer must be >= 0");
+    if (panel_cols < 1) return fail(NMF_E_INVAL, "panel_cols must be >= 1 (got %lld)", (long long)panel_cols);
+    if (!W || !Ht) return fail(NMF_E_INVAL, "W and Ht must be non-NULL");
+    if (!nqp_pick(r, 1, opt->lanes).E) return fail(NMF_E_INVAL, "lanes = %d cannot hold rank %d", opt->lanes, r);
+    hipStream_t s = (hipStream_t)stream;
+    if (opt->check_finite) {
+        int st = NMF_OK;
+        if (ld != n) {
+            for (int64_t i = 0; i < m && !st; i++) st = check_values(V->dense + i * ld, n, 1, s);
+        } else {
+            st = check_values(V->dense, m * n, 1, s);
+        }
+        if (st) return st;
+    }
+    Streamer S;
+    S.s = s;
+    S.resident = true;
+    S.Vh = V->dense; S.m = m; S.n = n; S.ld = ld; S.r = r; S.reg = *reg; S.opt = *opt;
+    S.pc = std::min(panel_cols, n);
+    S.ldp = (S.pc + 3) / 4 * 4;
+    S.vld = ld;  // panels are column ranges of V itself
+    S.np = (n + S.pc - 1) / S.pc;
+    return run_panels(S, W, Ht, trace, stats);
 }

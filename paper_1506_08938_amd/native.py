@@ -23,7 +23,7 @@ EXPORTS = [
     "nmf_default_opts", "nmf_last_error", "nnls_solve_batch", "nnls_layout", "nmf_gram",
     "nmf_product",
     "nmf_plan_create", "nmf_plan_run", "nmf_plan_destroy", "nmf_plan_profile", "nmf_plan_timers",
-    "nmf_fit", "nmf_fit_streamed", "nmf_objective", "nmf_fit_batched",
+    "nmf_fit", "nmf_fit_streamed", "nmf_fit_single_pass", "nmf_objective", "nmf_fit_batched",
     "nmf_server_create", "nmf_server_submit", "nmf_server_poll", "nmf_server_poll_times", "nmf_server_wait",
     "nmf_server_stats", "nmf_server_destroy",
     "nmf_basis_create", "nmf_foldin", "nmf_basis_destroy", "nmf_foldin_noalloc",
@@ -130,6 +130,9 @@ def lib():
         L.nmf_fit_streamed.argtypes = [_vp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
                                        ctypes.POINTER(NmfReg), ctypes.POINTER(NmfOpts), ctypes.c_int64,
                                        _vp, _vp, _vp, ctypes.POINTER(NmfStats), _vp]
+        L.nmf_fit_single_pass.argtypes = [ctypes.POINTER(NmfMatrix), ctypes.c_int32, ctypes.POINTER(NmfReg),
+                                          ctypes.POINTER(NmfOpts), ctypes.c_int64, _vp, _vp, _vp,
+                                          ctypes.POINTER(NmfStats), _vp]
         L.nmf_objective.argtypes = [ctypes.POINTER(NmfMatrix), ctypes.c_int32,
                                     ctypes.POINTER(NmfReg), _vp, _vp, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_double), _vp]
@@ -363,6 +366,22 @@ def fit(V: DeviceMatrix, r, regw: NmfReg, opt: NmfOpts, W, Ht, want_trace=True):
     check(lib().nmf_fit(ctypes.byref(V.m), r, ctypes.byref(regw), ctypes.byref(opt), _ptr(W),
                         _ptr(Ht), None if trace is None else trace.ctypes.data, ctypes.byref(st),
                         stream_ptr()))
+    return trace, st.as_dict()
+
+
+def fit_single_pass(V: DeviceMatrix, r, regw: NmfReg, opt: NmfOpts, W, Ht, panel_cols, want_trace=True):
+    """nmf_fit_single_pass: dense V on the device (a DeviceMatrix), W (m, r)
+    and Ht (n, r) device tensors, updated in place."""
+    import numpy as np
+    torch = _torch()
+    m, n = V.shape
+    _dev(W, torch.float32, "W", (m, r))
+    _dev(Ht, torch.float32, "Ht", (n, r))
+    trace = np.full(opt.max_outer + 1, np.nan) if want_trace else None
+    st = NmfStats()
+    check(lib().nmf_fit_single_pass(ctypes.byref(V.m), r, ctypes.byref(regw), ctypes.byref(opt), int(panel_cols),
+                                    _ptr(W), _ptr(Ht), None if trace is None else trace.ctypes.data,
+                                    ctypes.byref(st), stream_ptr()))
     return trace, st.as_dict()
 
 
