@@ -1,7 +1,6 @@
 // Host orchestration: the building-block entry points, the fit plan
 // (Algorithm 2 with the regularised NQPs of Section 3.5), the objective, and
 // fold-in against a resident basis (the E-step alone).
-#include <hipcub/hipcub.hpp>
 #include <math.h>
 
 #include <vector>
@@ -37,65 +36,118 @@ int validate_matrix(const nmf_matrix *V, bool need_transpose_ok) {
 }
 
 // ------------------------------------------------------------------ CSR transpose
-__global__ void k_expand_rows(const int32_t *__restrict__ rowptr, int64_t m, int32_t *__restrict__ rowid) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
-        for (int32_t t = rowptr[i]; t < rowptr[i + 1]; t++) rowid[t] = (int32_t)i;
-}
-__global__ void k_iota(int32_t *__restrict__ x, int64_t n) {
+// CSR(V') from CSR(V) by a counting sort on the column index that keeps the
+// rows ascending inside each column (what the products' fixed summation order
+// relies on).  The rows are cut into B contiguous blocks; block b counts its
+// entries per column, an exclusive scan over the blocks and the columns gives
+// every (block, column) its first output position, and then block b places
+// its rows one after another (a barrier between rows), each column's cursor
+// advanced by atomics: within a column, lower blocks come first and inside a
+// block lower rows come first.
+
+__global__ void k_zero_i32(int32_t *__restrict__ p, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        x[i] = (int32_t)i;
+        p[i] = 0;
 }
-__global__ void k_permute(const int32_t *__restrict__ perm, const int32_t *__restrict__ rowid,
-                          const float *__restrict__ vals, int64_t n, int32_t *__restrict__ tcol,
-                          float *__restrict__ tval) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t p = perm[i];
-        tcol[i] = rowid[p];
-        tval[i] = vals[p];
-    }
+
+// cnt[b * n + j] = entries of column j in rows [b * rows_per, (b + 1) * rows_per)
+__global__ __launch_bounds__(256) void k_tr_count(const int32_t *__restrict__ rowptr, int64_t m,
+                                                  const int32_t *__restrict__ colidx, int64_t rows_per, int64_t n,
+                                                  int32_t *__restrict__ cnt) {
+    const int64_t i0 = (int64_t)blockIdx.x * rows_per, i1 = min(m, i0 + rows_per);
+    int32_t *c = cnt + (int64_t)blockIdx.x * n;
+    if (i0 >= i1) return;
+    for (int64_t t = rowptr[i0] + threadIdx.x; t < rowptr[i1]; t += blockDim.x) atomicAdd(&c[colidx[t]], 1);
 }
-// t_rowptr[j] = first position whose (sorted) column is >= j
-__global__ void k_col_bounds(const int32_t *__restrict__ keys, int64_t nnz, int64_t n,
-                             int32_t *__restrict__ trp) {
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j <= n; j += (int64_t)gridDim.x * blockDim.x) {
-        int64_t lo = 0, hi = nnz;
-        while (lo < hi) {
-            const int64_t mid = (lo + hi) >> 1;
-            if (keys[mid] < j) lo = mid + 1; else hi = mid;
+
+// Per column j: cnt[b][j] <- sum over earlier blocks (the block's offset
+// inside column j), colcnt[j] <- the column's total.
+__global__ void k_tr_block_offsets(int32_t *__restrict__ cnt, int64_t nb, int64_t n, int32_t *__restrict__ colcnt) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+        int32_t run = 0;
+        for (int64_t b = 0; b < nb; b++) {
+            const int32_t v = cnt[b * n + j];
+            cnt[b * n + j] = run;
+            run += v;
         }
-        trp[j] = (int32_t)lo;
+        colcnt[j] = run;
     }
 }
 
-// CSR(V') from CSR(V) with a stable radix sort by column (rows stay ascending
-// inside each column).  Outputs are hipMalloc'd and owned by the caller.
+// out[0] = 0, out[j + 1] = in[0] + ... + in[j]: one block walks the array in
+// chunks of 1024, scanning each in LDS and carrying the running total.
+__global__ __launch_bounds__(1024) void k_tr_exclusive_scan(const int32_t *__restrict__ in, int64_t n,
+                                                            int32_t *__restrict__ out) {
+    __shared__ int32_t buf[1024];
+    __shared__ int32_t carry;
+    if (threadIdx.x == 0) { carry = 0; out[0] = 0; }
+    __syncthreads();
+    for (int64_t base = 0; base < n; base += 1024) {
+        const int64_t j = base + threadIdx.x;
+        buf[threadIdx.x] = j < n ? in[j] : 0;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {  // inclusive scan (Hillis-Steele)
+            const int32_t v = threadIdx.x >= (unsigned)off ? buf[threadIdx.x - off] : 0;
+            __syncthreads();
+            buf[threadIdx.x] += v;
+            __syncthreads();
+        }
+        if (j < n) out[j + 1] = carry + buf[threadIdx.x];
+        __syncthreads();
+        if (threadIdx.x == 1023) carry += buf[1023];
+        __syncthreads();
+    }
+}
+
+// Block b places the entries of its rows, row after row.
+__global__ __launch_bounds__(256) void k_tr_scatter(const int32_t *__restrict__ rowptr, int64_t m,
+                                                    const int32_t *__restrict__ colidx, const float *__restrict__ vals,
+                                                    int64_t rows_per, int64_t n, const int32_t *__restrict__ trp,
+                                                    int32_t *__restrict__ cur, int32_t *__restrict__ tci,
+                                                    float *__restrict__ tv) {
+    const int64_t i0 = (int64_t)blockIdx.x * rows_per, i1 = min(m, i0 + rows_per);
+    int32_t *c = cur + (int64_t)blockIdx.x * n;
+    for (int64_t i = i0; i < i1; i++) {
+        for (int32_t t = rowptr[i] + (int32_t)threadIdx.x; t < rowptr[i + 1]; t += (int32_t)blockDim.x) {
+            const int32_t j = colidx[t];
+            const int32_t pos = trp[j] + atomicAdd(&c[j], 1);
+            tci[pos] = (int32_t)i;
+            tv[pos] = vals[t];
+        }
+        __syncthreads();  // this row's cursor advances before the next row reads them
+    }
+}
+
+// Row blocks for the counting sort: as many as keep the (block x column)
+// cursors within about 64 MB, at most 256, at least one.
+static int64_t transpose_blocks(int64_t m, int64_t n) {
+    int64_t nb = (int64_t)(16 << 20) / std::max<int64_t>(n, 1);
+    nb = std::min<int64_t>(std::min<int64_t>(nb, 256), m);
+    return std::max<int64_t>(nb, 1);
+}
+
+// CSR(V') from CSR(V) (counting sort, rows ascending inside each column).
+// Outputs are hipMalloc'd and owned by the caller.
 int csr_transpose(const nmf_matrix *V, int32_t **trp, int32_t **tci, float **tv, hipStream_t s) {
     const int64_t m = V->rows, n = V->cols, nnz = V->nnz;
     *trp = nullptr; *tci = nullptr; *tv = nullptr;
     NMF_HIP(hipMalloc((void **)trp, (n + 1) * sizeof(int32_t)));
     NMF_HIP(hipMalloc((void **)tci, (nnz > 0 ? nnz : 1) * sizeof(int32_t)));
     NMF_HIP(hipMalloc((void **)tv, (nnz > 0 ? nnz : 1) * sizeof(float)));
-    int32_t *rowid = nullptr, *keys = nullptr, *idx = nullptr, *perm = nullptr;
-    void *tmp = nullptr;
-    size_t tmp_bytes = 0;
-    const size_t nb = (nnz > 0 ? nnz : 1) * sizeof(int32_t);
-    NMF_HIP(hipMalloc((void **)&rowid, nb));
-    NMF_HIP(hipMalloc((void **)&keys, nb));
-    NMF_HIP(hipMalloc((void **)&idx, nb));
-    NMF_HIP(hipMalloc((void **)&perm, nb));
-    const int g = 2048;
-    hipLaunchKernelGGL(k_expand_rows, dim3(g), dim3(256), 0, s, V->rowptr, m, rowid);
-    hipLaunchKernelGGL(k_iota, dim3(g), dim3(256), 0, s, idx, nnz);
-    int bits = 1;
-    while ((int64_t(1) << bits) < n) bits++;
-    NMF_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, V->colidx, keys, idx, perm, (int)nnz, 0, bits, s));
-    NMF_HIP(hipMalloc(&tmp, tmp_bytes > 0 ? tmp_bytes : 1));
-    NMF_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, V->colidx, keys, idx, perm, (int)nnz, 0, bits, s));
-    hipLaunchKernelGGL(k_permute, dim3(g), dim3(256), 0, s, perm, rowid, V->vals, nnz, *tci, *tv);
-    hipLaunchKernelGGL(k_col_bounds, dim3((unsigned)((n + 256) / 256)), dim3(256), 0, s, keys, nnz, n, *trp);
+    const int64_t nb = transpose_blocks(m, n), rows_per = (m + nb - 1) / nb;
+    int32_t *cnt = nullptr, *colcnt = nullptr;
+    NMF_HIP(hipMalloc((void **)&cnt, (size_t)nb * n * sizeof(int32_t)));
+    NMF_HIP(hipMalloc((void **)&colcnt, (size_t)n * sizeof(int32_t)));
+    const unsigned gcols = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_zero_i32, dim3(4096), dim3(256), 0, s, cnt, nb * n);
+    hipLaunchKernelGGL(k_tr_count, dim3((unsigned)nb), dim3(256), 0, s, V->rowptr, m, V->colidx, rows_per, n, cnt);
+    hipLaunchKernelGGL(k_tr_block_offsets, dim3(gcols), dim3(256), 0, s, cnt, nb, n, colcnt);
+    hipLaunchKernelGGL(k_tr_exclusive_scan, dim3(1), dim3(1024), 0, s, colcnt, n, *trp);
+    hipLaunchKernelGGL(k_tr_scatter, dim3((unsigned)nb), dim3(256), 0, s, V->rowptr, m, V->colidx, V->vals, rows_per,
+                       n, *trp, cnt, *tci, *tv);
     NMF_HIP(hipGetLastError());
     NMF_HIP(hipStreamSynchronize(s));
-    (void)hipFree(tmp); (void)hipFree(rowid); (void)hipFree(keys); (void)hipFree(idx); (void)hipFree(perm);
+    (void)hipFree(cnt); (void)hipFree(colcnt);
     return NMF_OK;
 }
 

@@ -137,9 +137,11 @@ def test_csr_product_matches_oracle_including_split_rows(m, n, per_row, r):
     W = g.random((m, r), dtype=np.float32); Ht = g.random((n, r), dtype=np.float32)
     colcount = np.bincount(V.indices, minlength=n)
     assert colcount.max() > 512 or m < 1000  # long columns exercise the split path
+    by_t = {}
     for with_t in (True, False):
         Vd = nat.DeviceMatrix(V, with_transpose=with_t)
         P0 = H(nat.product(Vd, T(W), 0)); R0 = oracle.product_csr(V, W, 0)
+        by_t[with_t] = P0
         P1 = H(nat.product(Vd, T(Ht), 1)); R1 = oracle.product_csr(V, Ht, 1)
         e0 = np.abs(P0 - R0).max() / max(np.abs(R0).max(), 1e-30)
         e1 = np.abs(P1 - R1).max() / max(np.abs(R1).max(), 1e-30)
@@ -156,6 +158,9 @@ def test_csr_product_matches_oracle_including_split_rows(m, n, per_row, r):
         print(f"csr bf16 {m}x{n} r={r} t={with_t}: vs rounded factor {b0:.2e} {b1:.2e}; vs fp32 {d0:.2e}")
         assert b0 < 5e-6 and b1 < 5e-6
         assert d0 < 2.0 ** -8
+    # CSR(V') built on the device (counting sort) holds each column's rows in
+    # ascending order, as scipy's transpose does: the same sums in the same order
+    assert np.array_equal(by_t[True], by_t[False])
 
 
 # empty rows and columns of V, a row longer than one chunk (split into partial
