@@ -331,19 +331,26 @@ NMF_API int nmf_foldin_noalloc(const nmf_basis *B, const nmf_matrix *Vnew, float
  * A request loop over a resident basis: fold-in requests (the E-step of
  * nmf_foldin for new columns) and small full fits (nmf_fit), continuously
  * batched.  max_slots slots each own a stream, a launcher thread and a
- * completion thread; a launcher admits work from the head of the
- * arrival-ordered queue while the HBM footprint of the admitted work stays
- * within hbm_budget bytes, packing consecutive fold-in requests (up to
- * max_batch_cols columns) into one batch with one product launch over its
- * sparse requests and a single solve launch; a fit request runs alone on its
- * slot with stream-ordered memory, and fits hold at most max_slots - 1
- * slots (fold-in requests queued behind a waiting fit go ahead of it).
- * Launchers do not wait for the device (up to two batches per slot are in
- * flight); the completion thread reports a batch done when its stream has
- * passed it.  The slots are capped at the process's hardware queues minus one
- * (GPU_MAX_HW_QUEUES, 4 unless set, so 3 slots by default): streams beyond
- * that would share hardware queues, whose work runs in order.  Requests arriving while others run are picked up by the next
- * free slot, so batches overlap on the device.  A request's result does not depend on what it is batched with.
+ * completion thread; a launcher admits the oldest waiting fold-in request,
+ * else the oldest fit request (a fit that has waited 50 ms goes ahead of
+ * fold-ins), while the HBM footprint of the admitted work stays within
+ * hbm_budget bytes, packing queued fold-in requests (up to max_batch_cols
+ * columns, in arrival order) into one batch with one product launch over its
+ * sparse requests and a single solve launch; fit requests run on a slot with
+ * stream-ordered memory, those waiting with the same options (and no
+ * check_finite) together as one batch of up to 32 through the batched fit's
+ * kernels, each result equal to its nmf_fit bitwise; fits hold at most
+ * max_slots - 1 slots.  Launchers do not wait for the device (up to two
+ * batches per slot are in flight); the completion thread reports a batch
+ * done when its stream has passed it.  The slots are capped at the process's
+ * hardware queues minus one (GPU_MAX_HW_QUEUES, 4 unless set, so 3 slots by
+ * default): streams beyond that would share hardware queues, whose work runs
+ * in order.  Requests arriving while others run are picked up by the next
+ * free slot, so batches overlap on the device.  A request's result does not
+ * depend on what it is batched with.  Batches allocate their workspace
+ * stream-ordered from the device's default memory pool; nmf_server_create
+ * sets that pool's release threshold to keep what it holds (a process-wide
+ * setting of the pool).
  * Request memory is the caller's (device pointers): its inputs must be
  * written before submission (workers run on their own streams, unordered with
  * the caller's) and it must stay valid until the request is done.  Fold-in requests use the basis' options; fit requests

@@ -9,6 +9,12 @@
 // range) chunks from a queue.  All max_outer outer iterations are captured
 // into one hipGraph and launched once.  Problems only ever read their own
 // buffers, so a problem's result does not depend on the batch it runs in.
+//
+// The same set-up serves the server's batches of fit requests
+// (batched_fit_start): memory stream-ordered on the slot's stream, the
+// phases launched straight onto it, and each problem's solve layout chosen
+// from its own column counts as nmf_fit chooses it, so that every request's
+// result equals its nmf_fit bitwise.
 #include <math.h>
 
 #include <map>
@@ -49,16 +55,63 @@ int upload(const std::vector<T> &v, T **dst, char *&cursor, hipStream_t s) {
 
 }  // namespace
 
-extern "C" int nmf_fit_batched(int32_t count, const nmf_problem *probs, const nmf_opts *opt,
-                               nmf_stats *per_problem, void *stream) {
-    if (count < 0) return fail(NMF_E_INVAL, "count must be >= 0");
-    if (count == 0) return NMF_OK;
-    if (!probs) return fail(NMF_E_INVAL, "probs is NULL");
-    if (int st = validate_opts(opt)) return st;
-    if (opt->max_outer < 0) return fail(NMF_E_INVAL, "max_outer must be >= 0");
-    hipStream_t s = (hipStream_t)stream;
-    const bool bf16 = opt->precision == NMF_BF16;
+
+namespace nmfi {
+
+// A batched fit: its device buffers, its work lists (host copies kept while
+// their uploads may be in flight) and how to launch them.
+struct BatchedFit {
+    int count = 0;
+    nmf_opts opt{};
+    bool bf16 = false, async_mem = false;
+    hipStream_t s = nullptr;
     int ntmax = 1;
+    char *base = nullptr, *lists = nullptr;
+    HalfLists hl[2];
+    DevHalf dh[2];
+    unsigned int *queues = nullptr;
+    struct Slot {
+        size_t G, part, P, V16, V16t, A16, inner, kpart[2];
+    };
+    std::vector<Slot> slot;
+    std::vector<nmf_problem> probs;
+
+    void *dptr(size_t o) const { return (void *)(base + o); }
+
+    hipError_t dmalloc(void **p, size_t bytes) {
+        return async_mem ? hipMallocAsync(p, bytes, s) : hipMalloc(p, bytes);
+    }
+    void dfree(void *p) {
+        if (!p) return;
+        if (async_mem) (void)hipFreeAsync(p, s);
+        else (void)hipFree(p);
+    }
+    void release() {
+        dfree(lists);
+        dfree(base);
+        lists = base = nullptr;
+    }
+
+    // Validates the problems, allocates, builds and uploads the work lists.
+    // solo_layout: each problem's solve layout from its own column counts
+    // (as nmf_fit), else from the whole launch's.
+    int prepare(int32_t count_, const nmf_problem *pr, const nmf_opts *o, hipStream_t s_, bool async,
+                bool solo_layout);
+    // Every outer iteration's phases straight onto the stream.
+    int launch_direct();
+    // Every outer iteration captured into one graph (the variants' solves as
+    // parallel branches) and launched on the stream; synchronises it.
+    int launch_graph();
+};
+
+int BatchedFit::prepare(int32_t count_, const nmf_problem *pr, const nmf_opts *o, hipStream_t s_, bool async,
+                        bool solo_layout) {
+    count = count_;
+    opt = *o;
+    s = s_;
+    async_mem = async;
+    bf16 = opt.precision == NMF_BF16;
+    probs.assign(pr, pr + count);
     for (int p = 0; p < count; p++) {
         const nmf_problem &q = probs[p];
         if (q.V.kind != NMF_DENSE)
@@ -66,8 +119,8 @@ extern "C" int nmf_fit_batched(int32_t count, const nmf_problem *probs, const nm
         if (q.V.rows < 1 || q.V.cols < 1 || !q.V.dense || q.V.ld < q.V.cols)
             return fail(NMF_E_INVAL, "problem %d: bad dense V", p);
         if (q.r < 1 || q.r > NMF_MAX_RANK) return fail(NMF_E_INVAL, "problem %d: r out of range", p);
-        if (opt->lanes && !nqp_lanes_ok(q.r, opt->lanes))
-            return fail(NMF_E_INVAL, "problem %d: lanes = %d cannot hold rank %d", p, opt->lanes, q.r);
+        if (opt.lanes && !nqp_lanes_ok(q.r, opt.lanes))
+            return fail(NMF_E_INVAL, "problem %d: lanes = %d cannot hold rank %d", p, opt.lanes, q.r);
         if (!q.W || !q.Ht) return fail(NMF_E_INVAL, "problem %d: W and Ht must be non-NULL", p);
         const float rg[4] = {q.reg.l1_w, q.reg.l2_w, q.reg.l1_h, q.reg.l2_h};
         for (float v : rg)
@@ -77,12 +130,9 @@ extern "C" int nmf_fit_batched(int32_t count, const nmf_problem *probs, const nm
     }
 
     // ---------------------------------------------------------------- buffers
-    struct Slot {
-        size_t G, part, P, V16, V16t, A16, inner, kpart[2];
-    };
-    std::vector<Slot> slot(count);
+    slot.resize(count);
     size_t off = 0;
-    auto place = [&](size_t bytes) { size_t o = off; off += al256(bytes); return o; };
+    auto place = [&](size_t bytes) { size_t o2 = off; off += al256(bytes); return o2; };
     for (int p = 0; p < count; p++) {
         const nmf_problem &q = probs[p];
         const int64_t m = q.V.rows, n = q.V.cols, r = q.r;
@@ -103,13 +153,12 @@ extern "C" int nmf_fit_batched(int32_t count, const nmf_problem *probs, const nm
     const size_t data_bytes = off;
 
     // ---------------------------------------------------------------- work lists
-    HalfLists hl[2];  // 0: H-update (A = W, data V'), 1: W-update (A = Ht, data V)
-    char *base = nullptr;  // set after allocation; lists hold offsets until then
-    auto dptr = [&](size_t o) { return (void *)(base + o); };
     {
-        const hipError_t e0 = hipMalloc((void **)&base, data_bytes + 256);
-        if (e0 != hipSuccess)
+        const hipError_t e0 = dmalloc((void **)&base, data_bytes + 256);
+        if (e0 != hipSuccess) {
+            base = nullptr;
             return fail(NMF_E_DEVICE, "batched buffers (%zu bytes): %s", data_bytes + 256, hipGetErrorString(e0));
+        }
     }
     int64_t ctot[2] = {0, 0};  // columns solved per half-iteration, all problems
     for (int p = 0; p < count; p++) {
@@ -134,10 +183,10 @@ extern "C" int nmf_fit_batched(int32_t count, const nmf_problem *probs, const nm
             const int64_t kc = dense_kchunk(C, k);
             const int ns = (int)((k + kc - 1) / kc);
             const int64_t lda16 = (std::max(m, n) + 63) / 64 * 64;
-            BProdProb pr{V, bf16 ? k : q.V.ld, C, k, A, r, (float *)dptr(slot[p].P),
-                         ns > 1 ? (float *)dptr(slot[p].kpart[h]) : nullptr, kc, ns,
-                         bf16 ? (__bf16 *)dptr(slot[p].A16) : nullptr, bf16 ? lda16 : 0};
-            hl[h].prod.push_back(pr);
+            BProdProb prd{V, bf16 ? k : q.V.ld, C, k, A, r, (float *)dptr(slot[p].P),
+                          ns > 1 ? (float *)dptr(slot[p].kpart[h]) : nullptr, kc, ns,
+                          bf16 ? (__bf16 *)dptr(slot[p].A16) : nullptr, bf16 ? lda16 : 0};
+            hl[h].prod.push_back(prd);
             if (bf16)
                 for (int64_t kb = 0; kb < (k + 63) / 64; kb++) hl[h].f16_items.push_back({p, (int32_t)kb});
             for (int64_t cb = 0; cb < (C + DENSE_BM - 1) / DENSE_BM; cb++)
@@ -148,9 +197,10 @@ extern "C" int nmf_fit_batched(int32_t count, const nmf_problem *probs, const nm
                           r, H ? q.reg.l1_h : q.reg.l1_w, (unsigned long long *)dptr(slot[p].inner),
                           nullptr, 0};
             hl[h].solve.push_back(sv);
-            // the layout is chosen for the whole launch's column count
-            const NqpVariant v = nqp_pick(r, ctot[h], opt->lanes);
-            const int chunk = bnqp_chunk_cols(v.L, opt->fast_break_cols);
+            // the layout is chosen for the whole launch's column count, or (solo
+            // layout) for the problem's own, as nmf_fit chooses it
+            const NqpVariant v = nqp_pick(r, solo_layout ? C : ctot[h], opt.lanes);
+            const int chunk = bnqp_chunk_cols(v.L, opt.fast_break_cols);
             auto &lst = hl[h].chunks[{v.E, v.L}];
             for (int64_t c0 = 0; c0 < C; c0 += chunk)
                 lst.push_back({p, (int32_t)c0, (int32_t)std::min<int64_t>(C, c0 + chunk)});
@@ -176,11 +226,9 @@ extern "C" int nmf_fit_batched(int32_t count, const nmf_problem *probs, const nm
     }
     const int ngroups = (int)(hl[0].chunks.size() + hl[1].chunks.size());
     list_bytes += al256((size_t)(ngroups + 1) * sizeof(unsigned int));
-    char *lists = nullptr;
-    hipError_t e = hipMalloc((void **)&lists, list_bytes + 256);
-    if (e != hipSuccess) { (void)hipFree(base); return hip_fail(e, "batched work lists"); }
+    hipError_t e = dmalloc((void **)&lists, list_bytes + 256);
+    if (e != hipSuccess) { lists = nullptr; return hip_fail(e, "batched work lists"); }
     int st = NMF_OK;
-    DevHalf dh[2];
     char *cur = lists;
     for (int h = 0; h < 2 && !st; h++) {
         st = upload(hl[h].gram_items, &dh[h].gram_items, cur, s);
@@ -200,7 +248,7 @@ extern "C" int nmf_fit_batched(int32_t count, const nmf_problem *probs, const nm
             dh[h].groups.push_back({NqpVariant{kv.first.first, kv.first.second}, {d, (int)kv.second.size()}});
         }
     }
-    unsigned int *queues = (unsigned int *)cur;
+    queues = (unsigned int *)cur;
     // BF16 copies of V and zeroed iteration counters
     for (int p = 0; p < count && !st; p++) {
         const nmf_problem &q = probs[p];
@@ -215,12 +263,37 @@ extern "C" int nmf_fit_batched(int32_t count, const nmf_problem *probs, const nm
             if (e != hipSuccess) st = hip_fail(e, "zero counters");
         }
     }
-    if (!st) {
+    if (!st && !async_mem) {
         e = hipStreamSynchronize(s);
         if (e != hipSuccess) st = hip_fail(e, "batched set-up");
     }
+    return st;
+}
 
-    // ---------------------------------------------------------------- graph
+int BatchedFit::launch_direct() {
+    hipError_t e = hipSuccess;
+    for (int t = 0; t < opt.max_outer && e == hipSuccess; t++) {
+        for (int h = 0; h < 2 && e == hipSuccess; h++) {
+            const int gi = h * (int)hl[0].chunks.size();
+            e = launch_zero_u32(queues + gi, (int)dh[h].groups.size(), s);
+            if (e == hipSuccess) e = launch_bgram(dh[h].gram_items, dh[h].n_gram_items, dh[h].gram, count, ntmax,
+                                                  opt.precision, s);
+            if (e == hipSuccess)
+                e = launch_bdense(dh[h].prod_items, dh[h].n_prod_items, dh[h].prod, ntmax, h == 0, bf16,
+                                  dh[h].red_items, dh[h].n_red_items, dh[h].f16_items, dh[h].n_f16_items, s);
+            for (size_t g = 0; g < dh[h].groups.size() && e == hipSuccess; g++)
+                e = launch_bnqp(dh[h].groups[g].first, dh[h].groups[g].second.first, dh[h].groups[g].second.second,
+                                queues + gi + (int)g, dh[h].solve, opt.max_inner, opt.eps, opt.ls_guard ? 1 : 0,
+                                opt.fast_break_cols, s);
+        }
+    }
+    if (e != hipSuccess) return hip_fail(e, "batched launches");
+    return NMF_OK;
+}
+
+int BatchedFit::launch_graph() {
+    int st = NMF_OK;
+    hipError_t e = hipSuccess;
     // The solve launches of a half (one per kernel variant) are independent:
     // they are captured as parallel branches (fork/join through events on
     // side streams), so one variant's tail overlaps the others' work.
@@ -231,25 +304,25 @@ extern "C" int nmf_fit_batched(int32_t count, const nmf_problem *probs, const nm
     for (int h = 0; h < 2; h++) maxg = std::max(maxg, dh[h].groups.size());
     std::vector<hipStream_t> side(maxg > 1 ? maxg - 1 : 0, nullptr);
     std::vector<hipEvent_t> evs;
-    if (!st && opt->max_outer > 0) {
+    if (opt.max_outer > 0) {
         e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
         for (size_t i = 0; i < side.size() && e == hipSuccess; i++)
             e = hipStreamCreateWithFlags(&side[i], hipStreamNonBlocking);
         // one fork event and one join event per side stream and half-iteration
-        const size_t nev = (size_t)opt->max_outer * 2 * (1 + side.size());
+        const size_t nev = (size_t)opt.max_outer * 2 * (1 + side.size());
         for (size_t i = 0; i < nev && e == hipSuccess; i++) {
             hipEvent_t ev = nullptr;
             e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
             if (e == hipSuccess) evs.push_back(ev);
         }
         if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-        for (int t = 0; t < opt->max_outer && e == hipSuccess; t++) {
+        for (int t = 0; t < opt.max_outer && e == hipSuccess; t++) {
             for (int h = 0; h < 2 && e == hipSuccess; h++) {
                 int gi = h * (int)hl[0].chunks.size();
                 e = launch_zero_u32(queues + gi, (int)dh[h].groups.size(), cs);
                 if (e == hipSuccess)
                     e = launch_bgram(dh[h].gram_items, dh[h].n_gram_items, dh[h].gram, count, ntmax,
-                                     opt->precision, cs);
+                                     opt.precision, cs);
                 if (e == hipSuccess)
                     e = launch_bdense(dh[h].prod_items, dh[h].n_prod_items, dh[h].prod, ntmax, h == 0,
                                       bf16, dh[h].red_items, dh[h].n_red_items, dh[h].f16_items,
@@ -263,8 +336,8 @@ extern "C" int nmf_fit_batched(int32_t count, const nmf_problem *probs, const nm
                     if (e == hipSuccess)
                         e = launch_bnqp(dh[h].groups[g].first, dh[h].groups[g].second.first,
                                         dh[h].groups[g].second.second, queues + gi + (int)g,
-                                        dh[h].solve, opt->max_inner, opt->eps, opt->ls_guard ? 1 : 0,
-                                        opt->fast_break_cols, gs);
+                                        dh[h].solve, opt.max_inner, opt.eps, opt.ls_guard ? 1 : 0,
+                                        opt.fast_break_cols, gs);
                     if (e == hipSuccess && g > 0) e = hipEventRecord(evs[ev0 + g], gs);
                 }
                 for (size_t g = 1; g < ng && e == hipSuccess; g++) e = hipStreamWaitEvent(cs, evs[ev0 + g], 0);  // join
@@ -283,6 +356,42 @@ extern "C" int nmf_fit_batched(int32_t count, const nmf_problem *probs, const nm
     for (hipStream_t x : side)
         if (x) (void)hipStreamDestroy(x);
     for (hipEvent_t ev : evs) (void)hipEventDestroy(ev);
+    return st;
+}
+
+// The server's batches of fit requests: prepared and launched on `stream`
+// without waiting for the device; *out is released (batched_fit_end) once
+// the stream has passed the launches.
+int batched_fit_start(int32_t count, const nmf_problem *probs, const nmf_opts *opt, hipStream_t stream,
+                      BatchedFit **out) {
+    *out = nullptr;
+    auto *b = new BatchedFit();
+    int st = b->prepare(count, probs, opt, stream, true, true);
+    if (!st) st = b->launch_direct();
+    b->release();  // stream-ordered: after the launches
+    if (st) {
+        delete b;
+        return st;
+    }
+    *out = b;
+    return NMF_OK;
+}
+
+void batched_fit_end(BatchedFit *b) { delete b; }
+
+}  // namespace nmfi
+
+extern "C" int nmf_fit_batched(int32_t count, const nmf_problem *probs, const nmf_opts *opt,
+                               nmf_stats *per_problem, void *stream) {
+    if (count < 0) return fail(NMF_E_INVAL, "count must be >= 0");
+    if (count == 0) return NMF_OK;
+    if (!probs) return fail(NMF_E_INVAL, "probs is NULL");
+    if (int st = validate_opts(opt)) return st;
+    if (opt->max_outer < 0) return fail(NMF_E_INVAL, "max_outer must be >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    BatchedFit b;
+    int st = b.prepare(count, probs, opt, s, false, false);
+    if (!st) st = b.launch_graph();
 
     // ---------------------------------------------------------------- statistics
     if (!st && per_problem) {
@@ -292,7 +401,7 @@ extern "C" int nmf_fit_batched(int32_t count, const nmf_problem *probs, const nm
             st = nmf_objective(&q.V, q.r, &q.reg, q.W, q.Ht, &loss, &obj, stream);
             unsigned long long inner = 0;
             if (!st) {
-                e = hipMemcpy(&inner, dptr(slot[p].inner), sizeof inner, hipMemcpyDeviceToHost);
+                hipError_t e = hipMemcpy(&inner, b.dptr(b.slot[p].inner), sizeof inner, hipMemcpyDeviceToHost);
                 if (e != hipSuccess) st = hip_fail(e, "batched stats");
             }
             nmf_stats &o = per_problem[p];
@@ -300,7 +409,7 @@ extern "C" int nmf_fit_batched(int32_t count, const nmf_problem *probs, const nm
             o.objective = obj;
             o.kkt_w = NAN;
             o.kkt_h = NAN;
-            for (int q = 0; q < 3; q++) o.kkt_w_cond[q] = o.kkt_h_cond[q] = NAN;
+            for (int q2 = 0; q2 < 3; q2++) o.kkt_w_cond[q2] = o.kkt_h_cond[q2] = NAN;
             o.inner_total = (int64_t)inner;
             o.outer_done = opt->max_outer;
             o.kbar = opt->max_outer > 0
@@ -309,8 +418,7 @@ extern "C" int nmf_fit_batched(int32_t count, const nmf_problem *probs, const nm
         }
     }
     (void)hipStreamSynchronize(s);
-    (void)hipFree(lists);
-    (void)hipFree(base);
+    b.release();
     return st;
 }
 

@@ -201,6 +201,17 @@ inline int bnqp_chunk_cols(int L) { return 4 * (64 / L) * 4; }
 inline int bnqp_chunk_cols(int L, int unit) {
     return unit > 1 ? (512 / L) * unit : bnqp_chunk_cols(L);
 }
+
+// A batched fit of dense problems launched on a stream without waiting
+// (the server's batches of fit requests): each problem's solve layout is its
+// nmf_fit layout, so results equal nmf_fit's bitwise; memory is
+// stream-ordered.  batched_fit_end releases the host side once the stream
+// has passed the launches.
+struct BatchedFit;
+int batched_fit_start(int32_t count, const nmf_problem *probs, const nmf_opts *opt, hipStream_t stream,
+                      BatchedFit **out);
+void batched_fit_end(BatchedFit *b);
+
 hipError_t launch_zero_u32(unsigned int *p, int n, hipStream_t s);
 
 // ------------------------------------------------------------------ objective

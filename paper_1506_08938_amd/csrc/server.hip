@@ -3,15 +3,18 @@
 //
 // Each of `max_slots` slots owns a HIP stream (default priority), a launcher
 // thread and a completion thread.  Requests queue in arrival order; a
-// launcher admits from the head of the queue (fit requests hold at most
-// max_slots - 1 slots: one stays free for fold-ins, which pass a fit that has
-// to wait) while the HBM footprint of the admitted work stays within the
-// budget:
-// consecutive fold-in requests (up to max_batch_cols columns) become one
+// launcher admits the oldest fold-in request when one waits, else the oldest
+// fit request (fits hold at most max_slots - 1 slots, and one that has waited
+// 50 ms goes ahead of fold-ins), while the HBM footprint of the admitted work
+// stays within the budget:
+// queued fold-in requests (up to max_batch_cols columns) become one
 // batch -- one product launch over all of its sparse requests' columns, then
 // ONE solve launch over all of the batch's columns -- and a full-fit request
-// runs alone on its slot, its plan's memory stream-ordered on the slot's
-// stream (no device-wide synchronisation).  The launcher never waits for the
+// runs on its slot, its memory stream-ordered on the slot's stream (no
+// device-wide synchronisation); fit requests with the same options that are
+// waiting in the queue go with it (up to kMaxFitBatch), through the batched
+// fit's kernels -- a fit is latency-bound (its solves wait for their slowest
+// column), so a batch of them takes about as long as one.  The launcher never waits for the
 // device: it hands the batch, with an event recorded after its last launch,
 // to the slot's completion thread and may admit the next one.  A slot with
 // work in flight takes more (at most kMaxInFlight batches) only behind a
@@ -25,6 +28,7 @@
 // alone and in the mix.
 #include <math.h>
 #include <stdlib.h>
+#include <string.h>
 
 #include <algorithm>
 #include <atomic>
@@ -51,6 +55,8 @@ double now_s() {
 size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 constexpr size_t kMaxInFlight = 2;  // batches launched and not yet complete, per slot
+constexpr size_t kMaxFitBatch = 32; // fit requests launched together
+constexpr double kFitMaxWait = 0.05; // s a fit waits behind fold-in requests at most
 
 struct Req {
     uint64_t ticket = 0;
@@ -73,6 +79,7 @@ struct InFlight {
     int status = NMF_OK;
     std::string msg;
     hipEvent_t ev = nullptr;
+    BatchedFit *fits = nullptr;  // several fit requests run together
     std::vector<BSolveProb> probs;
     std::vector<BSolveChunk> chunks;
     std::vector<SpRowsReq> rows;
@@ -179,10 +186,25 @@ int launch_foldin_batch(nmf_server *S, InFlight &F, hipStream_t s) {
     return NMF_OK;
 }
 
+// A batch of fit requests (same options): alone through nmf_fit's plan
+// (stream-ordered), together through the batched kernels with each
+// problem's nmf_fit layout -- the results equal nmf_fit's bitwise either way.
 int launch_fit_request(InFlight &F, hipStream_t s) {
-    Req &R = *F.batch[0];
-    nmf_opts o = R.q.fit_opts;
-    return fit_stream_ordered(&R.q.V, R.q.r, &R.q.reg, &o, R.q.W, R.q.Ht, s);
+    nmf_opts o = F.batch[0]->q.fit_opts;
+    if (F.batch.size() == 1) {
+        Req &R = *F.batch[0];
+        return fit_stream_ordered(&R.q.V, R.q.r, &R.q.reg, &o, R.q.W, R.q.Ht, s);
+    }
+    std::vector<nmf_problem> pr;
+    for (auto &q : F.batch) pr.push_back(nmf_problem{q->q.V, q->q.r, q->q.reg, q->q.W, q->q.Ht});
+    return batched_fit_start((int32_t)pr.size(), pr.data(), &o, s, &F.fits);
+}
+
+// Fit requests that may run in one batch: same options, no input scan (the
+// batched fit does not check its inputs), at least one outer iteration.
+bool fit_batchable(const nmf_request &a, const nmf_request &b) {
+    return !a.fit_opts.check_finite && a.fit_opts.max_outer > 0 &&
+           memcmp(&a.fit_opts, &b.fit_opts, sizeof(nmf_opts)) == 0;
 }
 
 // Whether a slot may take more work now: always when idle; a second batch
@@ -203,15 +225,24 @@ void launcher(nmf_server *S, Slot *sl) {
         auto F = std::make_unique<InFlight>();
         {
             std::unique_lock<std::mutex> lk(S->mu);
-            // The first request this slot may start: the head of the queue,
-            // except that a fit request waits while max_fits fits run, and the
-            // fold-in requests queued behind it go ahead meanwhile.
+            // The first request this slot may start: the oldest fold-in
+            // request when one waits (a fold-in batch takes a fraction of a
+            // millisecond, a batch of fits tens of them), else the oldest fit
+            // -- a fit may start only while fewer than max_fits fits run, and
+            // one that has waited kFitMaxWait goes ahead of fold-ins.
             auto first = [&]() -> std::deque<std::shared_ptr<Req>>::iterator {
+                auto fold = S->queue.end(), fit = S->queue.end();
                 for (auto it = S->queue.begin(); it != S->queue.end(); ++it) {
-                    if ((*it)->q.kind == NMF_REQ_FIT && S->fits_running >= S->max_fits) continue;
-                    return it;
+                    if ((*it)->q.kind == NMF_REQ_FIT) {
+                        if (fit == S->queue.end() && S->fits_running < S->max_fits) fit = it;
+                    } else if (fold == S->queue.end()) {
+                        fold = it;
+                    }
+                    if (fold != S->queue.end() && fit != S->queue.end()) break;
                 }
-                return S->queue.end();
+                if (fit != S->queue.end() && (fold == S->queue.end() || now_s() - (*fit)->t_submit > kFitMaxWait))
+                    return fit;
+                return fold;
             };
             S->cv_work.wait(lk, [&] {
                 if (S->stop && S->queue.empty()) return true;
@@ -224,15 +255,31 @@ void launcher(nmf_server *S, Slot *sl) {
             if ((*it)->q.kind == NMF_REQ_FIT) {
                 F->batch.push_back(*it);
                 F->fp = (*it)->footprint;
-                S->queue.erase(it);
+                it = S->queue.erase(it);
                 F->is_fit = true;
                 S->fits_running++;
+                // queued fit requests that can run with it, in arrival order
+                const nmf_request &head = F->batch[0]->q;
+                while (it != S->queue.end() && F->batch.size() < kMaxFitBatch) {
+                    auto &q = *it;
+                    if (q->q.kind == NMF_REQ_FIT && fit_batchable(head, q->q) &&
+                        S->in_use + F->fp + q->footprint <= S->budget) {
+                        F->fp += q->footprint;
+                        F->batch.push_back(q);
+                        it = S->queue.erase(it);
+                    } else {
+                        ++it;
+                    }
+                }
             } else {
-                // consecutive fold-in requests from there, in arrival order
+                // fold-in requests from there, in arrival order (fits stay queued)
                 int64_t cols = 0;
                 while (it != S->queue.end()) {
                     auto &q = *it;
-                    if (q->q.kind != NMF_REQ_FOLDIN) break;
+                    if (q->q.kind != NMF_REQ_FOLDIN) {
+                        ++it;
+                        continue;
+                    }
                     if (!F->batch.empty() && cols + req_cols(q->q) > S->max_cols) break;
                     if (S->in_use + F->fp + q->footprint > S->budget) break;
                     cols += req_cols(q->q);
@@ -285,6 +332,7 @@ void completer(nmf_server *S, Slot *sl) {
         }
         hipError_t e = F->ev ? hipEventSynchronize(F->ev) : hipStreamSynchronize(sl->s);
         if (F->ev) (void)hipEventDestroy(F->ev);
+        if (F->fits) batched_fit_end(F->fits);
         int st = F->status;
         std::string msg = F->msg;
         if (!st && e != hipSuccess) {
@@ -353,6 +401,17 @@ extern "C" int nmf_server_create(const nmf_basis *B, size_t hbm_budget, int32_t 
     S->max_cols = max_batch_cols;
     S->max_fits = max_slots > 1 ? max_slots - 1 : 1;
     if (hipGetDevice(&S->device) != hipSuccess) S->device = 0;
+    {
+        // Batches allocate their workspace stream-ordered from the device's
+        // default pool; keep what the pool holds instead of returning it to
+        // the system at every synchronisation (the next batch's allocation
+        // would then wait for a fresh one).
+        hipMemPool_t pool = nullptr;
+        if (hipDeviceGetDefaultMemPool(&pool, S->device) == hipSuccess && pool) {
+            uint64_t keep = UINT64_MAX;
+            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+        }
+    }
     for (int i = 0; i < max_slots; i++) {
         auto sl = std::make_unique<Slot>();
         hipError_t e = hipStreamCreateWithFlags(&sl->s, hipStreamNonBlocking);

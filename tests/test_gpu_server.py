@@ -161,3 +161,35 @@ def test_fast_break_results_do_not_depend_on_the_batch():
     assert np.array_equal(H(outs[1]), direct)
     S.close()
     B.close()
+
+
+def test_fit_requests_batched_together_equal_nmf_fit(basis):
+    """Fit requests waiting together run as one batch through the batched
+    kernels (each with its nmf_fit solve layout): every result equals its
+    nmf_fit bitwise, regularised problems and options included; a request
+    with other options, or one that asks for the input scan, runs alone."""
+    import torch
+    from paper_1506_08938_amd import native as nat
+    B, W = basis
+    fits = synth.workload5_fits(10, seed=7007)
+    regs = [nat.reg(0.01 * (i % 2), 0.02 * (i % 3 == 0), 0.05 * (i % 4 == 1), 0.01 * (i % 5 == 2))
+            for i in range(len(fits))]
+    opts = [nat.opts(max_outer=4) if i != 7 else nat.opts(max_outer=3, eps=1e-4) for i in range(len(fits))]
+    opts[8] = nat.opts(max_outer=4, check_finite=1)
+    # one slot for fits (max_slots 2): every fit submitted before the first
+    # can start waits in the queue and is taken with the next batch
+    S = nat.Server(B, hbm_budget=4 << 30, max_slots=2, max_batch_cols=4096)
+    outs, tickets = [], []
+    for f, rg, o in zip(fits, regs, opts):
+        Wd, Hd = T(f["W0"]), T(f["Ht0"])
+        outs.append((Wd, Hd))
+        tickets.append(S.submit_fit(T(f["V"]), f["r"], rg, o, Wd, Hd))
+    S.wait()
+    batches = S.stats()["batches"]
+    S.close()
+    for (Wd, Hd), f, rg, o in zip(outs, fits, regs, opts):
+        W2, H2 = T(f["W0"]), T(f["Ht0"])
+        nat.fit(nat.DeviceMatrix(T(f["V"])), f["r"], rg, o, W2, H2, want_trace=False)
+        assert np.array_equal(H(Wd), H(W2)) and np.array_equal(H(Hd), H(H2))
+    print(f"{len(fits)} fit requests in {batches} batches")
+    assert batches < len(fits)
