@@ -52,6 +52,26 @@ def test_batched_equals_solo_fits(precision, lanes, fb):
         assert stats[i]["loss"] == pytest.approx(st["loss"], rel=1e-12)
 
 
+def test_batched_many_chunks_per_block_equals_solo():
+    """Sixteen lanes per column make 64-column chunks, so 192 problems give
+    each block of the solve many chunks in turn (the Hessian restaged for
+    each, in the conditioning-weighted order), and every result still equals
+    its solo nmf_fit bitwise, iteration totals included."""
+    from paper_1506_08938_amd import native as nat
+    probs = problems(192)
+    opt = nat.opts(max_outer=2, lanes=16)
+    batch = [dict(V=T(p["V"]), r=p["r"], reg=nat.reg(), W=T(p["W0"]), Ht=T(p["Ht0"])) for p in probs]
+    stats = nat.fit_batched(batch, opt)
+    chunks = sum(-(-p["V"].shape[0] // 64) + -(-p["V"].shape[1] // 64) for p in probs)
+    print(f"{len(probs)} problems, {chunks} solve chunks per outer iteration")
+    for i, p in enumerate(probs):
+        W = T(p["W0"]); Ht = T(p["Ht0"])
+        _, st = nat.fit(nat.DeviceMatrix(T(p["V"])), p["r"], nat.reg(), opt, W, Ht, want_trace=False)
+        assert np.array_equal(H(batch[i]["W"]), H(W)), i
+        assert np.array_equal(H(batch[i]["Ht"]), H(Ht)), i
+        assert stats[i]["inner_total"] == st["inner_total"], i
+
+
 def test_batched_one_step_matches_oracle():
     from paper_1506_08938_amd import native as nat
     probs = problems(12)
