@@ -17,7 +17,9 @@ of 256 CUs x 64 lanes x 2.4 GHz; the exact count of the operations the
 method performs (r^2 + 5r, then 7 r^2 + 13 r per iteration) is reported
 beside it.  The product_roofline entry is for the product phase (row
 gathers of the CSR products), algorithmic bytes per step over its time from
-a separate run with events around every phase, against 8 TB/s.  The CPU
+a separate run with events around every phase, against 8 TB/s; beside it,
+the time of the gather probe (nothing but the same row loads in the same
+orders) over the phase's time, the measured ceiling of the gathers.  The CPU
 baseline is the FP64 oracle timed on the host cores for the first
 --cpu-iters outer iterations of the same workload from the same start point.
 
@@ -466,6 +468,75 @@ def bench_batched(args, native, synth, torch, np):
     print(json.dumps(out), flush=True)
 
 
+def gather_probe(native, synth, torch, np, V, r, bf16_case=True, uniform_case=True):
+    """Times the gather probe (nothing but the row loads of the sparse
+    products) on the headline workload's access orders: W rows in the
+    H-update's order (CSR(V') of the columns outside the plan's hot set) and
+    Ht rows in the W-update's order (CSR(V)), FP32 rows of r floats; optionally
+    W rows as BF16 (rows padded to 8 values) and uniformly random W rows."""
+    m, n = V.shape
+    # the plan's hot columns: c_j >= max(m/16, 256) entries, the longest first,
+    # all up to 127, else 128 or 256 of them
+    cnt = np.bincount(V.indices, minlength=n)
+    thr = max((m + 15) // 16, 256)
+    cand = np.nonzero(cnt >= thr)[0]
+    cand = cand[np.argsort(-cnt[cand], kind="stable")]
+    if cand.size >= 128:
+        cand = cand[: min(cand.size, 256) // 128 * 128]
+    hot = np.zeros(n, bool)
+    if cand.size >= 4:
+        hot[cand] = True
+    Vc = V.tocsc()
+    keep = np.repeat(~hot, np.diff(Vc.indptr))
+    idx_h = Vc.indices[keep].astype(np.int32)  # CSR(V') order, cold columns
+    idx_w = V.indices.astype(np.int32)          # CSR(V) order
+    # the probe's rate does not depend on the values it reads
+    W = torch.ones((m, r), device="cuda")
+    Ht = torch.ones((n, r), device="cuda")
+    cases = [("h_update", "H-update order, W rows FP32", W, idx_h),
+             ("w_update", "W-update order, Ht rows FP32", Ht, idx_w)]
+    if bf16_case:
+        W16 = torch.ones((m, (r + 7) // 8 * 8), dtype=torch.bfloat16, device="cuda")
+        cases.append(("h_update_bf16", "H-update order, W rows BF16", W16, idx_h))
+    if uniform_case:
+        idx_u = synth.rng(4711).integers(0, m, idx_h.size).astype(np.int32)
+        cases.append(("uniform", "uniformly random W rows FP32", W, idx_u))
+    out = torch.empty(native.PROBE_GATHER_OUT_FLOATS, device="cuda")
+    res = {}
+    for key, name, table, idx in cases:
+        d = torch.from_numpy(idx).cuda()
+        for _ in range(3):
+            native.probe_gather(table, d, out)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        K = 10
+        ev[0].record()
+        for _ in range(K):
+            native.probe_gather(table, d, out)
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1]) / K
+        row_bytes = int(table.shape[1] * table.element_size())
+        nbytes = idx.size * row_bytes
+        res[key] = dict(case=name, rows=int(table.shape[0]), row_bytes=row_bytes, gathers=int(idx.size),
+                        gathered_bytes=int(nbytes), ms=ms, bytes_per_s=nbytes / ms * 1e3)
+        log(f"[bench] probe, {name} ({row_bytes} B rows): {idx.size} rows, {nbytes / 1e9:.2f} GB in "
+            f"{ms:.3f} ms = {nbytes / ms / 1e9:.2f} TB/s")
+    return res, int(hot.sum())
+
+
+def bench_gather_ceiling(args, native, synth, torch, np):
+    """The row-gather ceiling of the sparse products on the headline workload
+    (gather_probe, all four cases)."""
+    log("[bench] generating the sparse workload")
+    wl = synth.workload3()
+    res, nhot = gather_probe(native, synth, torch, np, wl["V"], wl["r"])
+    print(json.dumps({"metric": "row-gather ceiling of the sparse products (probe)", "unit": "B/s",
+                      "data": "synthetic", "hot_columns": nhot,
+                      "config": {"workload": "sparse text-like CSR V 200000x100000 (the headline workload), r=100"},
+                      "cases": res}), flush=True)
+
+
 def bench_streamed(args, native, synth, torch, np):
     """Limited internal memory: workload 2 (V 20000x10000 FP32, 800 MB) kept in page-locked host
     memory and streamed to the device in panels of instances, one read of V per outer iteration
@@ -653,7 +724,7 @@ def main():
     ap.add_argument("--accuracy-iters", type=int, default=50,
                     help="--workload sparse_accuracy: outer iterations of the oracle's reference run")
     ap.add_argument("--workload", default="sparse",
-                    choices=["sparse", "dense", "batched", "serving", "streamed", "sparse_accuracy",
+                    choices=["sparse", "dense", "batched", "serving", "streamed", "sparse_accuracy", "gather_ceiling",
                              "single_pass"],
                     help="sparse: the headline line (default); the others print supplementary lines")
     ap.add_argument("--lanes", type=int, default=0,
@@ -665,6 +736,7 @@ def main():
     ap.add_argument("--fast-break", type=int, default=0,
                     help="Algorithm 3's fast-break over runs of this many columns (0: off)")
     ap.add_argument("--no-bf16", action="store_true", help="skip the BF16-products leg of the sparse workload")
+    ap.add_argument("--no-probe", action="store_true", help="skip the gather-ceiling probe of the product phase")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"],
                     help="sparse workload: float32 products, or BF16 gathers and Gram (the solve stays float32)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -703,6 +775,8 @@ def main():
         return bench_sparse_accuracy(args, native, synth, torch, np)
     if args.workload == "single_pass":
         return bench_single_pass(args, native, synth, torch, np)
+    if args.workload == "gather_ceiling":
+        return bench_gather_ceiling(args, native, synth, torch, np)
     log("[bench] generating the sparse workload")
     t_gen = time.perf_counter()
     wl = synth.workload3()
@@ -823,6 +897,19 @@ def main():
         "phases_ms_per_step": phases,
         "loss_after": st["loss"],
     }
+
+    if not args.no_probe:
+        # the measured ceiling of the product phase's row gathers: the probe in
+        # both halves' access orders (the hot columns' dense product excluded)
+        probe, _ = gather_probe(native, synth, torch, np, V, r, bf16_case=False, uniform_case=False)
+        ceil_ms = probe["h_update"]["ms"] + probe["w_update"]["ms"]
+        out["product_roofline"]["gather_probe"] = {
+            "h_update_ms": probe["h_update"]["ms"], "w_update_ms": probe["w_update"]["ms"],
+            "h_update_bytes_per_s": probe["h_update"]["bytes_per_s"],
+            "w_update_bytes_per_s": probe["w_update"]["bytes_per_s"],
+            "note": "nothing but the row loads of both products in their own orders (FP32 rows, cold entries "
+                    "of the H-update, all entries of the W-update)"}
+        out["product_roofline"]["frac_of_gather_probe"] = ceil_ms / (prod_s * 1e3)
 
     if not bf16 and not args.no_bf16:
         # the same steps with BF16 products (gathers from BF16 copies of the fixed

@@ -392,6 +392,22 @@ NMF_API int nmf_server_stats(nmf_server *s, int64_t *completed, int64_t *columns
 /* Finishes the queued work, stops the workers and frees the server. */
 NMF_API void nmf_server_destroy(nmf_server *s);
 
+/* ---------------------------------------------------------------- measurement aid
+ * nmf_probe_gather is not a step of the method: it reads the rows of `table`
+ * (rows x row_bytes, device, row-major, row_bytes a multiple of 16) named by
+ * idx[0..n) (device int32, NULL when n = 0; an index outside [0, rows) reads
+ * the nearest row)
+ * in that order, as the row gathers of the sparse data products do (Section
+ * 4.2, one factor row per stored entry), with no other work, and writes
+ * NMF_PROBE_GATHER_OUT_FLOATS floats of running sums to `out` (device) so
+ * that no load is dead.  Its rate (n * row_bytes / its time) is the gather
+ * ceiling the products are measured against.  Stream-ordered, allocates
+ * nothing; NMF_E_INVAL for bad arguments or n * row_bytes / 16 >= 2^32 less
+ * one launch's worth of work. */
+#define NMF_PROBE_GATHER_OUT_FLOATS (2048 * 256 * 4)
+NMF_API int nmf_probe_gather(const void *table, int64_t rows, int32_t row_bytes, const int32_t *idx, int64_t n,
+                             float *out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

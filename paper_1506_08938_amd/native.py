@@ -27,6 +27,7 @@ EXPORTS = [
     "nmf_server_create", "nmf_server_submit", "nmf_server_poll", "nmf_server_poll_times", "nmf_server_wait",
     "nmf_server_stats", "nmf_server_destroy",
     "nmf_basis_create", "nmf_foldin", "nmf_basis_destroy", "nmf_foldin_noalloc",
+    "nmf_probe_gather",
 ]
 
 
@@ -158,6 +159,7 @@ def lib():
         L.nmf_foldin_noalloc.argtypes = [_vp, ctypes.POINTER(NmfMatrix), _vp, _vp, _vp]
         L.nmf_basis_destroy.argtypes = [_vp]
         L.nmf_basis_destroy.restype = None
+        L.nmf_probe_gather.argtypes = [_vp, ctypes.c_int64, ctypes.c_int32, _vp, ctypes.c_int64, _vp, _vp]
         _lib = L
     return _lib
 
@@ -298,6 +300,27 @@ def product(V: DeviceMatrix, A, trans, precision=NMF_FP32):
     check(lib().nmf_product(ctypes.byref(V.m), int(trans), r, _ptr(A), precision, _ptr(P),
                             stream_ptr()))
     return P
+
+
+PROBE_GATHER_OUT_FLOATS = 2048 * 256 * 4
+
+
+def probe_gather(table, idx, out=None):
+    """Measurement aid (not a step of the method): reads the rows of `table`
+    (2-D device tensor, rows of a multiple of 16 bytes) named by `idx` (int32
+    device tensor) in that order; returns the float32 output buffer of
+    running sums."""
+    torch = _torch()
+    if not isinstance(table, torch.Tensor) or not table.is_cuda or not table.is_contiguous() or table.dim() != 2:
+        raise TypeError("table must be a contiguous 2-D CUDA (HIP) tensor")
+    _dev(idx, torch.int32, "idx")
+    if out is None:
+        out = torch.empty(PROBE_GATHER_OUT_FLOATS, dtype=torch.float32, device=table.device)
+    _dev(out, torch.float32, "out", (PROBE_GATHER_OUT_FLOATS,))
+    row_bytes = table.shape[1] * table.element_size()
+    check(lib().nmf_probe_gather(_ptr(table), table.shape[0], row_bytes, _ptr(idx), idx.numel(), _ptr(out),
+                                 stream_ptr()))
+    return out
 
 
 def reg(l1_w=0.0, l2_w=0.0, l1_h=0.0, l2_h=0.0) -> NmfReg:

@@ -113,3 +113,14 @@ def test_automatic_layout_follows_the_tuned_table():
             assert native.layout(r, c + 1) == (E, L)
             if j:
                 assert native.layout(r, c - 1)[1] == capped(rows[i][j - 1], r)
+
+
+def test_gather_probe_arguments_are_checked_on_host():
+    L = native.lib()
+    fake = ctypes.c_void_p(16)  # never dereferenced: every call below fails its host checks
+    assert L.nmf_probe_gather(None, 10, 16, fake, 4, fake, None) == native.NMF_E_INVAL
+    assert L.nmf_probe_gather(fake, 10, 24, fake, 4, fake, None) == native.NMF_E_INVAL  # not a multiple of 16
+    assert "multiple of 16" in native.last_error()
+    assert L.nmf_probe_gather(fake, 0, 16, fake, 4, fake, None) == native.NMF_E_INVAL
+    assert L.nmf_probe_gather(fake, 10, 16, fake, -1, fake, None) == native.NMF_E_INVAL
+    assert L.nmf_probe_gather(fake, 10, 400, fake, 1 << 30, fake, None) == native.NMF_E_INVAL  # too much work
