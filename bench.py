@@ -94,21 +94,47 @@ def kernel_source_hash(L):
     return h.hexdigest()
 
 
+def summary_fields(name):
+    """The "- key: value" lines of a committed counter summary (empty if absent)."""
+    path = os.path.join(ROOT, "profiles", name)
+    fields = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            for line in f:
+                if line.startswith("- ") and ": " in line:
+                    k, v = line[2:].split(": ", 1)
+                    fields[k.strip()] = v.strip().strip("`")
+    return fields
+
+
+def sources_hash(rels):
+    import hashlib
+    h = hashlib.sha256()
+    for rel in rels:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def measured_traffic(kernel, L):
     """HBM bytes per launch of `kernel` from the committed counter summary,
     or None when there is none or the kernel's sources changed since."""
-    path = os.path.join(ROOT, "profiles", "k_nqp_sparse_r100_hbm_traffic.md")
-    if not os.path.exists(path):
-        return None
-    fields = {}
-    with open(path) as f:
-        for line in f:
-            if line.startswith("- ") and ": " in line:
-                k, v = line[2:].split(": ", 1)
-                fields[k.strip()] = v.strip().strip("`")
+    fields = summary_fields("k_nqp_sparse_r100_hbm_traffic.md")
     if fields.get("kernel") != kernel or fields.get("source_sha256") != kernel_source_hash(L):
         return None
     return float(fields["traffic_bytes_per_launch"])
+
+
+def measured_product_traffic():
+    """HBM bytes per step of the sparse product phase (k_spmm both halves and
+    the hot columns' k_dense) from the committed counter summary, or None when
+    there is none or their sources changed since."""
+    fields = summary_fields("product_phase_sparse_r100_hbm_traffic.md")
+    src = ["paper_1506_08938_amd/csrc/k_spmm.hip", "paper_1506_08938_amd/csrc/k_dense.hip",
+           "paper_1506_08938_amd/build.py"]
+    if fields.get("kernel") != "product phase" or fields.get("source_sha256") != sources_hash(src):
+        return None
+    return float(fields["traffic_bytes_per_step"])
 
 
 def foldin_solve_roofline(native, synth, torch, W, m, r, seed, ncols=8192):
@@ -889,7 +915,7 @@ def main():
             "peak": 8e12,
             "unit": "B/s",
             "frac": prod_bytes / prod_s / 8e12,
-            "traffic": None,
+            "traffic": measured_product_traffic() if not bf16 else None,
             "algorithmic_bytes_per_step": prod_bytes,
             "ms_per_step": prod_s * 1e3,
         },
