@@ -39,6 +39,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--cpu-ite
        python bench.py --calibrate-copy   (1 GiB device copy, for counter scaling)
 """
 import argparse
+import gc
 import json
 import os
 import sys
@@ -224,20 +225,32 @@ def serving_leg(native, synth, torch, n_req, loads=(0.5,), seed=5005, n_warm=Non
         reset_fits()
         S = native.Server(basis, hbm_budget=8 << 30, max_slots=slots, max_batch_cols=batch_cols)
         tickets = []
-        t0 = time.perf_counter()
-        t_first = None
-        for i in range(total):
-            if arrivals is not None:
-                while time.perf_counter() - t0 < arrivals[i]:
-                    pass
-            if i == n_warm:
-                t_first = time.perf_counter()
-            tickets.append(submit(S, i))
-        S.wait()
-        t_end = time.perf_counter()
+        lag = np.zeros(total)  # how late each submission left the load generator (s)
+        # A full pass of Python's garbage collector inside the submission loop
+        # stalls the load generator for tens of milliseconds, and the overdue
+        # requests then arrive as one burst: it is kept out of the timed loop.
+        gc.collect()
+        gc.disable()
+        try:
+            t0 = time.perf_counter()
+            t_first = None
+            for i in range(total):
+                if arrivals is not None:
+                    while time.perf_counter() - t0 < arrivals[i]:
+                        pass
+                    lag[i] = time.perf_counter() - t0 - arrivals[i]
+                if i == n_warm:
+                    t_first = time.perf_counter()
+                tickets.append(submit(S, i))
+            S.wait()
+            t_end = time.perf_counter()
+        finally:
+            gc.enable()
         tl = np.array([S.poll_times(t)[1] for t in tickets])  # queued, launch, device, latency (ms)
         st = S.stats()
         S.close()
+        st["submit_lag_ms"] = {"p99": float(np.percentile(lag[n_warm:], 99) * 1e3),
+                               "max": float(lag[n_warm:].max() * 1e3)}
         return t_end - t_first, tl[n_warm:], st
 
     meas = slice(n_warm, total)
@@ -274,7 +287,8 @@ def serving_leg(native, synth, torch, n_req, loads=(0.5,), seed=5005, n_warm=Non
             "requests_per_s": n_req / el,
             "fold_in_p50_ms": float(np.percentile(lf, 50)), "fold_in_p99_ms": float(np.percentile(lf, 99)),
             "fit_p50_ms": float(np.percentile(lat[~fold], 50)) if (~fold).any() else None,
-            "batches": st["batches"], "p99_tail_median_breakdown": tail, "by_size_decile": dec})
+            "batches": st["batches"], "p99_tail_median_breakdown": tail, "by_size_decile": dec,
+            "submit_lag_ms": st["submit_lag_ms"]})
         log(f"[bench] load {ld}: {rate:.0f} req/s, fold-in p50 {per_load[-1]['fold_in_p50_ms']:.3f} ms "
             f"p99 {per_load[-1]['fold_in_p99_ms']:.3f} ms")
     basis.close()
