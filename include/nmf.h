@@ -347,10 +347,13 @@ NMF_API int nmf_foldin_noalloc(const nmf_basis *B, const nmf_matrix *Vnew, float
  * default): streams beyond that would share hardware queues, whose work runs
  * in order.  Requests arriving while others run are picked up by the next
  * free slot, so batches overlap on the device.  A request's result does not
- * depend on what it is batched with.  Batches allocate their workspace
- * stream-ordered from the device's default memory pool; nmf_server_create
- * sets that pool's release threshold to keep what it holds (a process-wide
- * setting of the pool).
+ * depend on what it is batched with.  A fold-in batch runs in one of its
+ * slot's two reused workspaces (device memory and page-locked host memory
+ * for its descriptors, grown to the largest batch they have held and kept,
+ * beside the budgeted footprints, until nmf_server_destroy); fit batches
+ * allocate theirs stream-ordered from the device's default memory pool, and
+ * nmf_server_create sets that pool's release threshold to keep what it
+ * holds (a process-wide setting of the pool).
  * Request memory is the caller's (device pointers): its inputs must be
  * written before submission (workers run on their own streams, unordered with
  * the caller's) and it must stay valid until the request is done.  Fold-in requests use the basis' options; fit requests
