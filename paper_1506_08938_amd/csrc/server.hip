@@ -191,7 +191,17 @@ int launch_foldin_batch(nmf_server *S, InFlight &F, Slot *sl) {
         ctot += req_cols(q->q);
         if (q->q.V.kind == NMF_DENSE) dense_scr = std::max(dense_scr, dense_scratch_bytes(B->m, q->q.V.cols, r));
     }
-    const int chunk = bnqp_chunk_cols(B->var.L, B->opt.fast_break_cols);
+    // Chunks of the solve: a block takes one at a time, so a batch of fewer
+    // columns than the chip has lane groups is cut finer (about two chunks
+    // per CU, whole waves' worth of lane groups) to run on every CU instead
+    // of a few; with the fast-break, whole units as always.  Only which block
+    // solves a column depends on it, never the column's arithmetic.
+    int chunk = bnqp_chunk_cols(B->var.L, B->opt.fast_break_cols);
+    if (B->opt.fast_break_cols <= 1) {
+        const int64_t gw = 64 / B->var.L;  // lane groups of a wave
+        const int64_t want = (ctot + 2 * (int64_t)device_cu_count() - 1) / (2 * (int64_t)device_cu_count());
+        chunk = (int)std::min<int64_t>(chunk, std::max<int64_t>(gw, (want + gw - 1) / gw * gw));
+    }
     int64_t off = 0;
     for (size_t j = 0; j < F.batch.size(); j++) {
         const nmf_request &q = F.batch[j]->q;
@@ -391,6 +401,12 @@ void completer(nmf_server *S, Slot *sl) {
         }
         hipError_t e = F->ev ? hipEventSynchronize(F->ev) : hipStreamSynchronize(sl->s);
         if (F->ev) (void)hipEventDestroy(F->ev);
+        // the batch's workspace is free before the slot counts the batch as
+        // done, so the launcher never finds a slot with room and no workspace
+        if (F->work >= 0) {
+            std::lock_guard<std::mutex> lk(sl->mu);
+            sl->work[F->work].busy = false;
+        }
         if (F->fits) batched_fit_end(F->fits);
         int st = F->status;
         std::string msg = F->msg;
@@ -419,7 +435,6 @@ void completer(nmf_server *S, Slot *sl) {
         }
         {
             std::lock_guard<std::mutex> lk(sl->mu);
-            if (F->work >= 0) sl->work[F->work].busy = false;  // the batch's work has run
             sl->inflight.pop_front();  // releases the batch's host arrays
         }
         sl->cv.notify_all();

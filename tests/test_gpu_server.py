@@ -193,3 +193,29 @@ def test_fit_requests_batched_together_equal_nmf_fit(basis):
         assert np.array_equal(H(Wd), H(W2)) and np.array_equal(H(Hd), H(H2))
     print(f"{len(fits)} fit requests in {batches} batches")
     assert batches < len(fits)
+
+
+def test_stream_of_small_requests_all_succeed_and_match_direct(basis):
+    """Thousands of small fold-in requests submitted at once keep every slot
+    at its limit of batches in flight, each batch in a reused workspace:
+    every request completes without error and equals the direct fold-in."""
+    import torch
+    from paper_1506_08938_amd import native as nat
+    B, W = basis
+    m, r = W.shape
+    reqs = [nat.sparse_request(synth.foldin_columns(m, c, 30, seed=900 + c), m) for c in (1, 3, 7, 20, 64)]
+    direct = [H(B.foldin(q)) for q in reqs]
+    S = nat.Server(B, hbm_budget=1 << 30, max_slots=3, max_batch_cols=256)
+    outs, tickets = [], []
+    for i in range(3000):
+        k = i % len(reqs)
+        o = torch.empty((reqs[k].m.cols, r), device="cuda")
+        outs.append((k, o))
+        tickets.append(S.submit_foldin(reqs[k], o))
+    for t in tickets:
+        S.wait(t)  # raises on a failed request
+    st = S.stats()
+    S.close()
+    assert st["completed"] == 3000
+    for k, o in outs[::37]:
+        assert np.array_equal(H(o), direct[k])
