@@ -408,8 +408,19 @@ NMF_API void nmf_server_destroy(nmf_server *s);
  * nothing; NMF_E_INVAL for bad arguments or n * row_bytes / 16 >= 2^32 less
  * one launch's worth of work. */
 #define NMF_PROBE_GATHER_OUT_FLOATS (2048 * 256 * 4)
+/* nmf_dense_product_time (measurement aid for the autotuner): the dense
+ * product of nmf_product (V m x n FP32 row-major with leading dimension ld,
+ * device; A the fixed factor, device, (trans ? n : m) x r) with its split-K
+ * slice count forced to nsplit (0: the library's own choice, the tuned table
+ * or its rule), timed with HIP events over reps launches after one warm-up
+ * (BF16: V converted once beforehand, untimed; the factor's BF16 copy and
+ * the slices' sum are part of each launch).  *ms: milliseconds per launch.
+ * Allocates stream-ordered and synchronises the stream. */
 NMF_API int nmf_probe_gather(const void *table, int64_t rows, int32_t row_bytes, const int32_t *idx, int64_t n,
                              float *out, void *stream);
+NMF_API int nmf_dense_product_time(const float *V, int64_t m, int64_t n, int64_t ld, int32_t trans, int32_t r,
+                                   const float *A, int32_t precision, int32_t nsplit, int32_t reps, double *ms,
+                                   void *stream);
 
 #ifdef __cplusplus
 }

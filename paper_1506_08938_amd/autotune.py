@@ -16,6 +16,9 @@ of slow columns).  A layout's score is the sum of its two times.
 
 Usage (on the GPU):  python -m paper_1506_08938_amd.autotune OUT_DIR
 writes OUT_DIR/nqp_tuned.h and OUT_DIR/nqp_tuned.json;
+python -m paper_1506_08938_amd.autotune --dense OUT_DIR writes the dense
+product's split-K table OUT_DIR/dense_tuned.h (and dense_tuned.json), and
+--dense-from-json JSON OUT_DIR re-derives it from a saved sweep;
 python -m paper_1506_08938_amd.autotune --from-json JSON OUT_DIR re-derives
 the header from a saved sweep.  The library compiles csrc/nqp_tuned.h (and
 csrc/nqp_tuned.json keeps the sweep it came from).
@@ -142,7 +145,137 @@ def from_json(path):
     return table
 
 
+# ---------------------------------------------------------------------------- dense split-K
+# The dense product's one free tile parameter per shape is its split-K slice
+# count (a block computes 128 rows of P by 32 x NT columns over one slice of
+# k; the slices' partial products are summed in slice order).  For a grid of
+# shapes (rows of P, k) and column tiles NT = 1..4 it times every candidate
+# count for each of the three kernel instantiations -- FP32 reading V (the
+# W-update), FP32 reading V' k-major (the H-update), BF16 -- and records the
+# fastest; the library's rule competes as candidate 0 and is kept (0 in the
+# table) unless a count beats it by more than DENSE_RULE_MARGIN (then, of the
+# counts within DENSE_MARGIN of the fastest, the fewest slices: less partial
+# traffic).  A table entry is applied to shapes around its grid point, where
+# an optimum a few percent deep does not carry over (measured at 20000 x 10000,
+# r = 64, BF16: the neighbouring grid points' 3-4% better counts were 7-10%
+# slower there), so only clear wins replace the rule.  Shapes beyond
+# DENSE_MAX_ELEMS entries of V keep the rule.
+DENSE_C = [128, 512, 2048, 8192, 32768]
+DENSE_K = [256, 1024, 4096, 16384, 65536]
+DENSE_NT = [1, 2, 3, 4]
+DENSE_KERNELS = [("fp32", 0, 1), ("fp32_vt", 0, 0), ("bf16", 1, 1)]  # (name, precision, trans)
+DENSE_MAX_ELEMS = 1 << 30
+DENSE_MARGIN = 1.02
+DENSE_RULE_MARGIN = 1.10
+DENSE_REPS = 5
+
+
+def dense_candidates(K):
+    most = min(512, (K + 63) // 64)
+    return sorted({1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512} & set(range(1, most + 1)))
+
+
+def dense_choose(times):
+    """0 (the rule) unless a slice count beats it by more than
+    DENSE_RULE_MARGIN; else the fewest slices within DENSE_MARGIN of the
+    fastest."""
+    best_t = min(times.values())
+    if times[0] <= DENSE_RULE_MARGIN * best_t:
+        return 0
+    return min(ns for ns, t in times.items() if ns > 0 and t <= DENSE_MARGIN * best_t)
+
+
+def dense_from_json(path):
+    """The table of an earlier sweep (its dense_tuned.json), re-chosen."""
+    with open(path) as f:
+        raw = json.load(f)
+    table = {}
+    for key, v in raw.items():
+        k, nt, C, K = key.split(",")
+        times = {int(ns): t for ns, t in v["ms"].items()}
+        table[(k, int(nt), int(C), int(K))] = (dense_choose(times), times)
+    return table
+
+
+def dense_sweep(log=print):
+    import torch
+    from . import native
+    table = {}
+    g = torch.Generator(device="cuda")
+    g.manual_seed(4242)
+    for C in DENSE_C:
+        for K in DENSE_K:
+            if C * K > DENSE_MAX_ELEMS:
+                continue
+            for kname, prec, trans in DENSE_KERNELS:
+                # trans = 1: P (m x r) = V A, C = m, K = n; trans = 0: P (n x r) = V' A, C = n, K = m
+                m, n = (C, K) if trans else (K, C)
+                V = torch.rand((m, n), device="cuda", generator=g)
+                for nt in DENSE_NT:
+                    r = 32 * nt
+                    A = torch.rand((K, r), device="cuda", generator=g)
+                    times = {}
+                    for ns in [0] + dense_candidates(K):
+                        ts = sorted(native.dense_product_time(V, A, trans, prec, ns, DENSE_REPS) for _ in range(3))
+                        times[ns] = ts[1]
+                    best = dense_choose(times)
+                    table[(kname, nt, C, K)] = (best, times)
+                    log(f"{kname:8s} NT={nt} C={C:6d} K={K:6d}: best {best:3d} slices {times[best]:.4f} ms "
+                        f"(1 slice {times[1]:.4f} ms, rule {times[0]:.4f} ms)")
+                    del A
+                del V
+                torch.cuda.empty_cache()
+    return table
+
+
+def dense_write(table, out_dir, command):
+    kn = [k for k, _, _ in DENSE_KERNELS]
+    lines = [
+        "// Split-K slices of the dense product, measured by autotune.py --dense on an",
+        "// MI355X at each grid point: 0 keeps the rule in k_dense.hip (not measured, or",
+        "// no count beat it by more than 10%); k_dense.hip reads an entry as the block",
+        "// count it gave at its grid point.",
+        f"// Command: {command}",
+        "#pragma once",
+        "",
+        "namespace nmfi {",
+        "",
+        f"constexpr long long kDenseTunedC[] = {{{', '.join(str(c) for c in DENSE_C)}}};",
+        f"constexpr long long kDenseTunedK[] = {{{', '.join(str(k) for k in DENSE_K)}}};",
+        "// [kernel: 0 FP32 V, 1 FP32 V' (k-major), 2 BF16][column tiles - 1][C index][K index]",
+        f"constexpr int kDenseTunedSplit[3][{len(DENSE_NT)}][{len(DENSE_C)}][{len(DENSE_K)}] = {{",
+    ]
+    for k in kn:
+        lines.append("    {")
+        for nt in DENSE_NT:
+            rows = []
+            for C in DENSE_C:
+                rows.append("{" + ", ".join(str(table.get((k, nt, C, K), (0,))[0]) for K in DENSE_K) + "}")
+            lines.append("        {" + ", ".join(rows) + "},")
+        lines.append("    },")
+    lines += ["};", "", "}  // namespace nmfi", ""]
+    with open(os.path.join(out_dir, "dense_tuned.h"), "w") as f:
+        f.write("\n".join(lines))
+    with open(os.path.join(out_dir, "dense_tuned.json"), "w") as f:
+        json.dump({f"{k},{nt},{C},{K}": {"best": v[0], "ms": {str(ns): t for ns, t in v[1].items()}}
+                   for (k, nt, C, K), v in table.items()}, f, indent=1)
+
+
 def main():
+    if len(sys.argv) > 3 and sys.argv[1] == "--dense-from-json":
+        src, out = sys.argv[2], sys.argv[3]
+        dense_write(dense_from_json(src), out,
+                    f"python -m paper_1506_08938_amd.autotune --dense OUT_DIR (sweep on the GPU), then "
+                    f"--dense-from-json {os.path.basename(src)}")
+        return
+    if len(sys.argv) > 2 and sys.argv[1] == "--dense":
+        out = sys.argv[2]
+        os.makedirs(out, exist_ok=True)
+        t0 = time.perf_counter()
+        table = dense_sweep(lambda s: print(s, flush=True))
+        dense_write(table, out, "python -m paper_1506_08938_amd.autotune --dense " + out)
+        print(f"dense autotune done in {time.perf_counter() - t0:.1f}s", flush=True)
+        return
     if len(sys.argv) > 3 and sys.argv[1] == "--from-json":
         src, out = sys.argv[2], sys.argv[3]
         write(from_json(src), out,

@@ -154,7 +154,7 @@ int BatchedFit::prepare(int32_t count_, const nmf_problem *pr, const nmf_opts *o
         slot[p].inner = place(8);
         for (int h = 0; h < 2; h++) {  // split-K partials of each half's product
             const int64_t C = h == 0 ? n : m, K = h == 0 ? m : n;
-            const int64_t kc = dense_kchunk(C, K);
+            const int64_t kc = dense_kchunk(C, K, q.r, bf16, h == 0 && !bf16);
             const int64_t ns = (K + kc - 1) / kc;
             slot[p].kpart[h] = ns > 1 ? place((size_t)ns * C * r * 4) : 0;
         }
@@ -189,7 +189,7 @@ int BatchedFit::prepare(int32_t count_, const nmf_problem *pr, const nmf_opts *o
             for (int c = 0; c < g.nchunks; c++) hl[h].gram_items.push_back({p, c});
             // BF16 reads the copy along k: V16t (n x m) for the H-update, V16 for the W-update
             const void *V = bf16 ? dptr(H ? slot[p].V16t : slot[p].V16) : (const void *)q.V.dense;
-            const int64_t kc = dense_kchunk(C, k);
+            const int64_t kc = dense_kchunk(C, k, r, bf16, H && !bf16);
             const int ns = (int)((k + kc - 1) / kc);
             const int64_t lda16 = (std::max(m, n) + 63) / 64 * 64;
             BProdProb prd{V, bf16 ? k : q.V.ld, C, k, A, r, (float *)dptr(slot[p].P),

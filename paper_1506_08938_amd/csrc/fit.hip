@@ -180,6 +180,52 @@ extern "C" int nmf_gram(const float *A, int64_t k, int32_t r, float l2, int32_t 
     return NMF_OK;
 }
 
+extern "C" int nmf_dense_product_time(const float *V, int64_t m, int64_t n, int64_t ld, int32_t trans, int32_t r,
+                                      const float *A, int32_t precision, int32_t nsplit, int32_t reps, double *ms,
+                                      void *stream) {
+    if (!V || !A || !ms) return fail(NMF_E_INVAL, "V, A and ms must be non-NULL");
+    if (m < 1 || n < 1 || ld < n) return fail(NMF_E_INVAL, "bad dense V (m, n >= 1, ld >= n)");
+    if (r < 1 || r > NMF_MAX_RANK) return fail(NMF_E_INVAL, "r must be in [1, %d]", NMF_MAX_RANK);
+    if (trans != 0 && trans != 1) return fail(NMF_E_INVAL, "trans must be 0 or 1");
+    if (precision != NMF_FP32 && precision != NMF_BF16) return fail(NMF_E_INVAL, "bad precision");
+    if (nsplit < 0 || nsplit > 512) return fail(NMF_E_INVAL, "nsplit must be in [0, 512]");
+    if (reps < 1) return fail(NMF_E_INVAL, "reps must be >= 1");
+    hipStream_t s = (hipStream_t)stream;
+    const bool bf16 = precision == NMF_BF16;
+    const int64_t C = trans ? m : n;
+    char *buf = nullptr;
+    const size_t pb = ((size_t)C * r * 4 + 255) & ~(size_t)255;
+    const size_t vb = bf16 ? (((size_t)m * n * 2 + 255) & ~(size_t)255) : 0;
+    const size_t sb = dense_scratch_bytes_forced(m, n, r, nsplit);
+    NMF_HIP(hipMallocAsync((void **)&buf, pb + vb + sb, s));
+    float *P = (float *)buf;
+    __bf16 *v16 = bf16 ? (__bf16 *)(buf + pb) : nullptr;
+    float *scratch = (float *)(buf + pb + vb);
+    hipError_t e = hipSuccess;
+    if (bf16) e = trans ? launch_to_bf16(V, m, n, ld, v16, s) : launch_to_bf16_t(V, m, n, ld, v16, s);
+    const void *src = bf16 ? (const void *)v16 : (const void *)V;
+    auto once = [&]() {
+        return launch_dense_product(src, bf16, m, n, bf16 ? n : ld, (bf16 && !trans) ? v16 : nullptr, trans, A, r,
+                                    P, scratch, s, nsplit);
+    };
+    if (e == hipSuccess) e = once();  // warm-up
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    if (e == hipSuccess) e = hipEventCreate(&ev[0]);
+    if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+    if (e == hipSuccess) e = hipEventRecord(ev[0], s);
+    for (int i = 0; i < reps && e == hipSuccess; i++) e = once();
+    if (e == hipSuccess) e = hipEventRecord(ev[1], s);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+    float el = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&el, ev[0], ev[1]);
+    for (hipEvent_t x : ev)
+        if (x) (void)hipEventDestroy(x);
+    (void)hipFreeAsync(buf, s);
+    if (e != hipSuccess) return hip_fail(e, "nmf_dense_product_time");
+    *ms = (double)el / reps;
+    return NMF_OK;
+}
+
 extern "C" int nmf_product(const nmf_matrix *V, int32_t trans, int32_t r, const float *A,
                            int32_t precision, float *P, void *stream) {
     if (int st = validate_matrix(V, true)) return st;

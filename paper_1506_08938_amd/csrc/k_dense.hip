@@ -20,8 +20,11 @@
 // result is deterministic; a P entry's arithmetic depends only on its
 // slice's k range, never on the block that computes it.
 #include "kernels_common.h"
+#include <math.h>
+
 #include <algorithm>
 
+#include "dense_tuned.h"
 #include "nmf_internal.h"
 
 namespace nmfi {
@@ -427,40 +430,85 @@ hipError_t launch_to_bf16(const float *x, int64_t rows, int64_t cols, int64_t ld
     return hipGetLastError();
 }
 
-// split-K factor: as many slices as keep the grid within one round of
-// resident blocks (a block uses one stage buffer of LDS, so four fit per CU:
-// 1024 on the chip), at least 256 k per slice.  Measured at 20000 x 10000,
-// r = 64: 5-8% faster than double-buffered LDS with a 2048 (FP32) or 1024
-// (BF16) block target rounded up; the same rule serves both precisions.
+// split-K factor without a measurement: as many slices as keep the grid
+// within one round of resident blocks (a block uses one stage buffer of LDS,
+// so four fit per CU: 1024 on the chip), at least 256 k per slice.
+// Measured at 20000 x 10000, r = 64: 5-8% faster than double-buffered LDS
+// with a 2048 (FP32) or 1024 (BF16) block target rounded up.
 constexpr int64_t DENSE_SPLIT_BLOCKS = 1024;
-int dense_nsplit(int64_t C, int64_t K) {
+static int dense_rule_nsplit(int64_t C, int64_t K) {
     const int64_t rb = (C + DENSE_BM - 1) / DENSE_BM;
     int64_t ns = DENSE_SPLIT_BLOCKS / rb;
     const int64_t maxs = (K + 255) / 256;
     if (ns > maxs) ns = maxs;
     if (ns < 1) ns = 1;
-    if (ns > 512) ns = 512;
     return (int)ns;
 }
 
-// slice length: a multiple of 64 (both stage depths)
-int64_t dense_kchunk(int64_t C, int64_t K) {
-    const int ns = dense_nsplit(C, K);
+// index of the grid value nearest v in log scale
+static int nearest_log(const long long *grid, int n, int64_t v) {
+    int best = 0;
+    double bd = 1e300;
+    for (int i = 0; i < n; i++) {
+        const double d = fabs(log((double)(v > 0 ? v : 1)) - log((double)grid[i]));
+        if (d < bd) { bd = d; best = i; }
+    }
+    return best;
+}
+
+// slices of the split-K: from the autotuned table at the grid point nearest
+// (C, K) in log scale, for the kernel instantiation and the column tiles --
+// read as the block count it gave there (slices x the grid point's 128-row
+// blocks) and divided by this product's row blocks, rounded down (the slices
+// a product needs to fill the chip fall as its rows grow, and one block past
+// a round of resident blocks costs a whole extra round: measured at 20000 x
+// 10000, r = 64, 13 slices of the H-update's 79 row blocks, 1027 blocks,
+// took 352 us against 300 us for 12) -- else the rule; at least 64 k per
+// slice, at most 512 slices
+int dense_nsplit(int64_t C, int64_t K, int r, int bf16, int xt) {
+    const int nt = std::min(4, std::max(1, (r + 31) / 32));
+    const int kern = bf16 ? 2 : (xt ? 1 : 0);
+    constexpr int nC = (int)(sizeof kDenseTunedC / sizeof(long long));
+    constexpr int nK = (int)(sizeof kDenseTunedK / sizeof(long long));
+    const int ci = nearest_log(kDenseTunedC, nC, C);
+    const int64_t tuned = kDenseTunedSplit[kern][nt - 1][ci][nearest_log(kDenseTunedK, nK, K)];
+    int64_t ns;
+    if (tuned > 0) {
+        const int64_t blocks = tuned * ((kDenseTunedC[ci] + DENSE_BM - 1) / DENSE_BM);
+        const int64_t rb = (C + DENSE_BM - 1) / DENSE_BM;
+        ns = blocks / rb;
+    } else {
+        ns = dense_rule_nsplit(C, K);
+    }
+    const int64_t maxs = (K + 63) / 64;
+    if (ns > maxs) ns = maxs;
+    if (ns > 512) ns = 512;
+    if (ns < 1) ns = 1;
+    return (int)ns;
+}
+
+// slice length for ns slices: a multiple of 64 (both stage depths)
+static int64_t kchunk_for(int64_t K, int64_t ns) {
     int64_t kchunk = (K + ns - 1) / ns;
     kchunk = ((kchunk + 63) / 64) * 64;
     return kchunk < 64 ? 64 : kchunk;
 }
+int64_t dense_kchunk(int64_t C, int64_t K, int r, int bf16, int xt) {
+    return kchunk_for(K, dense_nsplit(C, K, r, bf16, xt));
+}
 
-// Split-K partials of the larger half, then the BF16 factor copy (R32 x
-// lda16 with lda16 = max(m, n) rounded up to 64).
+// Split-K partials of the larger half (either precision), then the BF16
+// factor copy (R32 x lda16 with lda16 = max(m, n) rounded up to 64).
 static size_t dense_partial_bytes(int64_t m, int64_t n, int r) {
     // slices actually used (a single slice writes P directly)
-    auto used = [](int64_t C, int64_t K) {
-        const int64_t kc = dense_kchunk(C, K);
+    auto used = [&](int64_t C, int64_t K, int bf16, int xt) {
+        const int64_t kc = dense_kchunk(C, K, r, bf16, xt);
         const int64_t ns = K > 0 ? (K + kc - 1) / kc : 0;
         return ns > 1 ? ns * C : 0;
     };
-    const int64_t most = std::max(used(n, m), used(m, n));
+    // H-update: C = n, K = m (FP32 reads V' k-major); W-update: C = m, K = n
+    const int64_t most = std::max(std::max(used(n, m, 0, 1), used(m, n, 0, 0)),
+                                  std::max(used(n, m, 1, 0), used(m, n, 1, 0)));
     return (((size_t)most * r * sizeof(float)) + 255) & ~(size_t)255;
 }
 static int64_t dense_lda16(int64_t m, int64_t n) {
@@ -470,6 +518,23 @@ static int64_t dense_lda16(int64_t m, int64_t n) {
 size_t dense_scratch_bytes(int64_t m, int64_t n, int r) {
     const int R32 = (r + 31) / 32 * 32;
     return dense_partial_bytes(m, n, r) + (size_t)R32 * dense_lda16(m, n) * 2 + 256;
+}
+// ... with the slices forced (force_nsplit > 0, either half): the partials
+// region grows to hold them
+size_t dense_forced_partial_bytes(int64_t m, int64_t n, int r, int force_nsplit) {
+    size_t b = dense_partial_bytes(m, n, r);
+    if (force_nsplit > 0)
+        for (int h = 0; h < 2; h++) {
+            const int64_t C = h ? m : n, K = h ? n : m;
+            const int64_t kc = kchunk_for(K, std::min<int64_t>(force_nsplit, (K + 63) / 64));
+            const int64_t ns = (K + kc - 1) / kc;
+            if (ns > 1) b = std::max(b, (((size_t)ns * C * r * sizeof(float)) + 255) & ~(size_t)255);
+        }
+    return b;
+}
+size_t dense_scratch_bytes_forced(int64_t m, int64_t n, int r, int force_nsplit) {
+    const int R32 = (r + 31) / 32 * 32;
+    return dense_forced_partial_bytes(m, n, r, force_nsplit) + (size_t)R32 * dense_lda16(m, n) * 2 + 256;
 }
 
 template <int NT>
@@ -495,12 +560,13 @@ int dense_vec_ok(const void *V, int64_t ld, int bf16) {
 // scratch: dense_scratch_bytes(m, n, r) bytes.
 hipError_t launch_dense_product(const void *V, int bf16, int64_t m, int64_t n, int64_t ld,
                                 const __bf16 *V16t, int trans, const float *A, int r, float *P,
-                                float *scratch, hipStream_t s) {
+                                float *scratch, hipStream_t s, int force_nsplit) {
     const bool h_update = trans == 0;
     const int64_t C = h_update ? n : m, K = h_update ? m : n;
     if (C == 0) return hipSuccess;
     if (K == 0) return hipErrorInvalidValue;  // callers reject empty V
-    const int64_t kchunk = dense_kchunk(C, K);
+    const int64_t kchunk = force_nsplit > 0 ? kchunk_for(K, std::min<int64_t>(force_nsplit, (K + 63) / 64))
+                                            : dense_kchunk(C, K, r, bf16, h_update && !bf16);
     const int nsplit = (int)((K + kchunk - 1) / kchunk);
     float *out = nsplit > 1 ? scratch : P;
     const int NT = (r + 31) / 32;
@@ -517,7 +583,7 @@ hipError_t launch_dense_product(const void *V, int bf16, int64_t m, int64_t n, i
         }
         xt = false;
         lda16 = dense_lda16(m, n);
-        A16 = (__bf16 *)((char *)scratch + dense_partial_bytes(m, n, r));
+        A16 = (__bf16 *)((char *)scratch + dense_forced_partial_bytes(m, n, r, force_nsplit));
         hipLaunchKernelGGL(k_factor_t16, dim3((unsigned)((K + 63) / 64)), dim3(256), 0, s, A, K, r,
                            32 * NT, A16, lda16);
         hipError_t e = hipGetLastError();

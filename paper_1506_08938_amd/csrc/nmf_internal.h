@@ -122,14 +122,20 @@ hipError_t launch_gram(const float *A, int64_t k, int r, float l2, int precision
                        float *scratch, hipStream_t s, unsigned long long *counter = nullptr);
 
 size_t dense_scratch_bytes(int64_t m, int64_t n, int r);
+// scratch for a product with its slices forced (the autotuner's timing)
+size_t dense_forced_partial_bytes(int64_t m, int64_t n, int r, int force_nsplit);
+size_t dense_scratch_bytes_forced(int64_t m, int64_t n, int r, int force_nsplit);
 // split-K decomposition of P (C x r) = X (C x K) A shared by the single and
-// batched products, both precisions: nsplit slices of kchunk (a multiple of
-// 64) each
-int dense_nsplit(int64_t C, int64_t K);
-int64_t dense_kchunk(int64_t C, int64_t K);
+// batched products: nsplit slices of kchunk (a multiple of 64) each, from the
+// autotuned table (dense_tuned.h) for the kernel -- bf16, or FP32 reading X
+// k-major (xt: V' in the H-update) or not -- and the rank's column tiles
+int dense_nsplit(int64_t C, int64_t K, int r, int bf16, int xt);
+int64_t dense_kchunk(int64_t C, int64_t K, int r, int bf16, int xt);
+// force_nsplit > 0 (the autotuner): that many slices instead (scratch:
+// dense_scratch_bytes_forced)
 hipError_t launch_dense_product(const void *V, int bf16, int64_t m, int64_t n, int64_t ld,
                                 const __bf16 *V16t, int trans, const float *A, int r, float *P,
-                                float *scratch, hipStream_t s);
+                                float *scratch, hipStream_t s, int force_nsplit = 0);
 hipError_t launch_to_bf16_t(const float *x, int64_t rows, int64_t cols, int64_t ld, __bf16 *y,
                             hipStream_t s);
 hipError_t launch_to_bf16(const float *x, int64_t rows, int64_t cols, int64_t ld, __bf16 *y,

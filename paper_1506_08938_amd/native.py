@@ -27,7 +27,7 @@ EXPORTS = [
     "nmf_server_create", "nmf_server_submit", "nmf_server_poll", "nmf_server_poll_times", "nmf_server_wait",
     "nmf_server_stats", "nmf_server_destroy",
     "nmf_basis_create", "nmf_foldin", "nmf_basis_destroy", "nmf_foldin_noalloc",
-    "nmf_probe_gather",
+    "nmf_probe_gather", "nmf_dense_product_time",
 ]
 
 
@@ -160,6 +160,9 @@ def lib():
         L.nmf_basis_destroy.argtypes = [_vp]
         L.nmf_basis_destroy.restype = None
         L.nmf_probe_gather.argtypes = [_vp, ctypes.c_int64, ctypes.c_int32, _vp, ctypes.c_int64, _vp, _vp]
+        L.nmf_dense_product_time.argtypes = [_vp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
+                                             ctypes.c_int32, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.POINTER(ctypes.c_double), _vp]
         _lib = L
     return _lib
 
@@ -321,6 +324,19 @@ def probe_gather(table, idx, out=None):
     check(lib().nmf_probe_gather(_ptr(table), table.shape[0], row_bytes, _ptr(idx), idx.numel(), _ptr(out),
                                  stream_ptr()))
     return out
+
+
+def dense_product_time(V, A, trans, precision=NMF_FP32, nsplit=0, reps=5):
+    """Measurement aid for the autotuner: ms per launch of the dense product
+    with its split-K slice count forced (0: the library's choice)."""
+    torch = _torch()
+    _dev(V, torch.float32, "V")
+    _dev(A, torch.float32, "A")
+    m, n = V.shape
+    ms = ctypes.c_double()
+    check(lib().nmf_dense_product_time(_ptr(V), m, n, n, int(trans), A.shape[1], _ptr(A), precision, nsplit,
+                                       reps, ctypes.byref(ms), stream_ptr()))
+    return ms.value
 
 
 def reg(l1_w=0.0, l2_w=0.0, l1_h=0.0, l2_h=0.0) -> NmfReg:

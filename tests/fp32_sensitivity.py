@@ -105,7 +105,15 @@ def rel_fro(a, b):
 MODES = ("round", "ulp", "jitter")
 
 
-def spread(V, r, reg, W0, Ht0, T, seeds=(1, 2, 3), modes=MODES, **opts):
+# Jitter seeds of a spread: the largest change over the seeds estimates the
+# top of the oracle's own FP32 variability, and three under-sample it -- on
+# the dense regularised test problem the one-step |dJ|/J over 40 seeds has
+# median 2.5e-5, 90th percentile 8.1e-5, maximum 1.6e-4, while seeds 1-3 give
+# at most 2.4e-5.
+SEEDS = tuple(range(1, 21))
+
+
+def spread(V, r, reg, W0, Ht0, T, seeds=SEEDS, modes=MODES, **opts):
     """Largest relative change of J, of W and Ht, and (over the T outer
     iterations) of the loss, under the disturbances, against the undisturbed
     float64 run, and of the mean inner iterations per solved column (kbar).

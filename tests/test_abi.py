@@ -124,3 +124,19 @@ def test_gather_probe_arguments_are_checked_on_host():
     assert L.nmf_probe_gather(fake, 0, 16, fake, 4, fake, None) == native.NMF_E_INVAL
     assert L.nmf_probe_gather(fake, 10, 16, fake, -1, fake, None) == native.NMF_E_INVAL
     assert L.nmf_probe_gather(fake, 10, 400, fake, 1 << 30, fake, None) == native.NMF_E_INVAL  # too much work
+
+
+def test_dense_product_time_arguments_are_checked_on_host():
+    L = native.lib()
+    fake = ctypes.c_void_p(16)  # never dereferenced: every call below fails its host checks
+    ms = ctypes.c_double()
+    ok = dict(m=64, n=64, ld=64, trans=1, r=32, prec=0, ns=0, reps=1)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return L.nmf_dense_product_time(fake, a["m"], a["n"], a["ld"], a["trans"], a["r"], fake, a["prec"], a["ns"],
+                                        a["reps"], ctypes.byref(ms), None)
+    assert L.nmf_dense_product_time(None, 64, 64, 64, 1, 32, fake, 0, 0, 1, ctypes.byref(ms), None) == native.NMF_E_INVAL
+    for bad in [dict(trans=2), dict(r=0), dict(r=129), dict(prec=5), dict(ns=-1), dict(ns=513), dict(reps=0),
+                dict(ld=10), dict(m=0)]:
+        assert call(**bad) == native.NMF_E_INVAL, bad

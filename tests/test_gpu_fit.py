@@ -293,7 +293,7 @@ def half_columns(V, A, trans, l1, l2, X0, Xg, opts):
     return e, near_tied(cd)
 
 
-def step_parity(V, r, reg, W0, Ht0, t_before, opts, T=1, seeds=(1, 2, 3)):
+def step_parity(V, r, reg, W0, Ht0, t_before, opts, T=1, seeds=fp32_sensitivity.SEEDS):
     """State after t_before oracle iterations, then T more on both sides and
     in the oracle's disturbed runs.  For T = 1 also each half's columns: the
     H-update from the common start, the W-update from the GPU's new Ht."""
