@@ -20,8 +20,9 @@ gathers of the CSR products), algorithmic bytes per step over its time from
 a separate run with events around every phase, against 8 TB/s; beside it,
 the time of the gather probe (nothing but the same row loads in the same
 orders) over the phase's time, the measured ceiling of the gathers.  The CPU
-baseline is the FP64 oracle timed on the host cores for the first
---cpu-iters outer iterations of the same workload from the same start point.
+baseline is the FP64 oracle timed on the host cores for --cpu-iters outer
+iterations of the same workload from the same start point, after --warmup
+untimed ones (the GPU's warm-up).
 
 The "serving" entry covers the fold-in side of the metric: a basis W
 (100000 x 128) fitted on the device to Gamma-factor data stays resident;
@@ -973,9 +974,17 @@ def main():
         import oracle
         cores = oracle.num_threads()
         T_cpu = args.cpu_iters
-        log(f"[bench] CPU oracle: {T_cpu} outer iterations on {cores} threads")
+        # the same window as the GPU's timed steps: the oracle's own first
+        # `warmup` iterations untimed (their inner-iteration counts are higher),
+        # then T_cpu timed from the oracle's state
+        W_c, H_c = wl["W0"], wl["Ht0"]
+        if args.warmup:
+            pre = oracle.nmf_fit(V, r, wl["reg"], W_c, H_c, T=args.warmup, max_inner=100, eps=1e-3, ls_guard=1,
+                                 want_trace=False)
+            W_c, H_c = pre["W"], pre["Ht"]
+        log(f"[bench] CPU oracle: {T_cpu} outer iterations after {args.warmup} untimed, on {cores} threads")
         tc = time.perf_counter()
-        res = oracle.nmf_fit(V, r, wl["reg"], wl["W0"], wl["Ht0"], T=T_cpu, max_inner=100,
+        res = oracle.nmf_fit(V, r, wl["reg"], W_c, H_c, T=T_cpu, max_inner=100,
                              eps=1e-3, ls_guard=1, want_trace=False)
         tcpu = time.perf_counter() - tc
         kbar_cpu = res["inner"].sum() / (T_cpu * (m + n))
@@ -984,9 +993,11 @@ def main():
             "unit": "column NNLS solves/s",
             "cores": cores,
             "kind": "oracle",
-            "sample": f"the first {T_cpu} outer iterations ({T_cpu * (m + n)} column NQP solves "
-                      f"plus the Gram and CSR products, FP64) of the same workload from the same "
-                      f"start point; {tcpu:.1f}s; kbar {kbar_cpu:.3f}",
+            "sample": f"outer iterations {args.warmup + 1}..{args.warmup + T_cpu} ({T_cpu * (m + n)} column "
+                      f"NQP solves plus the Gram and CSR products, FP64) of the same workload from the same "
+                      f"start point, the first {args.warmup} untimed as the GPU's warm-up; {tcpu:.1f}s; "
+                      f"kbar {kbar_cpu:.3f} (the GPU's timed steps: iterations {args.warmup + 1}.."
+                      f"{args.warmup + args.steps})",
         }
         log(f"[bench] CPU oracle {tcpu:.1f}s")
     print(json.dumps(out), flush=True)

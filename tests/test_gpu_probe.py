@@ -22,3 +22,21 @@ def test_probe_reads_the_named_rows(rows, width, n):
     # each float32 running sum adds at most n*width/(4*lanes) terms of [0, 1)
     bound = 1e-6 * max(want, 1.0) * max(1.0, n * width / 4 / (2048 * 256)) + 1e-3
     assert abs(got - want) <= bound, (got, want)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("trans", [0, 1])
+def test_dense_product_time_runs_every_split(precision, trans):
+    """The autotuner's timing entry runs the product with any slice count
+    (0: the library's choice; counts above k/64 are clamped) and reports a
+    positive time per launch."""
+    import torch
+    from paper_1506_08938_amd import native as nat
+    g = torch.Generator(device="cuda")
+    g.manual_seed(3)
+    V = torch.rand((700, 300), device="cuda", generator=g)
+    K = 700 if trans == 0 else 300
+    A = torch.rand((K, 40), device="cuda", generator=g)
+    for ns in (0, 1, 3, 512):
+        ms = nat.dense_product_time(V, A, trans, precision, ns, reps=2)
+        assert 0.0 < ms < 1e3, (ns, ms)
