@@ -191,8 +191,8 @@ def serving_leg(native, synth, torch, n_req, loads=(0.5,), seed=5005, n_warm=Non
     # a pool of distinct requests, reused by the arrivals (each arrival has its own output)
     n_pool = 96
     sizes = synth.request_sizes(n_pool, seed, cmax=8192)
-    pool = [native.sparse_request(synth.foldin_columns_many(m, int(c), 500, seed + 1 + i), m)
-            for i, c in enumerate(sizes)]
+    pool_csr = [synth.foldin_columns_many(m, int(c), 500, seed + 1 + i) for i, c in enumerate(sizes)]
+    pool = [native.sparse_request(q, m) for q in pool_csr]
     fits = synth.workload5_fits(8)
     fit_V = [torch.from_numpy(f["V"]).cuda() for f in fits]
     total = n_warm + n_req
@@ -263,6 +263,28 @@ def serving_leg(native, synth, torch, n_req, loads=(0.5,), seed=5005, n_warm=Non
     el_sat, _, st_sat = run(None)
     rate_sat = n_req / el_sat
     log(f"[bench] serving saturated {el_sat * 1e3:.1f} ms ({rate_sat:.0f} req/s)")
+    # The fold-in products gather one basis row (r floats) per stored entry of
+    # a request; at saturation, against the gather probe's rate for as many
+    # uniformly random rows of the same basis (the fits share the window, so
+    # this is a lower bound of the fold-ins' own rate).
+    nnz_meas = int(sum(pool_csr[pick[i]].nnz for i in range(n_warm, total) if not is_fit[i]))
+    gathered = nnz_meas * r * 4
+    idx = torch.from_numpy(synth.rng(seed + 31).integers(0, m, min(nnz_meas, 1 << 25)).astype(np.int32)).cuda()
+    pout = torch.empty(native.PROBE_GATHER_OUT_FLOATS, device="cuda")
+    for _ in range(2):
+        native.probe_gather(W, idx, pout)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(5):
+        native.probe_gather(W, idx, pout)
+    ev[1].record()
+    torch.cuda.synchronize()
+    probe_rate = idx.numel() * r * 4 / (ev[0].elapsed_time(ev[1]) / 5 / 1e3)
+    gather_bound = {"gathered_bytes": gathered, "saturated_bytes_per_s": gathered / el_sat,
+                    "probe_bytes_per_s": probe_rate, "frac_of_probe": gathered / el_sat / probe_rate,
+                    "note": "fold-in products' basis-row gathers at saturation over the gather probe's rate for "
+                            "uniformly random rows of the same basis"}
+    del idx, pout
     per_load = []
     for k, ld in enumerate(loads):
         rate = ld * rate_sat
@@ -305,6 +327,7 @@ def serving_leg(native, synth, torch, n_req, loads=(0.5,), seed=5005, n_warm=Non
         "saturated_requests_per_s": rate_sat,
         "saturated_ms": el_sat * 1e3,
         "saturated_batches": st_sat["batches"],
+        "saturated_gathers": gather_bound,
         "loads": per_load,
     }
     if fsolve is not None:
