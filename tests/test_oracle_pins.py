@@ -477,3 +477,30 @@ def test_faststop_follows_the_rule_on_each_columns_own_trace(chunk):
             assert np.array_equal(x[j], xt)
     if chunk > 1:
         assert saw_break  # the instance does exercise the fast-break
+
+
+# ---------------------------------------------------------------------------
+# The stopping quantity of Algorithm 3 recorded per iteration: ||f~_k||^2, the
+# squared norm of the projected gradient in the rescaled variables y = x sqrt(d)
+# (Q = D^-1/2 H D^-1/2, q = h / sqrt(d): g = Q y + q, and g_i counts where
+# y_i > 0 or g_i < 0), checked against that definition at the iterate the
+# solver reaches after k iterations.
+
+@pytest.mark.parametrize("seed,r,l1", [(3, 6, 0.0), (8, 10, 0.05), (21, 16, 0.2)])
+def test_trace_is_the_projected_gradient_norm_of_each_iterate(seed, r, l1):
+    _, _, H, h = random_nqp(r, seed, l1=l1)
+    x0 = np.random.default_rng(seed + 100).random(r)
+    K = 12
+    _, kt, tr = oracle.nqp_trace(H, h, x0, max_inner=K, eps=0.0)
+    assert kt == K and len(tr) == K + 1
+    s = np.sqrt(np.diag(H))
+    Q = H / np.outer(s, s)
+    q = h / s
+    for k in range(K + 1):
+        xk = x0 if k == 0 else oracle.nqp(H, h, x0, max_inner=k, eps=0.0)[0]
+        y = xk * s
+        g = Q @ y + q
+        p = np.where((y > 0) | (g < 0), g, 0.0)
+        want = float(p @ p)
+        assert tr[k] == pytest.approx(want, rel=1e-9, abs=1e-300), (k, tr[k], want)
+    assert tr[K] < tr[0]  # the iterations make progress on these instances
