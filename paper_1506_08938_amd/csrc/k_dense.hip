@@ -293,28 +293,94 @@ __global__ __launch_bounds__(256) void k_dense(const void *__restrict__ V, int64
 }
 
 // A16[j][k] = bf16(A[k][j]) for j < r, 0 for r <= j < R32 (rows of lda16 >= K
-// entries; columns K..lda16 are left alone).  A block moves 64 rows of A
-// through LDS so that both sides are read and written contiguously.
-__device__ __forceinline__ void factor_t16_body(const float *__restrict__ A, int64_t K, int r,
-                                                int R32, __bf16 *__restrict__ A16, int64_t lda16,
-                                                int64_t k0, float *tile /* 64 x 129 */) {
-    for (int e = threadIdx.x; e < 64 * R32; e += blockDim.x) {
-        const int kk = e / R32, j = e % R32;
-        const int64_t gk = k0 + kk;
-        tile[kk * 129 + j] = (gk < K && j < r) ? A[gk * r + j] : 0.f;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < 64 * R32; e += blockDim.x) {
-        const int j = e / 64, kk = e % 64;
-        const int64_t gk = k0 + kk;
-        if (gk < K) A16[j * lda16 + gk] = (__bf16)tile[kk * 129 + j];
+// entries; columns K..lda16 are left alone).  A tile of 64 rows of A (64 r <=
+// 8192 contiguous floats) moves through LDS: every thread issues all of its
+// (coalesced) loads of the tile at once, and then packs eight consecutive k of
+// one row j into one 16-byte store.  LDS rows are S = r or r + 1 (the odd
+// one) floats apart, so the eight lanes of one j and the eight k that a lane
+// reads fall in 64 distinct banks.
+constexpr int FT16_U = 32;  // loads per thread: 256 * 32 = 64 rows of r <= 128
+
+__device__ __forceinline__ void ft16_load(const float *__restrict__ A, int64_t K, int r, int64_t k0,
+                                          float (&v)[FT16_U]) {
+    const int nflat = (int)min<int64_t>(64, K - k0) * r;
+    const float *src = A + k0 * r;
+#pragma unroll
+    for (int u = 0; u < FT16_U; ++u) {
+        const int f = u * 256 + (int)threadIdx.x;
+        if (f < nflat) v[u] = src[f];
     }
 }
 
+// element f = u * 256 + thread of the tile is A[k0 + f / r][f % r]; the row
+// and column advance by 256 / r and 256 % r from one u to the next
+__device__ __forceinline__ void ft16_to_lds(int64_t K, int r, int64_t k0, const float (&v)[FT16_U],
+                                            float *tile) {
+    const int S = r | 1;
+    const int nflat = (int)min<int64_t>(64, K - k0) * r;
+    const int dq = 256 / r, dr = 256 - dq * r;
+    int kk = (int)threadIdx.x / r, j = (int)threadIdx.x - kk * r;
+#pragma unroll
+    for (int u = 0; u < FT16_U; ++u) {
+        if (u * 256 + (int)threadIdx.x < nflat) tile[kk * S + j] = v[u];
+        kk += dq;
+        j += dr;
+        if (j >= r) { j -= r; ++kk; }
+    }
+}
+
+__device__ __forceinline__ void ft16_store(int64_t K, int r, int R32, __bf16 *__restrict__ A16,
+                                           int64_t lda16, int64_t k0, const float *tile) {
+    const int S = r | 1;
+    const int nk = (int)min<int64_t>(64, K - k0);
+    const bool vst = (((uintptr_t)A16 | (uintptr_t)(lda16 * 2)) & 15) == 0;
+    for (int e = threadIdx.x; e < R32 * 8; e += blockDim.x) {
+        const int j = e >> 3, kk0 = (e & 7) * 8;
+        if (kk0 >= nk) continue;
+        float x[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) x[t] = j < r && kk0 + t < nk ? tile[(kk0 + t) * S + j] : 0.f;
+        __bf16 *dst = A16 + j * lda16 + k0 + kk0;
+        if (vst && kk0 + 8 <= nk) {
+            uint32_t w[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                w[t] = (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)x[2 * t]) |
+                       (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)x[2 * t + 1]) << 16;
+            *reinterpret_cast<uint4 *>(dst) = make_uint4(w[0], w[1], w[2], w[3]);
+        } else {
+            for (int t = 0; t < 8 && kk0 + t < nk; ++t) dst[t] = (__bf16)x[t];
+        }
+    }
+}
+
+// one tile (k0 = first row of A)
+__device__ __forceinline__ void factor_t16_body(const float *__restrict__ A, int64_t K, int r,
+                                                int R32, __bf16 *__restrict__ A16, int64_t lda16,
+                                                int64_t k0, float *tile /* 64 x 129 */) {
+    float v[FT16_U];
+    ft16_load(A, K, r, k0, v);
+    ft16_to_lds(K, r, k0, v, tile);
+    __syncthreads();
+    ft16_store(K, r, R32, A16, lda16, k0, tile);
+}
+
+// every tile of one factor: a block takes tiles blockIdx.x, + gridDim.x, ...
+// and loads the next while it stores the current
 __global__ __launch_bounds__(256) void k_factor_t16(const float *__restrict__ A, int64_t K, int r,
                                                     int R32, __bf16 *__restrict__ A16, int64_t lda16) {
     __shared__ float tile[64 * 129];
-    factor_t16_body(A, K, r, R32, A16, lda16, (int64_t)blockIdx.x * 64, tile);
+    const int64_t ntiles = (K + 63) / 64;
+    float v[FT16_U];
+    int64_t t = blockIdx.x;
+    if (t < ntiles) ft16_load(A, K, r, t * 64, v);
+    for (; t < ntiles; t += gridDim.x) {
+        ft16_to_lds(K, r, t * 64, v, tile);
+        __syncthreads();
+        if (t + gridDim.x < ntiles) ft16_load(A, K, r, (t + gridDim.x) * 64, v);
+        ft16_store(K, r, R32, A16, lda16, t * 64, tile);
+        __syncthreads();
+    }
 }
 
 // y (cols x rows) = x' in BF16: 64 x 64 tiles through LDS
@@ -584,8 +650,11 @@ hipError_t launch_dense_product(const void *V, int bf16, int64_t m, int64_t n, i
         xt = false;
         lda16 = dense_lda16(m, n);
         A16 = (__bf16 *)((char *)scratch + dense_forced_partial_bytes(m, n, r, force_nsplit));
-        hipLaunchKernelGGL(k_factor_t16, dim3((unsigned)((K + 63) / 64)), dim3(256), 0, s, A, K, r,
-                           32 * NT, A16, lda16);
+        // four blocks fit a CU (33 KB of LDS each); tiles are shared out evenly
+        const int64_t ntiles = (K + 63) / 64;
+        const int64_t per = (ntiles + 4 * device_cu_count() - 1) / (4 * device_cu_count());
+        hipLaunchKernelGGL(k_factor_t16, dim3((unsigned)((ntiles + per - 1) / per)), dim3(256), 0, s, A,
+                           K, r, 32 * NT, A16, lda16);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

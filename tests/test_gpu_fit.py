@@ -85,6 +85,25 @@ def test_dense_product_matches_oracle(m, n, r):
         assert errb < 1e-2
 
 
+# BF16 dense products are exactly the product of the BF16-rounded V and factor
+# (accumulated in float32): ragged k (the factor's transposed BF16 copy is
+# built 64 rows at a time), odd ranks, and ranks that fill every MFMA column
+@pytest.mark.parametrize("m,n,r", [(70, 131, 1), (300, 257, 33), (129, 1000, 100), (64, 64, 128),
+                                   (1000, 77, 7)])
+def test_dense_bf16_product_is_the_rounded_inputs_product(m, n, r):
+    nat = native()
+    g = np.random.default_rng(7 * m + n + r)
+    V = g.random((m, n), dtype=np.float32)
+    W = g.random((m, r), dtype=np.float32); Ht = g.random((n, r), dtype=np.float32)
+    Vd = nat.DeviceMatrix(T(V))
+    for trans, A in ((0, W), (1, Ht)):
+        Q = oracle.product_dense(bf16_round(V), bf16_round(A), trans)
+        B = H(nat.product(Vd, T(A), trans, precision=nat.NMF_BF16))
+        e = np.abs(B - Q).max() / np.abs(Q).max()
+        print(f"dense bf16 {m}x{n} r={r} trans={trans}: vs rounded inputs {e:.2e}")
+        assert e < 1e-5
+
+
 # dense V as a column slice of a wider matrix (leading dimension > n, not a
 # multiple of 4): products, objective and a fit equal those of the compact copy
 @pytest.mark.parametrize("prec", [0, 1])
