@@ -93,8 +93,14 @@ __device__ __forceinline__ void dense_body(const void *__restrict__ Vv, int64_t 
     // X tile: 1024 16-byte chunks, four per thread
     constexpr int XCH = BM * BK * (int)sizeof(T) / 16 / 256;
     static_assert(XCH == 4, "a 16 KB X tile per stage");
-    // A tile in 16-byte chunks: FP32 float4 along r (BK * R32 / 4 of them);
-    // BF16 eight k of one row j (R32 * BK / 8)
+    // A tile in chunks (BK * R32 / 4 of four floats, or R32 * BK / 8 of eight
+    // BF16 values of one row j of A16).  FP32 with r > 64 takes four
+    // consecutive k of one column j, stored as two 8-byte pairs: the float4
+    // of four j of one k is stored as four 4-byte writes at a stride that puts
+    // the lanes of one k in four banks (8-way conflicts), which costs the
+    // wider tiles 5-18% and the r <= 64 tiles nothing (their A tile is half
+    // the LDS traffic and the extra loads cost more there).
+    constexpr bool A_KPAIRS = !BF16 && NT >= 3;
     constexpr int ACH = BK * R32 / 4 / 256 / (BF16 ? 2 : 1);
     static_assert(ACH >= 1, "A tile smaller than one chunk per thread");
     const T *__restrict__ V = (const T *)Vv;
@@ -145,7 +151,13 @@ __device__ __forceinline__ void dense_body(const void *__restrict__ Vv, int64_t 
 #pragma unroll
                     for (int e = 0; e < 8; e++) ar16[u][e] = gk + e < ke ? A16[j * lda16 + gk + e] : (__bf16)0.f;
                 }
-            } else {
+            } else if constexpr (A_KPAIRS) {  // four consecutive k of one column j
+                const int j = q % R32, kq = (q / R32) * 4;
+                const float *Ab = A + k0 * r;  // the stage's first row (uniform)
+                const int kn = (int)min<int64_t>(ke - k0, BK);
+#pragma unroll
+                for (int e = 0; e < 4; e++) ar[u][e] = (kq + e < kn && j < r) ? Ab[(kq + e) * r + j] : 0.f;
+            } else {  // four consecutive j of one row k of A (a float4)
                 constexpr int CPR = R32 / 4;
                 const int kk = q / CPR, j = (q % CPR) * 4;
                 const int64_t gk = k0 + kk;
@@ -162,8 +174,6 @@ __device__ __forceinline__ void dense_body(const void *__restrict__ Vv, int64_t 
     auto store_stage = [&](char *buf) {
         T *Xs = (T *)buf;
         T *As = (T *)(buf + L::X_ELEMS * L::ESZ);
-        // FP32 position of stage-local k within a row
-        auto perm = [](int k) { return (k & 1) * 16 + (k >> 1); };
 #pragma unroll
         for (int u = 0; u < XCH; u++) {
             const int q = tid + 256 * u;
@@ -192,11 +202,19 @@ __device__ __forceinline__ void dense_body(const void *__restrict__ Vv, int64_t 
                 constexpr int CPR = BK / 8;
                 const int j = q / CPR, kk = (q % CPR) * 8;
                 *(bf16x8 *)(As + j * L::AP + kk) = ar16[u];
+            } else if constexpr (A_KPAIRS) {  // k .. k+3 of one j (k % 4 == 0): pairs, as for X
+                const int j = q % R32, kq = (q / R32) * 4;
+                f32x2 ev, od;
+                ev[0] = ar[u][0]; ev[1] = ar[u][2];
+                od[0] = ar[u][1]; od[1] = ar[u][3];
+                *(f32x2 *)(As + j * L::AP + (kq >> 1)) = ev;
+                *(f32x2 *)(As + j * L::AP + 16 + (kq >> 1)) = od;
             } else {  // the four j of one k, into four rows
                 constexpr int CPR = R32 / 4;
                 const int kk = q / CPR, j = (q % CPR) * 4;
+                const int pk = (kk & 1) * 16 + (kk >> 1);
 #pragma unroll
-                for (int e = 0; e < 4; e++) As[(j + e) * L::AP + perm(kk)] = ar[u][e];
+                for (int e = 0; e < 4; e++) As[(j + e) * L::AP + pk] = ar[u][e];
             }
         }
     };
