@@ -51,60 +51,79 @@ __device__ __forceinline__ void gram_partial_rows(const float *__restrict__ A, i
 #pragma unroll
     for (int i = 0; i < NTILE; i++) acc[i] = f32x16{};
 
+    // Every load is from a valid (clamped) address and is zeroed only when
+    // its trip runs, so the next trip's loads are issued before this trip's
+    // MFMAs and arrive while they run.
     if constexpr (PREC == NMF_BF16) {
-        for (int64_t t = s0; t < s1; t += 16) {
-            bf16x8 v[NT];
-            // loads from clamped (valid) addresses, zeroed after: all of the
-            // step's loads are in flight together
+        if (s0 < s1) {
             float f[NT][8];
-#pragma unroll
-            for (int c = 0; c < NT; c++) {
-                const int a = c * 32 + col;
-#pragma unroll
-                for (int q = 0; q < 8; q++) {
-                    const int64_t row = t + half * 8 + q;
-                    f[c][q] = A[(row < s1 ? row : s0) * r + (a < r ? a : 0)];
-                }
-            }
-#pragma unroll
-            for (int c = 0; c < NT; c++) {
-                const int a = c * 32 + col;
-#pragma unroll
-                for (int q = 0; q < 8; q++) {
-                    const int64_t row = t + half * 8 + q;
-                    if (!(row < s1 && a < r)) f[c][q] = 0.f;
-                }
-                v[c] = pack_bf16x8(f[c]);
-            }
-            int ti = 0;
-#pragma unroll
-            for (int ta = 0; ta < NT; ta++)
-#pragma unroll
-                for (int tb = ta; tb < NT; tb++, ti++)
-                    acc[ti] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(v[ta], v[tb], acc[ti], 0, 0, 0);
-        }
-    } else {
-        constexpr int U = 4;  // row pairs per trip: loads in flight
-        for (int64_t t = s0; t < s1; t += 2 * U) {
-            float v[U][NT];
-#pragma unroll
-            for (int u = 0; u < U; u++) {
-                const int64_t row = t + 2 * u + half;
+            auto load = [&](int64_t t, float (&w)[NT][8]) {
 #pragma unroll
                 for (int c = 0; c < NT; c++) {
                     const int a = c * 32 + col;
-                    v[u][c] = (row < s1 && a < r) ? A[row * r + a] : 0.f;
-                }
-            }
 #pragma unroll
-            for (int u = 0; u < U; u++) {
+                    for (int q = 0; q < 8; q++) {
+                        const int64_t row = t + half * 8 + q;
+                        w[c][q] = A[(row < s1 ? row : s0) * r + (a < r ? a : 0)];
+                    }
+                }
+            };
+            load(s0, f);
+            for (int64_t t = s0; t < s1; t += 16) {
+                bf16x8 v[NT];
+#pragma unroll
+                for (int c = 0; c < NT; c++) {
+                    const int a = c * 32 + col;
+#pragma unroll
+                    for (int q = 0; q < 8; q++) {
+                        const int64_t row = t + half * 8 + q;
+                        if (!(row < s1 && a < r)) f[c][q] = 0.f;
+                    }
+                    v[c] = pack_bf16x8(f[c]);
+                }
+                load(t + 16, f);
                 int ti = 0;
 #pragma unroll
                 for (int ta = 0; ta < NT; ta++)
 #pragma unroll
                     for (int tb = ta; tb < NT; tb++, ti++)
-                        acc[ti] = __builtin_amdgcn_mfma_f32_32x32x2f32(v[u][ta], v[u][tb], acc[ti],
-                                                                       0, 0, 0);
+                        acc[ti] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(v[ta], v[tb], acc[ti], 0, 0, 0);
+            }
+        }
+    } else {
+        constexpr int U = 4;  // row pairs per trip
+        if (s0 < s1) {
+            float v[U][NT], w[U][NT];
+            auto load = [&](int64_t t, float (&x)[U][NT]) {
+#pragma unroll
+                for (int u = 0; u < U; u++) {
+                    const int64_t row = t + 2 * u + half;
+#pragma unroll
+                    for (int c = 0; c < NT; c++) {
+                        const int a = c * 32 + col;
+                        x[u][c] = A[(row < s1 ? row : s0) * r + (a < r ? a : 0)];
+                    }
+                }
+            };
+            load(s0, w);
+            for (int64_t t = s0; t < s1; t += 2 * U) {
+#pragma unroll
+                for (int u = 0; u < U; u++) {
+                    const int64_t row = t + 2 * u + half;
+#pragma unroll
+                    for (int c = 0; c < NT; c++) v[u][c] = (row < s1 && c * 32 + col < r) ? w[u][c] : 0.f;
+                }
+                load(t + 2 * U, w);
+#pragma unroll
+                for (int u = 0; u < U; u++) {
+                    int ti = 0;
+#pragma unroll
+                    for (int ta = 0; ta < NT; ta++)
+#pragma unroll
+                        for (int tb = ta; tb < NT; tb++, ti++)
+                            acc[ti] = __builtin_amdgcn_mfma_f32_32x32x2f32(v[u][ta], v[u][tb], acc[ti],
+                                                                           0, 0, 0);
+                }
             }
         }
     }
