@@ -104,6 +104,29 @@ def test_dense_bf16_product_is_the_rounded_inputs_product(m, n, r):
         assert e < 1e-5
 
 
+# the factor at an address that is only 4-byte aligned (a contiguous view one
+# float into a buffer): the FP32 tiles fall back from 16-byte loads and the
+# BF16 factor copy reads it as dwords; every product equals the aligned one
+@pytest.mark.parametrize("r", [7, 64, 100])
+def test_dense_product_with_unaligned_factor(r):
+    nat = native()
+    import torch
+    g = np.random.default_rng(400 + r)
+    m, n = 700, 333
+    V = g.random((m, n), dtype=np.float32)
+    Vd = nat.DeviceMatrix(T(V))
+    for trans, k in ((0, m), (1, n)):
+        A = g.random((k, r), dtype=np.float32)
+        buf = torch.zeros(k * r + 1, device="cuda")
+        Au = buf[1:].view(k, r)
+        Au.copy_(T(A))
+        assert Au.is_contiguous() and Au.data_ptr() % 16 == 4
+        for prec in (0, 1):
+            Pa = H(nat.product(Vd, T(A), trans, precision=prec))
+            Pu = H(nat.product(Vd, Au, trans, precision=prec))
+            assert np.array_equal(Pa, Pu), (trans, prec)
+
+
 # dense V as a column slice of a wider matrix (leading dimension > n, not a
 # multiple of 4): products, objective and a fit equal those of the compact copy
 @pytest.mark.parametrize("prec", [0, 1])
