@@ -94,13 +94,23 @@ __device__ __forceinline__ void dense_body(const void *__restrict__ Vv, int64_t 
     constexpr int XCH = BM * BK * (int)sizeof(T) / 16 / 256;
     static_assert(XCH == 4, "a 16 KB X tile per stage");
     // A tile in chunks (BK * R32 / 4 of four floats, or R32 * BK / 8 of eight
-    // BF16 values of one row j of A16).  FP32 with r > 64 takes four
-    // consecutive k of one column j, stored as two 8-byte pairs: the float4
-    // of four j of one k is stored as four 4-byte writes at a stride that puts
-    // the lanes of one k in four banks (8-way conflicts), which costs the
-    // wider tiles 5-18% and the r <= 64 tiles nothing (their A tile is half
-    // the LDS traffic and the extra loads cost more there).
-    constexpr bool A_KPAIRS = !BF16 && NT >= 3;
+    // BF16 values of one row j of A16).  FP32 takes a float4 of four j of one
+    // k, stored as four 4-byte writes into four rows; or, for the widest tile
+    // with X = V' (the hot columns' product), four consecutive k of one
+    // column j, stored as two 8-byte pairs -- the faster of the two there,
+    // the slower everywhere else (measured).
+    constexpr bool A_KPAIRS = !BF16 && XT && NT == 4;
+    // FP32 float4 chunk q of the A tile: row kk of the stage, columns j..j+3.
+    // A wave's 64 chunks are eight rows (every other k of one half of the
+    // stage, so their even/odd positions are eight consecutive floats) by
+    // eight column groups: each row is one 128-byte read, and the four
+    // 4-byte stores of a chunk meet at most two lanes per bank.
+    auto a_chunk = [](int q, int &kk, int &j) {
+        constexpr int CPR = R32 / 4;  // column groups (a multiple of 8)
+        const int kl = q & 7, j4 = (q >> 3) % CPR, g = (q >> 3) / CPR;  // g < BK / 8
+        kk = 16 * (g >> 1) + 2 * kl + (g & 1);
+        j = 4 * j4;
+    };
     constexpr int ACH = BK * R32 / 4 / 256 / (BF16 ? 2 : 1);
     static_assert(ACH >= 1, "A tile smaller than one chunk per thread");
     const T *__restrict__ V = (const T *)Vv;
@@ -158,8 +168,8 @@ __device__ __forceinline__ void dense_body(const void *__restrict__ Vv, int64_t 
 #pragma unroll
                 for (int e = 0; e < 4; e++) ar[u][e] = (kq + e < kn && j < r) ? Ab[(kq + e) * r + j] : 0.f;
             } else {  // four consecutive j of one row k of A (a float4)
-                constexpr int CPR = R32 / 4;
-                const int kk = q / CPR, j = (q % CPR) * 4;
+                int kk, j;
+                a_chunk(q, kk, j);
                 const int64_t gk = k0 + kk;
                 if (gk < ke && a_vec && j + 4 <= r) {
                     ar[u] = *(const f32x4a *)(A + gk * r + j);
@@ -210,8 +220,8 @@ __device__ __forceinline__ void dense_body(const void *__restrict__ Vv, int64_t 
                 *(f32x2 *)(As + j * L::AP + (kq >> 1)) = ev;
                 *(f32x2 *)(As + j * L::AP + 16 + (kq >> 1)) = od;
             } else {  // the four j of one k, into four rows
-                constexpr int CPR = R32 / 4;
-                const int kk = q / CPR, j = (q % CPR) * 4;
+                int kk, j;
+                a_chunk(q, kk, j);
                 const int pk = (kk & 1) * 16 + (kk >> 1);
 #pragma unroll
                 for (int e = 0; e < 4; e++) As[(j + e) * L::AP + pk] = ar[u][e];
