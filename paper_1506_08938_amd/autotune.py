@@ -161,7 +161,7 @@ def from_json(path):
 # slower there), so only clear wins replace the rule.  Shapes beyond
 # DENSE_MAX_ELEMS entries of V keep the rule.
 DENSE_C = [128, 512, 2048, 8192, 32768]
-DENSE_K = [256, 1024, 4096, 16384, 65536]
+DENSE_K = [256, 1024, 4096, 16384, 65536, 262144]
 DENSE_NT = [1, 2, 3, 4]
 DENSE_KERNELS = [("fp32", 0, 1), ("fp32_vt", 0, 0), ("bf16", 1, 1)]  # (name, precision, trans)
 DENSE_MAX_ELEMS = 1 << 30
