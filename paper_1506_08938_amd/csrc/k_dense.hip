@@ -443,15 +443,25 @@ hipError_t launch_to_bf16_t(const float *x, int64_t rows, int64_t cols, int64_t 
 // group order.  (Up to SPLIT_GROUP slices this is the plain slice-order sum.)
 constexpr int SPLIT_GROUP = 8;
 
+// Sum of slices g0 .. g1 - 1 (at most SPLIT_GROUP of them) of entry i, in
+// slice order; all loads are issued before the adds.
+__device__ __forceinline__ float group_sum(const float *__restrict__ part, int g0, int g1, int64_t n,
+                                           int64_t i) {
+    float v[SPLIT_GROUP];
+#pragma unroll
+    for (int k = 0; k < SPLIT_GROUP; k++) v[k] = g0 + k < g1 ? part[(int64_t)(g0 + k) * n + i] : 0.f;
+    float gs = 0.f;
+#pragma unroll
+    for (int k = 0; k < SPLIT_GROUP; k++)
+        if (g0 + k < g1) gs += v[k];
+    return gs;
+}
+
 __device__ __forceinline__ float split_sum(const float *__restrict__ part, int nsplit, int64_t n,
                                            int64_t i) {
     float s = 0.f;
-    for (int g0 = 0; g0 < nsplit; g0 += SPLIT_GROUP) {
-        float gs = 0.f;
-        const int g1 = min(nsplit, g0 + SPLIT_GROUP);
-        for (int k = g0; k < g1; k++) gs += part[(int64_t)k * n + i];
-        s += gs;
-    }
+    for (int g0 = 0; g0 < nsplit; g0 += SPLIT_GROUP)
+        s += group_sum(part, g0, min(nsplit, g0 + SPLIT_GROUP), n, i);
     return s;
 }
 
@@ -471,10 +481,8 @@ __global__ void k_split_groups(float *__restrict__ part, int nsplit, int64_t n) 
          e += (int64_t)gridDim.x * blockDim.x) {
         const int g = (int)(e / n);
         const int64_t i = e - (int64_t)g * n;
-        const int g0 = g * SPLIT_GROUP, g1 = min(nsplit, g0 + SPLIT_GROUP);
-        float gs = 0.f;
-        for (int k = g0; k < g1; k++) gs += part[(int64_t)k * n + i];
-        part[(int64_t)g0 * n + i] = gs;
+        const int g0 = g * SPLIT_GROUP;
+        part[(int64_t)g0 * n + i] = group_sum(part, g0, min(nsplit, g0 + SPLIT_GROUP), n, i);
     }
 }
 
@@ -482,8 +490,20 @@ __global__ void k_split_final(const float *__restrict__ part, int nsplit, int64_
                               float *__restrict__ P) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
+        // the group sums (at slices 0, SPLIT_GROUP, ...) added in order, eight
+        // loads at a time
         float s = 0.f;
-        for (int g0 = 0; g0 < nsplit; g0 += SPLIT_GROUP) s += part[(int64_t)g0 * n + i];
+        for (int g0 = 0; g0 < nsplit; g0 += SPLIT_GROUP * SPLIT_GROUP) {
+            float v[SPLIT_GROUP];
+#pragma unroll
+            for (int k = 0; k < SPLIT_GROUP; k++) {
+                const int sl = g0 + k * SPLIT_GROUP;
+                v[k] = sl < nsplit ? part[(int64_t)sl * n + i] : 0.f;
+            }
+#pragma unroll
+            for (int k = 0; k < SPLIT_GROUP; k++)
+                if (g0 + k * SPLIT_GROUP < nsplit) s += v[k];
+        }
         P[i] = s;
     }
 }
