@@ -198,7 +198,15 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const float *__restrict__ p
     float a = 0.f;
     if (e < N) {
         const int full = nblocks / 8 * 8;
-        for (int pb = q; pb < full; pb += 8) a += partial[(size_t)pb * N + e];
+        // partials q, q + 8, ... added in order, their loads issued eight at a time
+        for (int pb0 = q; pb0 < full; pb0 += 64) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) v[u] = pb0 + 8 * u < full ? partial[(size_t)(pb0 + 8 * u) * N + e] : 0.f;
+#pragma unroll
+            for (int u = 0; u < 8; u++)
+                if (pb0 + 8 * u < full) a += v[u];
+        }
         if (full + q < nblocks) a += partial[(size_t)(full + q) * N + e];
     }
     sm[q][el] = a;
