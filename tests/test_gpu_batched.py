@@ -72,6 +72,31 @@ def test_batched_many_chunks_per_block_equals_solo():
         assert stats[i]["inner_total"] == st["inner_total"], i
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batched_tall_problems_with_many_slices_equal_solo(precision):
+    """Problems with one row block of P and a long k (96 x 40000 either way)
+    take hundreds of split-K slices: a solo fit sums them in two passes (group
+    sums, then the groups in order), the batched fit in one; both orders are
+    the same, so every result still equals its solo nmf_fit bitwise."""
+    from paper_1506_08938_amd import native as nat
+    shapes = [(40000, 96, 16), (96, 40000, 48), (300, 200, 8), (40000, 96, 100)]
+    probs = []
+    for i, (m, n, r) in enumerate(shapes):
+        V = synth.dense_lowrank(m, n, min(r, 12), 900 + i, "gamma", 0.05)
+        W0, Ht0 = synth.start_point(m, n, r, 950 + i)
+        probs.append(dict(V=V, r=r, W0=W0, Ht0=Ht0))
+    opt = nat.opts(max_outer=2, lanes=4, precision=precision)
+    batch = [dict(V=T(p["V"]), r=p["r"], reg=nat.reg(0.0, 0.01, 0.01, 0.0), W=T(p["W0"]), Ht=T(p["Ht0"]))
+             for p in probs]
+    nat.fit_batched(batch, opt, want_stats=False)
+    for i, p in enumerate(probs):
+        W = T(p["W0"]); Ht = T(p["Ht0"])
+        nat.fit(nat.DeviceMatrix(T(p["V"])), p["r"], nat.reg(0.0, 0.01, 0.01, 0.0), opt, W, Ht,
+                want_trace=False)
+        assert np.array_equal(H(batch[i]["W"]), H(W)), i
+        assert np.array_equal(H(batch[i]["Ht"]), H(Ht)), i
+
+
 def test_batched_one_step_matches_oracle():
     from paper_1506_08938_amd import native as nat
     probs = problems(12)
