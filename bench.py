@@ -130,10 +130,11 @@ def measured_traffic(kernel, L):
 def measured_product_traffic():
     """HBM bytes per step of the sparse product phase (k_spmm both halves and
     the hot columns' k_dense) from the committed counter summary, or None when
-    there is none or their sources changed since."""
+    there is none or their sources (or the plan's column split) changed since."""
     fields = summary_fields("product_phase_sparse_r100_hbm_traffic.md")
+    # the kernels, and the plan that splits the columns between them
     src = ["paper_1506_08938_amd/csrc/k_spmm.hip", "paper_1506_08938_amd/csrc/k_dense.hip",
-           "paper_1506_08938_amd/build.py"]
+           "paper_1506_08938_amd/csrc/fit.hip", "paper_1506_08938_amd/build.py"]
     if fields.get("kernel") != "product phase" or fields.get("source_sha256") != sources_hash(src):
         return None
     return float(fields["traffic_bytes_per_step"])
@@ -539,10 +540,10 @@ def gather_probe(native, synth, torch, np, V, r, bf16_case=True, uniform_case=Tr
     Ht rows in the W-update's order (CSR(V)), FP32 rows of r floats; optionally
     W rows as BF16 (rows padded to 8 values) and uniformly random W rows."""
     m, n = V.shape
-    # the plan's hot columns: c_j >= max(m/16, 256) entries, the longest first,
+    # the plan's hot columns: c_j >= max(m/24, 256) entries, the longest first,
     # all up to 127, else 128 or 256 of them
     cnt = np.bincount(V.indices, minlength=n)
-    thr = max((m + 15) // 16, 256)
+    thr = max((m + 23) // 24, 256)
     cand = np.nonzero(cnt >= thr)[0]
     cand = cand[np.argsort(-cnt[cand], kind="stable")]
     if cand.size >= 128:

@@ -377,14 +377,16 @@ static hipError_t plan_malloc(const nmf_plan *p, void **ptr, size_t bytes) {
 // Hot columns of a CSR V: a column j with c_j stored entries costs the
 // H-update c_j gathered rows of W (4r bytes each, from cache), and costs the
 // dense product about m (4 bytes + 2r flop).  At the gather and MFMA rates
-// measured on MI355X the dense side wins from c_j ~ m/17 on; columns with
-// c_j >= max(m/16, 256) are taken, the longest first (ties: lower index):
+// measured on MI355X the dense side wins from about c_j ~ m/32 on (a second
+// slab of 128 columns adds about 0.4 us per column to the dense product, a
+// column's gathers cost c_j x 400 bytes at 5.8 TB/s); columns with
+// c_j >= max(m/24, 256) are taken, the longest first (ties: lower index):
 // all of them up to 127, else 128 or 256 (whole 128-row slabs of the dense
 // product), and only when there are at least 4.
 static int choose_hot_columns(nmf_plan *p, const std::vector<int32_t> &t_rowptr,
                               std::vector<char> &hot, hipStream_t s) {
     const int64_t n = p->n, m = p->m;
-    const int64_t thr = std::max<int64_t>((m + 15) / 16, 256);
+    const int64_t thr = std::max<int64_t>((m + 23) / 24, 256);
     std::vector<int32_t> cand;
     for (int64_t j = 0; j < n; j++)
         if (t_rowptr[j + 1] - t_rowptr[j] >= thr) cand.push_back((int32_t)j);

@@ -61,10 +61,10 @@ def bf16_round(a):
 
 def hot_columns(Vt, m):
     """The columns the plan's H-update takes through the dense product: at
-    least max(m/16, 256) stored entries, the longest first (ties: lower index),
+    least max(m/24, 256) stored entries, the longest first (ties: lower index),
     all of them up to 127, else whole slabs of 128 (at most 256)."""
     cnt = np.diff(Vt.indptr)
-    thr = max((m + 15) // 16, 256)
+    thr = max((m + 23) // 24, 256)
     cand = np.flatnonzero(cnt >= thr)
     cand = cand[np.argsort(-cnt[cand], kind="stable")]
     if len(cand) >= 128:
